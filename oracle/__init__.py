@@ -1,0 +1,179 @@
+"""CPU oracle of the time-averaged flux reconstruction step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library in ``paper_2512_08611_amd``; the two meet only through the
+seeded input generators of ``paper_2512_08611_amd.workloads``, which hold none
+of the method's arithmetic.
+
+The numerics live in plain C++ (``oracle/*.hpp``, compiled into
+``oracle/liboracle.so`` by ``__graft_entry__.build()``); this module is the
+ctypes marshalling plus the Fourier (von Neumann) analysis in ``cfl.py``.
+
+Parity status of each part (what pins it) is listed in the design notes.  The
+smoothness indicator constants come from the cited work of Hennemann et al.,
+not from the paper: "parity unpinned" for the indicator beyond its special
+cases (constant state -> 0, pure highest mode -> alpha_max).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .cfl import cfl_number  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+EQ_SW1D, EQ_SW2D, EQ_MHD2D, EQ_LINADV1D, EQ_VARADV1D = 1, 2, 3, 4, 5
+NVARS = {EQ_SW1D: 3, EQ_SW2D: 4, EQ_MHD2D: 9, EQ_LINADV1D: 1, EQ_VARADV1D: 2}
+DIMS = {EQ_SW1D: 1, EQ_SW2D: 2, EQ_MHD2D: 2, EQ_LINADV1D: 1, EQ_VARADV1D: 1}
+NCONSTR = {EQ_SW1D: 1, EQ_SW2D: 1, EQ_MHD2D: 2, EQ_LINADV1D: 0, EQ_VARADV1D: 0}
+
+FLAG_ALG2, FLAG_LOW_INADM, FLAG_ALG1, FLAG_NONFINITE, FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
+
+
+class OraCfg(ctypes.Structure):
+    _fields_ = [
+        ("eq", ctypes.c_int32), ("N", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("lo", ctypes.c_double * 2), ("hi", ctypes.c_double * 2),
+        ("gamma", ctypes.c_double), ("gravity", ctypes.c_double),
+        ("cs", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("blending", ctypes.c_int32),
+        ("alpha_max", ctypes.c_double), ("alpha_min", ctypes.c_double), ("alpha_force", ctypes.c_double),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            raise RuntimeError("oracle/liboracle.so is not built; run __graft_entry__.build()")
+        _lib = ctypes.CDLL(_LIBPATH)
+    return _lib
+
+
+def _p(a, ctype=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81, cs=0.9,
+             cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0):
+    c = OraCfg()
+    c.eq, c.N, c.nx, c.ny = eq, N, nx, (ny if DIMS[eq] == 2 else 1)
+    c.lo[0], c.lo[1] = lo
+    c.hi[0], c.hi[1] = hi
+    c.gamma, c.gravity, c.cs = gamma, gravity, cs
+    c.cfl = cfl_number(N) if cfl is None else cfl
+    c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
+    return c
+
+
+def shape(c):
+    n1 = c.N + 1
+    P = n1 if DIMS[c.eq] == 1 else n1 * n1
+    return (NVARS[c.eq], c.nx * c.ny, P)
+
+
+def nfp(c):
+    return 1 if DIMS[c.eq] == 1 else c.N + 1
+
+
+def refel(N):
+    n1 = N + 1
+    out = {k: np.zeros(n1) for k in ("xi", "w", "VL", "VR", "gLp", "gRp")}
+    D = np.zeros((n1, n1))
+    Leg = np.zeros((n1, n1))
+    rc = lib().ora_refel(N, _p(out["xi"]), _p(out["w"]), _p(D), _p(out["VL"]), _p(out["VR"]),
+                         _p(out["gLp"]), _p(out["gRp"]), _p(Leg))
+    assert rc == 0
+    out["D"], out["Leg"] = D, Leg
+    return out
+
+
+def tableau(N):
+    s = ctypes.c_int(0)
+    A = np.zeros(36)
+    b = np.zeros(6)
+    assert lib().ora_tableau(N, ctypes.byref(s), _p(A), _p(b)) == 0
+    n = s.value
+    return A[: n * n].reshape(n, n).copy(), b[:n].copy()
+
+
+def physics(eq, what, d, u, w=None, gamma=5.0 / 3.0, gravity=9.81, ch=0.0):
+    """Pointwise physics of one state: what in {'flux','nc','sigma','constraints','indicator','speeds'}."""
+    code = {"flux": 0, "nc": 1, "sigma": 2, "constraints": 3, "indicator": 4, "speeds": 5}[what]
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros(max(NVARS[eq], 2))
+    rc = lib().ora_physics(eq, ctypes.c_double(gamma), ctypes.c_double(gravity), ctypes.c_double(ch), code, d,
+                           _p(u), _p(w), _p(out))
+    assert rc == 0
+    n = {0: NVARS[eq], 1: NVARS[eq], 2: 1, 3: NCONSTR[eq], 4: 1, 5: 2}[code]
+    return out[:n]
+
+
+def dt_ch(c, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(2)
+    assert lib().ora_dt_ch(ctypes.byref(c), _p(u), _p(out)) == 0
+    return float(out[0]), float(out[1])
+
+
+def alpha(c, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    E = c.nx * c.ny
+    araw, al, tie = np.zeros(E), np.zeros(E), np.zeros(E, dtype=np.uint8)
+    assert lib().ora_alpha(ctypes.byref(c), _p(u), _p(araw), _p(al), _p(tie, ctypes.c_uint8)) == 0
+    return araw, al, tie
+
+
+def step(c, u, dt=0.0, ch=-1.0, alpha_in=None):
+    """One step.  dt > 0 is used as given, otherwise eq. time.step.2d; ch >= 0 overrides c_h;
+    alpha_in replaces the indicator's blending coefficients."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    E = c.nx * c.ny
+    d = DIMS[c.eq]
+    out = {
+        "u": np.zeros_like(u),
+        "dt_ch": np.zeros(2),
+        "alpha": np.zeros(E),
+        "flags": np.zeros(E, dtype=np.uint32),
+        "tie": np.zeros(E, dtype=np.uint8),
+        "theta_face": np.ones((d, E, nfp(c))),
+        "theta_elem": np.ones(E),
+    }
+    ain = None if alpha_in is None else np.ascontiguousarray(alpha_in, dtype=np.float64)
+    rc = lib().ora_step(ctypes.byref(c), _p(u), _p(out["u"]), ctypes.c_double(dt), ctypes.c_double(ch), _p(ain),
+                        _p(out["dt_ch"]), _p(out["alpha"]), _p(out["flags"], ctypes.c_uint32),
+                        _p(out["tie"], ctypes.c_uint8), _p(out["theta_face"]), _p(out["theta_elem"]))
+    assert rc == 0
+    out["dt"], out["ch"] = float(out["dt_ch"][0]), float(out["dt_ch"][1])
+    return out
+
+
+def residual(c, u, dt, mode, ch=-1.0):
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    R = np.zeros_like(u)
+    assert lib().ora_residual(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch), mode, _p(R)) == 0
+    return R
+
+
+def jvp(c, u, v, dt, ch):
+    """J v of the step with dt, c_h, alpha and every theta frozen at their values at u."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(shape(c))
+    un, Jv = np.zeros_like(u), np.zeros_like(u)
+    assert lib().ora_jvp(ctypes.byref(c), _p(u), _p(v), ctypes.c_double(dt), ctypes.c_double(ch), _p(un),
+                         _p(Jv)) == 0
+    return un, Jv
+
+
+def count_ops(c, u, dt, ch):
+    """Operation counts [phase][add, mul, div, sqrt, exp] for phases (stages, faces, update)."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    counts = np.zeros(15, dtype=np.uint64)
+    assert lib().ora_count_ops(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch),
+                               _p(counts, ctypes.c_uint64)) == 0
+    return counts.reshape(3, 5)

@@ -1,0 +1,200 @@
+// C entry points of the CPU oracle for the Python test harness (ctypes).
+// TEST INFRASTRUCTURE ONLY: only tests/, the smoke check and the CPU baseline
+// leg of the benchmark may load this library.
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "scheme.hpp"
+
+using namespace ora;
+
+struct ora_cfg {
+  int32_t eq, N, nx, ny;
+  double lo[2], hi[2];
+  double gamma, gravity;
+  double cs, cfl;
+  int32_t blending;
+  double alpha_max, alpha_min, alpha_force;
+};
+
+static Config to_cfg(const ora_cfg* c) {
+  Config k;
+  k.eq = c->eq; k.N = c->N; k.nx = c->nx; k.ny = c->ny;
+  for (int i = 0; i < 2; ++i) { k.lo[i] = c->lo[i]; k.hi[i] = c->hi[i]; }
+  k.gamma = c->gamma; k.gravity = c->gravity; k.cs = c->cs; k.cfl = c->cfl;
+  k.blending = c->blending; k.alpha_max = c->alpha_max; k.alpha_min = c->alpha_min;
+  k.alpha_force = c->alpha_force;
+  return k;
+}
+
+// Calls fn(scheme) with the scheme of the configured equation system.
+template <class Fn>
+static int dispatch(const ora_cfg* c, Fn fn) {
+  Config k = to_cfg(c);
+  if (k.N < 0 || k.N > 4 || k.nx < 1 || k.ny < 1) return 1;
+  switch (k.eq) {
+    case EQ_SW1D: { SW1D ph{k.gravity}; Scheme<SW1D> s(ph, k); fn(s); return 0; }
+    case EQ_SW2D: { SW2D ph{k.gravity}; Scheme<SW2D> s(ph, k); fn(s); return 0; }
+    case EQ_MHD2D: { MHD2D ph{k.gamma}; Scheme<MHD2D> s(ph, k); fn(s); return 0; }
+    case EQ_LINADV1D: { LinAdv1D ph; Scheme<LinAdv1D> s(ph, k); fn(s); return 0; }
+    case EQ_VARADV1D: { VarAdv1D ph; Scheme<VarAdv1D> s(ph, k); fn(s); return 0; }
+  }
+  return 2;
+}
+
+extern "C" {
+
+int ora_refel(int N, double* xi, double* w, double* D, double* VL, double* VR, double* gLp, double* gRp,
+              double* Leg) {
+  if (N < 0 || N > 8) return 1;
+  RefElem r(N);
+  int n1 = N + 1;
+  std::memcpy(xi, r.xi.data(), n1 * sizeof(double));
+  std::memcpy(w, r.w.data(), n1 * sizeof(double));
+  std::memcpy(D, r.D.data(), n1 * n1 * sizeof(double));
+  std::memcpy(VL, r.VL.data(), n1 * sizeof(double));
+  std::memcpy(VR, r.VR.data(), n1 * sizeof(double));
+  std::memcpy(gLp, r.gLp.data(), n1 * sizeof(double));
+  std::memcpy(gRp, r.gRp.data(), n1 * sizeof(double));
+  std::memcpy(Leg, r.Leg.data(), n1 * n1 * sizeof(double));
+  return 0;
+}
+
+int ora_tableau(int N, int* s, double* A, double* b) {
+  if (N < 0 || N > 4) return 1;
+  Tableau t(N);
+  *s = t.s;
+  std::memcpy(A, t.A.data(), t.s * t.s * sizeof(double));
+  std::memcpy(b, t.b.data(), t.s * sizeof(double));
+  return 0;
+}
+
+// Pointwise physics: what = 0 flux f_d(u), 1 B_d(u) w, 2 sigma_d(u) (out[0]),
+// 3 constraints P_k(u) (out[0..K-1]), 4 indicator variable (out[0]),
+// 5 ideal speeds (out[0] = |v_d|, out[1] = c).
+int ora_physics(int eq, double gamma, double gravity, double ch, int what, int d, const double* u,
+                const double* w, double* out) {
+  auto run = [&](const auto& ph) {
+    using P = std::decay_t<decltype(ph)>;
+    switch (what) {
+      case 0: ph.template flux<double>(d, u, out, ch); break;
+      case 1: ph.template ncprod<double>(d, u, w, out); break;
+      case 2: out[0] = ph.template sigma<double>(d, u, ch); break;
+      case 3: for (int k = 0; k < P::K; ++k) out[k] = ph.template constraint<double>(k, u); break;
+      case 4: out[0] = ph.template indicator<double>(u); break;
+      case 5: ph.speeds(d, u, out[0], out[1]); break;
+    }
+  };
+  switch (eq) {
+    case EQ_SW1D: run(SW1D{gravity}); return 0;
+    case EQ_SW2D: run(SW2D{gravity}); return 0;
+    case EQ_MHD2D: run(MHD2D{gamma}); return 0;
+    case EQ_LINADV1D: run(LinAdv1D{}); return 0;
+    case EQ_VARADV1D: run(VarAdv1D{}); return 0;
+  }
+  return 2;
+}
+
+int ora_dt_ch(const ora_cfg* c, const double* u, double* dt_ch) {
+  return dispatch(c, [&](auto& s) { s.dt_ch(u, dt_ch[0], dt_ch[1]); });
+}
+
+int ora_alpha(const ora_cfg* c, const double* u, double* araw, double* alpha, uint8_t* tie) {
+  return dispatch(c, [&](auto& s) {
+    std::vector<double> a, b;
+    std::vector<uint8_t> t;
+    s.indicator(u, a, b, t);
+    std::memcpy(araw, a.data(), a.size() * sizeof(double));
+    std::memcpy(alpha, b.data(), b.size() * sizeof(double));
+    if (tie) std::memcpy(tie, t.data(), t.size());
+  });
+}
+
+// One step.  dt_in > 0: use it (c_h is still computed from u unless ch_in >= 0);
+// otherwise dt from eq. time.step.2d.  dt_ch_out = {dt, c_h}.
+// alpha_in (nullable): blending coefficients to use instead of the indicator's.
+int ora_step(const ora_cfg* c, const double* u, double* unew, double dt_in, double ch_in, const double* alpha_in,
+             double* dt_ch_out, double* alpha_out, uint32_t* flags, uint8_t* tie, double* theta_face,
+             double* theta_elem) {
+  return dispatch(c, [&](auto& s) {
+    double dt, ch;
+    s.dt_ch(u, dt, ch);
+    if (dt_in > 0) dt = dt_in;
+    if (ch_in >= 0) ch = ch_in;
+    std::vector<double> araw, alpha;
+    std::vector<uint8_t> t;
+    s.indicator(u, araw, alpha, t);
+    if (alpha_in) alpha.assign(alpha_in, alpha_in + s.E);
+    s.template step<double>(u, unew, dt, ch, alpha, flags, theta_face, theta_elem);
+    if (dt_ch_out) { dt_ch_out[0] = dt; dt_ch_out[1] = ch; }
+    if (alpha_out) std::memcpy(alpha_out, alpha.data(), alpha.size() * sizeof(double));
+    if (tie) std::memcpy(tie, t.data(), t.size());
+  });
+}
+
+// Residual R = (u^n - u^{n+1})/dt; mode 0: high order only (alpha = 0, no
+// limiter), 1: lower order only (alpha = 1, no limiter), 2: as configured.
+int ora_residual(const ora_cfg* c, const double* u, double dt, double ch_in, int mode, double* R) {
+  ora_cfg cc = *c;
+  if (mode == 0) { cc.blending = 0; cc.alpha_force = -1; }
+  if (mode == 1) { cc.blending = 1; cc.alpha_force = 1.0; }
+  return dispatch(&cc, [&](auto& s) {
+    double dtc, ch;
+    s.dt_ch(u, dtc, ch);
+    if (ch_in >= 0) ch = ch_in;
+    std::vector<double> araw, alpha;
+    std::vector<uint8_t> t;
+    s.indicator(u, araw, alpha, t);
+    size_t n = (size_t)s.M * s.E * s.P;
+    std::vector<double> un(n);
+    s.template step<double>(u, un.data(), dt, ch, alpha, nullptr, nullptr, nullptr);
+    for (size_t i = 0; i < n; ++i) R[i] = (u[i] - un[i]) / dt;
+  });
+}
+
+// Forward-mode derivative of the step with dt, c_h, every alpha_e and every
+// theta held at their values at u (frozen switches): Jv = d unew/du . v.
+int ora_jvp(const ora_cfg* c, const double* u, const double* v, double dt, double ch, double* unew, double* Jv) {
+  return dispatch(c, [&](auto& s) {
+    std::vector<double> araw, alpha;
+    std::vector<uint8_t> t;
+    s.indicator(u, araw, alpha, t);
+    size_t n = (size_t)s.M * s.E * s.P;
+    std::vector<Dual> x(n), y(n);
+    for (size_t i = 0; i < n; ++i) x[i] = Dual(u[i], v[i]);
+    s.template step<Dual>(x.data(), y.data(), dt, ch, alpha, nullptr, nullptr, nullptr);
+    for (size_t i = 0; i < n; ++i) { if (unew) unew[i] = y[i].v; Jv[i] = y[i].d; }
+  });
+}
+
+// Algorithmic operation counts of one step, split into the element-local
+// stages, the interface fluxes and the element update:
+// counts[phase*5 + {add, mul, div, sqrt, exp}].
+int ora_count_ops(const ora_cfg* c, const double* u, double dt, double ch, uint64_t* counts) {
+  return dispatch(c, [&](auto& s) {
+    using S = std::decay_t<decltype(s)>;
+    std::vector<double> araw, alpha;
+    std::vector<uint8_t> t;
+    s.indicator(u, araw, alpha, t);
+    size_t n = (size_t)s.M * s.E * s.P;
+    std::vector<Counting> x(n), y(n);
+    for (size_t i = 0; i < n; ++i) x[i] = Counting(u[i]);
+    typename S::template Local<Counting> L;
+    typename S::template Faces<Counting> Fc;
+    auto grab = [&](int ph) {
+      counts[ph * 5 + 0] = FlopCounter::add; counts[ph * 5 + 1] = FlopCounter::mul;
+      counts[ph * 5 + 2] = FlopCounter::div; counts[ph * 5 + 3] = FlopCounter::sqrt;
+      counts[ph * 5 + 4] = FlopCounter::exp; FlopCounter::reset();
+    };
+    FlopCounter::reset();
+    s.template stages<Counting>(x.data(), dt, ch, L);
+    grab(0);
+    s.template faces<Counting>(x.data(), L, alpha, dt, ch, Fc);
+    grab(1);
+    s.template update<Counting>(x.data(), L, Fc, alpha, dt, ch, y.data(), nullptr, nullptr);
+    grab(2);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,549 @@
+// One time step of the time-averaged compact Runge-Kutta flux reconstruction
+// scheme for u_t + f(u)_x + B(u) u_x = 0 with the subcell-FV blend and the
+// admissibility limiters.  TEST INFRASTRUCTURE ONLY: a plain, slow, obviously
+// correct CPU reference; nothing in the product path may use it.
+//
+// The step follows the paper in this order:
+//   1. element means and time step (§5 eq. time.step.2d, Def. of admissibility
+//      in means), GLM cleaning speed c_h (§5.5 below eq. glm.mhd);
+//   2. smoothness indicator alpha_e (§4 eq. blended.scheme and the indicator of
+//      Hennemann et al. it cites);
+//   3. element-local stages (§3 eq. crkfr.non.cons.final with the inner stages
+//      above it), time averages F (eq. disc.avg.flux), U (eq. time.avg.soln),
+//      B^loc (eq. local.time.avg.non.cons) and the face values F^nc (§3 below
+//      eq. local.time.avg.non.cons);
+//   4. interface fluxes: F^num (eq. numflux.cons with the wave speed of eq.
+//      combined.wave.speed), the non-conservative part B(u^{n,±}) U^num (eq.
+//      good.numflux.non.cons), the lower order fluxes (eqs. combined.num.flux,
+//      numflux.args), the blend of eq. Fblend and Algorithm 1;
+//   5. high order update (eq. crkfr.non.cons.final), lower order subcell update
+//      (eq. low.order.update), blend (eq. blended.scheme) and Algorithm 2.
+// Readings of points the paper leaves open are listed in the design notes
+// (time-step CFL(N), c_h, the indicator constants, the 2-D form of Alg. 1, the
+// theta convention).
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "physics.hpp"
+#include "refel.hpp"
+#include "scalar.hpp"
+#include "tableau.hpp"
+
+namespace ora {
+
+struct Config {
+  int eq, N, nx, ny;
+  double lo[2], hi[2];
+  double gamma, gravity;
+  double cs, cfl;  // safety factor C_s and CFL(N) of eq. time.step.2d
+  int blending;    // 0: pure high order; 1: indicator blend; 2: blend + Alg. 1 + Alg. 2
+  double alpha_max, alpha_min;
+  double alpha_force;  // >= 0: every alpha_e is set to this value (tests, residual modes)
+};
+
+enum : uint32_t {
+  FLAG_ALG2 = 1u,          // Algorithm 2 limited the element (theta < 1)
+  FLAG_LOW_INADM = 2u,     // the lower order update u^L is not admissible somewhere
+  FLAG_ALG1 = 4u,          // Algorithm 1 limited a flux on one of the element's faces
+  FLAG_NONFINITE = 8u,     // u^{n+1} holds a non-finite value
+  FLAG_ALG1_GUARD = 16u,   // Algorithm 1 met an inadmissible lower order candidate
+};
+
+// theta_{P_k}(eps, u_a, u_b) of eq. theta.adk for a concave P_k (eq.
+// theta.formula), written with the weight on the candidate u_b: the limited
+// state is theta u_b + (1 - theta) u_a.  Admissible candidates keep theta = 1.
+inline double theta_concave(double eps, double Pa, double Pb, bool& guard) {
+  if (Pa <= 0.0) { guard = true; return 0.0; }
+  if (Pb >= eps) return 1.0;
+  return std::min(1.0, std::fabs((eps - Pa) / (Pb - Pa)));
+}
+
+template <class Phys>
+struct Scheme {
+  static constexpr int M = Phys::M, DIM = Phys::DIM, K = Phys::K;
+  const Phys& ph;
+  Config cfg;
+  RefElem re;
+  Tableau tb;
+  int N, n1, P, nx, ny, E, nfp;
+  double dx[2];
+
+  Scheme(const Phys& p, const Config& c)
+      : ph(p), cfg(c), re(c.N), tb(c.N), N(c.N), n1(c.N + 1) {
+    P = DIM == 1 ? n1 : n1 * n1;
+    nfp = DIM == 1 ? 1 : n1;
+    nx = c.nx; ny = DIM == 1 ? 1 : c.ny;
+    E = nx * ny;
+    dx[0] = (c.hi[0] - c.lo[0]) / nx;
+    dx[1] = DIM == 1 ? 1.0 : (c.hi[1] - c.lo[1]) / ny;
+  }
+
+  // ---------------------------------------------------------------- mesh ---
+  size_t idx(int v, int e, int p) const { return ((size_t)v * E + e) * P + p; }
+  // neighbour across the upper (side=1) or lower (side=0) face in direction d
+  int nbr(int e, int d, int side) const {
+    int ex = e % nx, ey = e / nx;
+    if (d == 0) ex = side ? (ex + 1) % nx : (ex + nx - 1) % nx;
+    else ey = side ? (ey + 1) % ny : (ey + ny - 1) % ny;
+    return ex + nx * ey;
+  }
+  // node with position r along direction d on line q
+  int node(int d, int q, int r) const { return d == 0 ? r + n1 * q : q + n1 * r; }
+  int pos(int d, int p) const { return d == 0 ? p % n1 : p / n1; }
+  int line(int d, int p) const { return d == 0 ? p / n1 : p % n1; }
+  double wnode(int p) const { return DIM == 1 ? re.w[p] : re.w[p % n1] * re.w[p / n1]; }
+  size_t fidx(int d, int v, int e, int q) const { return (((size_t)d * M + v) * E + e) * nfp + q; }
+
+  // ------------------------------------------------- 1. means, dt and c_h ---
+  void mean(const double* u, int e, double* ub) const {
+    for (int v = 0; v < M; ++v) {
+      double s = 0;
+      for (int p = 0; p < P; ++p) s += wnode(p) * u[idx(v, e, p)];
+      ub[v] = s;
+    }
+  }
+  // Lambda = max_e sum_d (|v_d| + c_d)(ubar_e)/dx_d with the ideal (non-GLM)
+  // speeds; dt = C_s CFL(N) / Lambda (eq. time.step.2d).  For GLM-MHD c_h is the
+  // largest value whose waves |v_d| + max(c_f, c_h) leave Lambda unchanged.
+  void dt_ch(const double* u, double& dt, double& ch) const {
+    std::vector<double> ub(M);
+    double Lam = 0;
+    for (int e = 0; e < E; ++e) {
+      mean(u, e, ub.data());
+      double s = 0;
+      for (int d = 0; d < DIM; ++d) {
+        double av, c;
+        ph.speeds(d, ub.data(), av, c);
+        s += (av + c) / dx[d];
+      }
+      Lam = std::max(Lam, s);
+    }
+    dt = cfg.cs * cfg.cfl / Lam;
+    ch = 0.0;
+    if (cfg.eq == EQ_MHD2D) {
+      double best = INFINITY;
+      for (int e = 0; e < E; ++e) {
+        mean(u, e, ub.data());
+        double av[2], c[2];
+        for (int d = 0; d < 2; ++d) ph.speeds(d, ub.data(), av[d], c[d]);
+        double wx = 1.0 / dx[0], wy = 1.0 / dx[1];
+        double R = Lam - (av[0] * wx + av[1] * wy);
+        // largest c with wx max(c_x, c) + wy max(c_y, c) <= R
+        double lo = c[0], hi = c[1], wlo = wx, whi = wy;
+        if (lo > hi) { std::swap(lo, hi); std::swap(wlo, whi); }
+        double ce = (wlo + whi) * hi >= R ? (R - whi * hi) / wlo : R / (wlo + whi);
+        best = std::min(best, ce);
+      }
+      ch = best;
+    }
+  }
+
+  // ---------------------------------------------------- 2. indicator -------
+  // Modal energy indicator: E = max of the energy fractions of the highest and
+  // second highest modes of the indicator variable in orthonormal Legendre
+  // modes; alpha = logistic((s/T)(E - T)), T(N) = 0.5 10^{-1.8 (N+1)^{1/4}},
+  // s = ln(9999); clip below alpha_min / above 1-alpha_min, cap alpha_max;
+  // smoothing alpha_e <- max(alpha_e, alpha_nb/2) over face neighbours.
+  void indicator(const double* u, std::vector<double>& araw, std::vector<double>& alpha,
+                 std::vector<uint8_t>& tie) const {
+    araw.assign(E, 0.0); alpha.assign(E, 0.0); tie.assign(E, 0);
+    if (cfg.alpha_force >= 0.0) { alpha.assign(E, cfg.alpha_force); araw = alpha; return; }
+    if (cfg.blending == 0 || N == 0) return;
+    const double T = 0.5 * std::pow(10.0, -1.8 * std::pow(N + 1.0, 0.25));
+    const double s = std::log(9999.0);
+    std::vector<double> q(P), mode(P), ue(M);
+    for (int e = 0; e < E; ++e) {
+      for (int p = 0; p < P; ++p) {
+        for (int v = 0; v < M; ++v) ue[v] = u[idx(v, e, p)];
+        q[p] = ph.indicator(ue.data());
+      }
+      double tot = 0, c1 = 0, c2 = 0;
+      if (DIM == 1) {
+        for (int k = 0; k < n1; ++k) {
+          double m = 0;
+          for (int p = 0; p < n1; ++p) m += re.w[p] * q[p] * re.Leg[k * n1 + p];
+          tot += m * m;
+          if (k <= N - 1) c1 += m * m;
+          if (k <= N - 2) c2 += m * m;
+        }
+      } else {
+        for (int l = 0; l < n1; ++l)
+          for (int k = 0; k < n1; ++k) {
+            double m = 0;
+            for (int j = 0; j < n1; ++j)
+              for (int i = 0; i < n1; ++i)
+                m += re.w[i] * re.w[j] * q[i + n1 * j] * re.Leg[k * n1 + i] * re.Leg[l * n1 + j];
+            int deg = std::max(k, l);
+            tot += m * m;
+            if (deg <= N - 1) c1 += m * m;
+            if (deg <= N - 2) c2 += m * m;
+          }
+      }
+      double En = tot > 0 ? (tot - c1) / tot : 0.0;
+      if (N >= 2) En = std::max(En, c1 > 0 ? (c1 - c2) / c1 : 0.0);
+      double a = 1.0 / (1.0 + std::exp(-(s / T) * (En - T)));
+      if (std::fabs(a - cfg.alpha_min) < 1e-9 || std::fabs(a - (1.0 - cfg.alpha_min)) < 1e-9) tie[e] = 1;
+      if (a < cfg.alpha_min) a = 0.0;
+      if (a > 1.0 - cfg.alpha_min) a = 1.0;
+      a = std::min(a, cfg.alpha_max);
+      araw[e] = a;
+    }
+    for (int e = 0; e < E; ++e) {
+      double a = araw[e];
+      for (int d = 0; d < DIM; ++d)
+        for (int sd = 0; sd < 2; ++sd) a = std::max(a, 0.5 * araw[nbr(e, d, sd)]);
+      alpha[e] = a;
+    }
+  }
+
+  // ------------------------------------------ 3. element-local stages -----
+  template <class T>
+  struct Local {
+    std::vector<T> F;    // [d][v][e][p] time-averaged flux F_d
+    std::vector<T> U;    // [v][e][p] time-averaged solution
+    std::vector<T> Bl;   // [v][e][p] B^loc
+    std::vector<T> Fnc;  // [d][side][v][e][q]
+    std::vector<T> Ftr, Utr, untr;  // traces [d][side][v][e][q]
+  };
+  size_t tidx(int d, int side, int v, int e, int q) const {
+    return ((((size_t)d * 2 + side) * M + v) * E + e) * nfp + q;
+  }
+
+  template <class T>
+  void stages(const T* un, double dt, double ch, Local<T>& L) const {
+    const int s = tb.s;
+    L.F.assign((size_t)DIM * M * E * P, T(0.0));
+    L.U.assign((size_t)M * E * P, T(0.0));
+    L.Bl.assign((size_t)M * E * P, T(0.0));
+    L.Fnc.assign((size_t)DIM * 2 * M * E * nfp, T(0.0));
+    L.Ftr.assign(L.Fnc.size(), T(0.0));
+    L.Utr.assign(L.Fnc.size(), T(0.0));
+    L.untr.assign(L.Fnc.size(), T(0.0));
+    std::vector<T> Lst((size_t)s * M * P), uj((size_t)M * P), f((size_t)DIM * M * P);
+    std::vector<T> a(M), fo(M), w(M), o(M), du(M), nc(M);
+    for (int e = 0; e < E; ++e) {
+      for (int j = 0; j < s; ++j) {
+        // inner stage u^(j) = u^n - dt sum_{k<j} a_jk L^(k)
+        for (int v = 0; v < M; ++v)
+          for (int p = 0; p < P; ++p) {
+            T acc = T(0.0);
+            for (int k = 0; k < j; ++k) acc = acc + T(tb.A[j * s + k]) * Lst[((size_t)k * M + v) * P + p];
+            uj[(size_t)v * P + p] = j == 0 ? un[idx(v, e, p)] : un[idx(v, e, p)] - T(dt) * acc;
+          }
+        // fluxes at the solution points
+        for (int p = 0; p < P; ++p) {
+          for (int v = 0; v < M; ++v) a[v] = uj[(size_t)v * P + p];
+          for (int d = 0; d < DIM; ++d) {
+            ph.flux(d, a.data(), fo.data(), ch);
+            for (int v = 0; v < M; ++v) f[((size_t)d * M + v) * P + p] = fo[v];
+          }
+        }
+        // L^(j) = sum_d [ D_d f_d + B_d(u) D_d u ] / dx_d  (local operator, eq. dlocx.defn)
+        for (int p = 0; p < P; ++p) {
+          for (int v = 0; v < M; ++v) a[v] = uj[(size_t)v * P + p];
+          T Lp[M], Bp[M];
+          for (int v = 0; v < M; ++v) { Lp[v] = T(0.0); Bp[v] = T(0.0); }
+          for (int d = 0; d < DIM; ++d) {
+            int i = pos(d, p), q = line(d, p);
+            for (int v = 0; v < M; ++v) {
+              T df = T(0.0), dv = T(0.0);
+              for (int r = 0; r < n1; ++r) {
+                T Dir = T(re.D[i * n1 + r]);
+                df = df + Dir * f[((size_t)d * M + v) * P + node(d, q, r)];
+                dv = dv + Dir * uj[(size_t)v * P + node(d, q, r)];
+              }
+              fo[v] = df;
+              du[v] = dv;
+            }
+            ph.ncprod(d, a.data(), du.data(), nc.data());
+            for (int v = 0; v < M; ++v) {
+              Lp[v] = Lp[v] + (fo[v] + nc[v]) / T(dx[d]);
+              Bp[v] = Bp[v] + nc[v] / T(dx[d]);
+            }
+          }
+          for (int v = 0; v < M; ++v) {
+            Lst[((size_t)j * M + v) * P + p] = Lp[v];
+            T bj = T(tb.b[j]);
+            L.U[idx(v, e, p)] = L.U[idx(v, e, p)] + bj * a[v];
+            L.Bl[idx(v, e, p)] = L.Bl[idx(v, e, p)] + bj * Bp[v];
+            for (int d = 0; d < DIM; ++d)
+              L.F[(size_t)d * M * E * P + idx(v, e, p)] =
+                  L.F[(size_t)d * M * E * P + idx(v, e, p)] + bj * f[((size_t)d * M + v) * P + p];
+          }
+        }
+      }
+      // traces of F_d, U and u^n at the faces
+      for (int d = 0; d < DIM; ++d)
+        for (int side = 0; side < 2; ++side) {
+          const std::vector<double>& V = side ? re.VR : re.VL;
+          for (int q = 0; q < nfp; ++q)
+            for (int v = 0; v < M; ++v) {
+              T tf = T(0.0), tu = T(0.0), tn = T(0.0);
+              for (int r = 0; r < n1; ++r) {
+                int p = node(d, q, r);
+                tf = tf + T(V[r]) * L.F[(size_t)d * M * E * P + idx(v, e, p)];
+                tu = tu + T(V[r]) * L.U[idx(v, e, p)];
+                tn = tn + T(V[r]) * un[idx(v, e, p)];
+              }
+              size_t id = tidx(d, side, v, e, q);
+              L.Ftr[id] = tf; L.Utr[id] = tu; L.untr[id] = tn;
+            }
+          // non-conservative extrapolation F^nc = B(u^{n,±}) U^± : the companion of
+          // the interface term B(u^{n,±}) U^num of eq. good.numflux.non.cons (the
+          // same replacement of the stage values u^(j)± by u^{n,±} in both terms,
+          // so that their difference vanishes where the solution is continuous)
+          for (int q = 0; q < nfp; ++q) {
+            for (int v = 0; v < M; ++v) {
+              a[v] = L.untr[tidx(d, side, v, e, q)];
+              w[v] = L.Utr[tidx(d, side, v, e, q)];
+            }
+            ph.ncprod(d, a.data(), w.data(), o.data());
+            for (int v = 0; v < M; ++v) L.Fnc[tidx(d, side, v, e, q)] = o[v];
+          }
+        }
+    }
+  }
+
+  // ----------------------------------------------- 4. interface fluxes ----
+  // lower order fluxes f^{num,-}, f^{num,+}(uL, uR) of eq. combined.num.flux
+  template <class T>
+  void lof(int d, const T* uL, const T* uR, double ch, T* fm, T* fp) const {
+    T fL[M], fR[M], bL[M], bR[M], avg[M];
+    T lam = tmax(ph.sigma(d, uL, ch), ph.sigma(d, uR, ch));
+    ph.flux(d, uL, fL, ch);
+    ph.flux(d, uR, fR, ch);
+    for (int v = 0; v < M; ++v) avg[v] = T(0.5) * (uL[v] + uR[v]);
+    ph.ncprod(d, uL, avg, bL);
+    ph.ncprod(d, uR, avg, bR);
+    for (int v = 0; v < M; ++v) {
+      T fc = T(0.5) * (fL[v] + fR[v]) - T(0.5) * lam * (uR[v] - uL[v]);
+      fm[v] = fc + bL[v];
+      fp[v] = fc + bR[v];
+    }
+  }
+
+  template <class T>
+  bool admissible(const T* x) const {
+    for (int k = 0; k < K; ++k)
+      if (!(val(ph.constraint(k, x)) > 0.0)) return false;
+    return true;
+  }
+
+  template <class T>
+  struct Faces {
+    std::vector<T> Fm, Fp;        // [d][v][e][q]: face d between e and nbr(e,d,1)
+    std::vector<double> theta;    // [d][e][q] product of Alg. 1 thetas
+    std::vector<uint8_t> guard;   // [d][e][q]
+  };
+
+  template <class T>
+  void faces(const T* un, const Local<T>& L, const std::vector<double>& alpha, double dt, double ch,
+             Faces<T>& Fc) const {
+    Fc.Fm.assign((size_t)DIM * M * E * nfp, T(0.0));
+    Fc.Fp.assign(Fc.Fm.size(), T(0.0));
+    Fc.theta.assign((size_t)DIM * E * nfp, 1.0);
+    Fc.guard.assign((size_t)DIM * E * nfp, 0);
+    T a[M], b[M], FL[M], FR[M], UL[M], UR[M], Fnum[M], Unum[M], Ba[M], Bb[M];
+    T sL[M], sR[M], sLi[M], sRi[M], fLOm[M], fLOp[M], Fm[M], Fp[M], tmp[M], finL[M], finR[M];
+    T uN[M], u0[M], uNlo[M], u0lo[M];
+    for (int d = 0; d < DIM; ++d)
+      for (int e = 0; e < E; ++e) {
+        int en = nbr(e, d, 1);
+        for (int q = 0; q < nfp; ++q) {
+          for (int v = 0; v < M; ++v) {
+            a[v] = L.untr[tidx(d, 1, v, e, q)];
+            b[v] = L.untr[tidx(d, 0, v, en, q)];
+            FL[v] = L.Ftr[tidx(d, 1, v, e, q)];
+            FR[v] = L.Ftr[tidx(d, 0, v, en, q)];
+            UL[v] = L.Utr[tidx(d, 1, v, e, q)];
+            UR[v] = L.Utr[tidx(d, 0, v, en, q)];
+          }
+          for (int v = 0; v < M; ++v) {
+            sL[v] = un[idx(v, e, node(d, q, N))];
+            sR[v] = un[idx(v, en, node(d, q, 0))];
+          }
+          // high order time-averaged fluxes (eqs. numflux.cons, good.numflux.non.cons);
+          // lambda from the face values of u^n (eq. rusanov.wave.speed); a face value
+          // that is not admissible (an undershoot of the polynomial next to a jump)
+          // gives its wave speed at the adjacent solution point instead.
+          T sa = admissible(a) ? ph.sigma(d, a, ch) : ph.sigma(d, sL, ch);
+          T sb = admissible(b) ? ph.sigma(d, b, ch) : ph.sigma(d, sR, ch);
+          T lam = tmax(sa, sb);
+          for (int v = 0; v < M; ++v) {
+            Fnum[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * lam * (UR[v] - UL[v]);
+            Unum[v] = T(0.5) * (UL[v] + UR[v]);
+          }
+          ph.ncprod(d, a, Unum, Ba);
+          ph.ncprod(d, b, Unum, Bb);
+          // lower order flux at the face from the neighbouring subcell values
+          lof(d, sL, sR, ch, fLOm, fLOp);
+          // blend with alpha_{e+1/2} = (alpha_e + alpha_{e+1})/2 (eq. Fblend)
+          double af = 0.5 * (alpha[e] + alpha[en]);
+          for (int v = 0; v < M; ++v) {
+            Fm[v] = T(1.0 - af) * (Fnum[v] + Ba[v]) + T(af) * fLOm[v];
+            Fp[v] = T(1.0 - af) * (Fnum[v] + Bb[v]) + T(af) * fLOp[v];
+          }
+          // Algorithm 1: limit F^± so that the neighbouring subcell updates stay
+          // admissible; in DIM dimensions the candidate uses DIM*dt (the subcell
+          // update is the mean of DIM one-directional updates with DIM*dt).
+          size_t fi = ((size_t)d * E + e) * nfp + q;
+          if (cfg.blending == 2 && N >= 1) {
+            for (int v = 0; v < M; ++v) {
+              sLi[v] = un[idx(v, e, node(d, q, N - 1))];
+              sRi[v] = un[idx(v, en, node(d, q, 1))];
+            }
+            lof(d, sLi, sL, ch, tmp, finL);  // f^{e,+}_{N-1/2}
+            lof(d, sR, sRi, ch, finR, tmp);  // f^{e+1,-}_{1/2}
+            T cN = T(DIM * dt / (re.w[N] * dx[d])), c0 = T(DIM * dt / (re.w[0] * dx[d]));
+            auto cand = [&]() {
+              for (int v = 0; v < M; ++v) {
+                uN[v] = sL[v] - cN * (Fm[v] - finL[v]);
+                u0[v] = sR[v] - c0 * (finR[v] - Fp[v]);
+              }
+            };
+            for (int v = 0; v < M; ++v) {
+              uNlo[v] = sL[v] - cN * (fLOm[v] - finL[v]);
+              u0lo[v] = sR[v] - c0 * (finR[v] - fLOp[v]);
+            }
+            cand();
+            double Theta = 1.0;
+            bool guard = false;
+            for (int k = 0; k < K; ++k) {
+              double PN = val(ph.constraint(k, uNlo)), P0 = val(ph.constraint(k, u0lo));
+              double th0 = theta_concave(0.1 * P0, P0, val(ph.constraint(k, u0)), guard);
+              double thN = theta_concave(0.1 * PN, PN, val(ph.constraint(k, uN)), guard);
+              double th = std::min(th0, thN);
+              for (int v = 0; v < M; ++v) {
+                Fm[v] = T(th) * Fm[v] + T(1.0 - th) * fLOm[v];
+                Fp[v] = T(th) * Fp[v] + T(1.0 - th) * fLOp[v];
+              }
+              cand();
+              Theta *= th;
+            }
+            Fc.theta[fi] = Theta;
+            Fc.guard[fi] = guard ? 1 : 0;
+          }
+          for (int v = 0; v < M; ++v) {
+            Fc.Fm[fidx(d, v, e, q)] = Fm[v];
+            Fc.Fp[fidx(d, v, e, q)] = Fp[v];
+          }
+        }
+      }
+  }
+
+  // ------------------------------------------------ 5. element update -----
+  template <class T>
+  void update(const T* un, const Local<T>& L, const Faces<T>& Fc, const std::vector<double>& alpha,
+              double dt, double ch, T* unew, uint32_t* flags, double* theta_elem) const {
+    std::vector<T> uH((size_t)M * P), uL((size_t)M * P), us((size_t)M * P);
+    T x0[M], x1[M], fm[M], fp[M], tmp[M];
+    for (int e = 0; e < E; ++e) {
+      uint32_t fl = 0;
+      // faces of this element: Alg. 1 activity
+      for (int d = 0; d < DIM; ++d)
+        for (int q = 0; q < nfp; ++q) {
+          size_t iu = ((size_t)d * E + e) * nfp + q, il = ((size_t)d * E + nbr(e, d, 0)) * nfp + q;
+          if (Fc.theta[iu] < 1.0 || Fc.theta[il] < 1.0) fl |= FLAG_ALG1;
+          if (Fc.guard[iu] || Fc.guard[il]) fl |= FLAG_ALG1_GUARD;
+        }
+      // high order update (eq. crkfr.non.cons.final), corrections along each line
+      for (int p = 0; p < P; ++p)
+        for (int v = 0; v < M; ++v) {
+          T R = L.Bl[idx(v, e, p)];
+          for (int d = 0; d < DIM; ++d) {
+            int i = pos(d, p), q = line(d, p);
+            T dF = T(0.0);
+            for (int r = 0; r < n1; ++r)
+              dF = dF + T(re.D[i * n1 + r]) * L.F[(size_t)d * M * E * P + idx(v, e, node(d, q, r))];
+            int el = nbr(e, d, 0);
+            T cR = Fc.Fm[fidx(d, v, e, q)] - L.Ftr[tidx(d, 1, v, e, q)] - L.Fnc[tidx(d, 1, v, e, q)];
+            T cL = Fc.Fp[fidx(d, v, el, q)] - L.Ftr[tidx(d, 0, v, e, q)] - L.Fnc[tidx(d, 0, v, e, q)];
+            R = R + (dF + cR * T(re.gRp[i]) + cL * T(re.gLp[i])) / T(dx[d]);
+          }
+          uH[(size_t)v * P + p] = un[idx(v, e, p)] - T(dt) * R;
+        }
+      if (cfg.blending == 0) {
+        for (int v = 0; v < M; ++v)
+          for (int p = 0; p < P; ++p) unew[idx(v, e, p)] = uH[(size_t)v * P + p];
+      } else {
+        // lower order subcell update (eq. low.order.update); subcell p has width w_p dx
+        for (int p = 0; p < P; ++p) {
+          T R[M];
+          for (int v = 0; v < M; ++v) R[v] = T(0.0);
+          for (int d = 0; d < DIM; ++d) {
+            int i = pos(d, p), q = line(d, p), el = nbr(e, d, 0);
+            T right[M], left[M];
+            if (i < N) {
+              for (int v = 0; v < M; ++v) { x0[v] = un[idx(v, e, p)]; x1[v] = un[idx(v, e, node(d, q, i + 1))]; }
+              lof(d, x0, x1, ch, fm, tmp);
+              for (int v = 0; v < M; ++v) right[v] = fm[v];
+            } else {
+              for (int v = 0; v < M; ++v) right[v] = Fc.Fm[fidx(d, v, e, q)];
+            }
+            if (i > 0) {
+              for (int v = 0; v < M; ++v) { x0[v] = un[idx(v, e, node(d, q, i - 1))]; x1[v] = un[idx(v, e, p)]; }
+              lof(d, x0, x1, ch, tmp, fp);
+              for (int v = 0; v < M; ++v) left[v] = fp[v];
+            } else {
+              for (int v = 0; v < M; ++v) left[v] = Fc.Fp[fidx(d, v, el, q)];
+            }
+            for (int v = 0; v < M; ++v) R[v] = R[v] + (right[v] - left[v]) / T(re.w[i] * dx[d]);
+          }
+          for (int v = 0; v < M; ++v) uL[(size_t)v * P + p] = un[idx(v, e, p)] - T(dt) * R[v];
+        }
+        // blend (eq. blended.scheme)
+        double al = alpha[e];
+        for (size_t i = 0; i < us.size(); ++i) us[i] = T(1.0 - al) * uH[i] + T(al) * uL[i];
+        // Algorithm 2
+        double Theta = 1.0;
+        T z[M];
+        for (int k = 0; k < K; ++k) {
+          double Pmin = INFINITY;
+          for (int p = 0; p < P; ++p) {
+            for (int v = 0; v < M; ++v) z[v] = uL[(size_t)v * P + p];
+            Pmin = std::min(Pmin, val(ph.constraint(k, z)));
+          }
+          if (Pmin <= 0.0) fl |= FLAG_LOW_INADM;
+          if (cfg.blending == 2) {
+            double eps = 0.1 * Pmin, th = 1.0;
+            bool guard = false;
+            for (int p = 0; p < P; ++p) {
+              for (int v = 0; v < M; ++v) z[v] = uL[(size_t)v * P + p];
+              double Pa = val(ph.constraint(k, z));
+              for (int v = 0; v < M; ++v) z[v] = us[(size_t)v * P + p];
+              double Pb = val(ph.constraint(k, z));
+              th = std::min(th, theta_concave(eps, Pa, Pb, guard));
+            }
+            for (size_t i = 0; i < us.size(); ++i) us[i] = T(th) * us[i] + T(1.0 - th) * uL[i];
+            Theta *= th;
+          }
+        }
+        if (Theta < 1.0) fl |= FLAG_ALG2;
+        if (theta_elem) theta_elem[e] = Theta;
+        for (int v = 0; v < M; ++v)
+          for (int p = 0; p < P; ++p) unew[idx(v, e, p)] = us[(size_t)v * P + p];
+      }
+      for (int v = 0; v < M; ++v)
+        for (int p = 0; p < P; ++p)
+          if (!std::isfinite(val(unew[idx(v, e, p)]))) fl |= FLAG_NONFINITE;
+      if (flags) flags[e] = fl;
+    }
+  }
+
+  // full step for scalar type T with dt, c_h and alpha given (frozen)
+  template <class T>
+  void step(const T* un, T* unew, double dt, double ch, const std::vector<double>& alpha, uint32_t* flags,
+            double* theta_face, double* theta_elem) const {
+    Local<T> L;
+    Faces<T> Fc;
+    stages(un, dt, ch, L);
+    faces(un, L, alpha, dt, ch, Fc);
+    if (theta_face) std::copy(Fc.theta.begin(), Fc.theta.end(), theta_face);
+    update(un, L, Fc, alpha, dt, ch, unew, flags, theta_elem);
+  }
+};
+
+}  // namespace ora
