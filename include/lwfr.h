@@ -1,0 +1,147 @@
+/*
+ * lwfr.h - C ABI of the MI355X (gfx950) time step of the single-stage,
+ * time-averaged flux reconstruction scheme for hyperbolic systems with
+ * non-conservative products (Babbar & Ranocha, "Compact Runge-Kutta flux
+ * reconstruction methods for non-conservative hyperbolic equations").
+ *
+ * Problem (paper §3 eq. flux.and.non.cons, 2-D form in §5 above eq.
+ * time.step.2d):   u_t + sum_d [ f_d(u)_{x_d} + B_d(u) u_{x_d} ] = 0
+ * on a uniform periodic Cartesian mesh of tensor-product elements with the
+ * N+1 Gauss-Legendre solution points per direction (§2 eq. soln.points).
+ *
+ * Conventions shared by every call
+ *  - All floating point data are IEEE FP64.
+ *  - State layout u[var][elem][node]: elements x-fastest (e = ex + nx*ey),
+ *    nodes x-fastest inside an element (p = i + (N+1)*j).  Variables:
+ *      SW1D    (h, h v, b)                SW2D (h, h v1, h v2, b)
+ *      GLMMHD2D (rho, rho v1, rho v2, rho v3, E, B1, B2, B3, psi)
+ *      LINADV1D (u)                       VARADV1D (v, a)
+ *  - Pointers named d_* are device pointers on the device current when
+ *    lwfr_bind was called; the caller owns and allocates every buffer
+ *    (state, outputs, workspace).  The library never allocates device memory.
+ *  - Calls that take device pointers only enqueue work on the bound stream and
+ *    return at once; their status covers argument checks and launch errors.
+ *    Numerical trouble inside a step is reported per element through d_flags
+ *    and accumulated in the context; lwfr_query reads it back.
+ *  - Functions return lwfr_status; lwfr_last_error() gives a thread-local
+ *    message for the last failing call.
+ */
+#ifndef LWFR_H
+#define LWFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LWFR_ABI_VERSION 1u
+
+typedef struct lwfr_ctx lwfr_ctx;
+
+typedef enum {
+  LWFR_OK = 0,
+  LWFR_E_INVALID_ARG = 1,   /* bad pointer, size, aliasing or configuration value */
+  LWFR_E_UNSUPPORTED = 2,   /* valid request the library does not implement */
+  LWFR_E_HIP = 3,           /* a HIP runtime call failed */
+  LWFR_E_INADMISSIBLE = 4,  /* lwfr_query: a lower order update was not admissible */
+  LWFR_E_NONFINITE = 5,     /* lwfr_query: a step produced a non-finite value */
+  LWFR_E_WORKSPACE = 6,     /* workspace missing, too small or misaligned */
+  LWFR_E_STATE = 7          /* call out of order (e.g. step before bind) */
+} lwfr_status;
+
+typedef enum {
+  LWFR_EQ_SW1D = 1,      /* shallow water, bed b carried as a variable, B u_x = (0, g h b_x, 0) */
+  LWFR_EQ_SW2D = 2,
+  LWFR_EQ_GLMMHD2D = 3,  /* ideal GLM-MHD with Godunov-Powell and GLM terms (§5.5 eq. glm.mhd) */
+  LWFR_EQ_LINADV1D = 4,  /* u_t + u_x = 0 (test system) */
+  LWFR_EQ_VARADV1D = 5   /* v_t + a v_x = 0 as a non-conservative system (§5.1 eq. var.coeff.adv.non.cons) */
+} lwfr_equation;
+
+typedef enum {
+  LWFR_BLEND_OFF = 0,        /* pure high order step (alpha_e = 0, no limiting) */
+  LWFR_BLEND_INDICATOR = 1,  /* subcell blend with the smoothness indicator (§4 eq. blended.scheme) */
+  LWFR_BLEND_ADMISSIBLE = 2  /* blend + Algorithm 1 (face fluxes) + Algorithm 2 (element blend) */
+} lwfr_blending;
+
+/* Per-element flag bits written to d_flags. */
+#define LWFR_FLAG_ALG2 1u          /* Algorithm 2 limited the element */
+#define LWFR_FLAG_LOW_INADM 2u     /* the lower order update is not admissible in the element */
+#define LWFR_FLAG_ALG1 4u          /* Algorithm 1 limited a flux on one of the element's faces */
+#define LWFR_FLAG_NONFINITE 8u     /* the new state holds a non-finite value */
+#define LWFR_FLAG_ALG1_GUARD 16u   /* Algorithm 1 met an inadmissible lower order candidate */
+
+typedef struct {
+  uint32_t abi_version;  /* LWFR_ABI_VERSION */
+  int32_t equation;      /* lwfr_equation */
+  int32_t degree;        /* N, 1..4 */
+  int32_t nelem[2];      /* elements per direction; nelem[1] ignored in 1-D */
+  double lo[2], hi[2];   /* domain box; periodic in every direction */
+  double gamma;          /* GLM-MHD ratio of specific heats (5/3) */
+  double gravity;        /* shallow water g (9.81) */
+  double cfl_safety;     /* C_s of eq. time.step.2d (the paper's default 0.9) */
+  double cfl_number;     /* CFL(N) of eq. time.step.2d; <= 0: the library's own Fourier value */
+  int32_t blending;      /* lwfr_blending */
+  double alpha_max;      /* cap of the blending coefficient (0.5) */
+  double alpha_min;      /* indicator clip threshold (1e-3) */
+  double alpha_force;    /* >= 0: every alpha_e is this value; < 0: smoothness indicator */
+} lwfr_config;
+
+/* Validates cfg and builds the reference element, tableau and launch shapes on
+ * the host.  No device work.  *out receives a context owned by the caller
+ * until lwfr_destroy.  Errors: LWFR_E_INVALID_ARG (bad value, null pointer,
+ * ABI mismatch), LWFR_E_UNSUPPORTED (degree outside 1..4). */
+lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out);
+
+/* Device workspace bytes the context needs (traces, face fluxes, indicator,
+ * reductions).  256-byte alignment is required for the workspace pointer. */
+lwfr_status lwfr_workspace_bytes(const lwfr_ctx* ctx, size_t* bytes);
+
+/* Number of doubles of one state u (M * E * (N+1)^d). */
+lwfr_status lwfr_state_size(const lwfr_ctx* ctx, size_t* ndouble);
+
+/* Reference solution points xi_p on [0,1] and weights w_p (host arrays of N+1). */
+lwfr_status lwfr_reference_nodes(const lwfr_ctx* ctx, double* xi, double* w);
+
+/* The library's Fourier (von Neumann) CFL(N) of the linearised scheme. */
+lwfr_status lwfr_cfl_number(int32_t degree, double* cfl);
+
+/* Attaches caller-owned device workspace and a HIP stream (hipStream_t passed as
+ * void*; NULL = default stream).  The workspace must stay valid until the next
+ * bind or lwfr_destroy.  Errors: LWFR_E_WORKSPACE. */
+lwfr_status lwfr_bind(lwfr_ctx* ctx, void* d_workspace, size_t bytes, void* stream);
+
+/* One time step u^n -> u^{n+1} (paper §3 eq. crkfr.non.cons.final with the
+ * blend of §4 and Algorithms 1-2).
+ *   d_u_in   state u^n (read only)
+ *   d_u_out  state u^{n+1}; must not alias d_u_in (LWFR_E_INVALID_ARG)
+ *   dt       > 0: time step used as given; <= 0: eq. time.step.2d on the device
+ *   d_dt_ch  nullable; receives {dt, c_h} (c_h = GLM cleaning speed, 0 otherwise)
+ *   d_alpha  nullable; receives the blending coefficient alpha_e of each element
+ *   d_flags  nullable; receives LWFR_FLAG_* bits of each element
+ * Asynchronous on the bound stream; LWFR_E_STATE if not bound. */
+lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
+                      double* d_alpha, uint32_t* d_flags);
+
+/* Residual R = (u^n - u^{n+1})/dt of one step with the given dt > 0.
+ * mode 0: high order only (alpha = 0, no limiting); 1: lower order subcell
+ * scheme only (alpha = 1, no limiting); 2: as configured.  d_R must not alias d_u. */
+lwfr_status lwfr_residual(lwfr_ctx* ctx, const double* d_u, double dt, int32_t mode, double* d_R);
+
+/* Synchronises the bound stream and returns the OR of the flags of every step
+ * since the previous query (then clears it): LWFR_E_NONFINITE if a non-finite
+ * value appeared, LWFR_E_INADMISSIBLE if a lower order update was inadmissible,
+ * LWFR_OK otherwise.  flags_or (nullable) receives the raw OR. */
+lwfr_status lwfr_query(lwfr_ctx* ctx, uint32_t* flags_or);
+
+lwfr_status lwfr_destroy(lwfr_ctx* ctx);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* lwfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LWFR_H */

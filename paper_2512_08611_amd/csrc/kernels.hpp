@@ -1,0 +1,734 @@
+// gfx950 kernels of one time step of the time-averaged flux reconstruction
+// scheme with non-conservative products (paper §2-§4).
+//
+//   k_pre      element means, ideal wave speeds, smoothness indicator (raw)
+//   k_dt       Lambda = max_e sum_d (|v_d|+c_d)/dx_d, dt = C_s CFL(N)/Lambda (eq. time.step.2d)
+//   k_ch       GLM cleaning speed candidates per element, k_ch_fin the minimum
+//   k_stages   element-local stages, time averages F, U, B^loc, volume residual and face traces
+//   k_faces    interface fluxes, blend of eq. Fblend and Algorithm 1, one thread per face point
+//   k_update   correction update, subcell FV update, blend and Algorithm 2
+//   k_residual R = (u^n - u^{n+1})/dt
+//
+// Layouts: state [var][elem][node]; face arrays [dir][..][var][elem*nfp + q]
+// where q is the position along the face; elements and nodes x-fastest.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "physics.hpp"
+#include "refel.hpp"
+
+namespace lwfr {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// everything a kernel needs besides the state pointers, passed by value
+struct KParams {
+  int nx, ny, E, nblk_pre;
+  double dx[2], inv_dx[2];
+  double D[kMaxN1][kMaxN1], VL[kMaxN1], VR[kMaxN1], w[kMaxN1], gR[kMaxN1], gL[kMaxN1];
+  double Leg[kMaxN1][kMaxN1];
+  double inv_wdx[2][kMaxN1];  // 1/(w_p dx_d)
+  double g, gamma;
+  int blending;
+  double alpha_max, alpha_min, alpha_force;
+  double ind_T, ind_s;        // indicator threshold T(N) and logistic sharpness s
+  double cs_cfl;              // C_s * CFL(N)
+  double dt_in;               // > 0: fixed time step
+  // workspace
+  double* scal;               // [0] dt, [1] c_h, [2] Lambda
+  double* part;               // per-block partial maxima / minima
+  double* part2;
+  double* speeds;             // [E][2*DIM] (|v_d|, c_d)
+  double* alpha_raw;          // [E]
+  double* alpha;              // [E] smoothed alpha used by the step
+  double* Ftr;                // [d][side][M][E*nfp] trace of F_d
+  double* Utr;                // [d][side][M][E*nfp] trace of U
+  double* untr;               // [d][side][M][E*nfp] trace of u^n
+  double* Fm;                 // [d][M][E*nfp] F^- of face (e, e+1)
+  double* Fp;                 // [d][M][E*nfp] F^+
+  double* Dm;                 // [d][M][E*nfp] F^- - F_tr^- - B(u^{n,-}) U^-
+  double* Dp;                 // [d][M][E*nfp] F^+ - F_tr^+ - B(u^{n,+}) U^+
+  double* theta_face;         // [d][E*nfp] product of Algorithm 1 thetas
+  uint32_t* guard_face;       // [d][E*nfp]
+  uint32_t* flag_or;          // [1] OR of every element flag since the last query
+  double* theta_elem;         // [E] product of Algorithm 2 thetas
+};
+
+__device__ inline int nbr_elem(const KParams& kp, int e, int d, int side) {
+  int ex = e % kp.nx, ey = e / kp.nx;
+  if (d == 0) ex = side ? (ex + 1 == kp.nx ? 0 : ex + 1) : (ex == 0 ? kp.nx - 1 : ex - 1);
+  else ey = side ? (ey + 1 == kp.ny ? 0 : ey + 1) : (ey == 0 ? kp.ny - 1 : ey - 1);
+  return ex + kp.nx * ey;
+}
+
+template <int n1>
+__device__ __host__ constexpr int node_at(int d, int q, int r) { return d == 0 ? r + n1 * q : q + n1 * r; }
+
+__device__ inline double theta_limit(double eps, double Pa, double Pb, bool& guard) {
+  // theta_{P_k}(eps, u_a, u_b) for a concave P_k (eq. theta.formula), weight on the
+  // candidate u_b; admissible candidates keep theta = 1
+  if (Pa <= 0.0) { guard = true; return 0.0; }
+  if (Pb >= eps) return 1.0;
+  return fmin(1.0, fabs((eps - Pa) / (Pb - Pa)));
+}
+
+// ------------------------------------------------------------------------
+// k_pre: one thread per element
+template <class Ph, int N>
+__global__ void __launch_bounds__(256) k_pre(const KParams kp, const double* __restrict__ un) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
+  __shared__ double s_max[256];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const PhysParams pp{kp.g, kp.gamma, 0.0};
+  double lam = 0.0;
+  if (e < kp.E) {
+    double ub[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const double* src = un + ((size_t)v * kp.E + e) * P;
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const double wp = DIM == 1 ? kp.w[p] : kp.w[p % n1] * kp.w[p / n1];
+        s += wp * src[p];
+      }
+      ub[v] = s;
+    }
+    double av, c;
+    Ph::template speeds<0>(ub, av, c, pp);
+    lam = (av + c) * kp.inv_dx[0];
+    kp.speeds[(size_t)e * 2 * DIM + 0] = av;
+    kp.speeds[(size_t)e * 2 * DIM + 1] = c;
+    if constexpr (DIM == 2) {
+      Ph::template speeds<1>(ub, av, c, pp);
+      lam += (av + c) * kp.inv_dx[1];
+      kp.speeds[(size_t)e * 4 + 2] = av;
+      kp.speeds[(size_t)e * 4 + 3] = c;
+    }
+    // smoothness indicator: energy fractions of the highest modes of q in the
+    // orthonormal Legendre basis, logistic map, clip and cap
+    if (kp.blending >= 1 && kp.alpha_force < 0.0) {
+      double q[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        double x[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = un[((size_t)v * kp.E + e) * P + p];
+        q[p] = Ph::indicator(x, pp);
+      }
+      double tot = 0.0, c1 = 0.0, c2 = 0.0;
+      if constexpr (DIM == 1) {
+#pragma unroll
+        for (int k = 0; k < n1; ++k) {
+          double m = 0.0;
+#pragma unroll
+          for (int p = 0; p < n1; ++p) m += kp.w[p] * q[p] * kp.Leg[k][p];
+          const double m2 = m * m;
+          tot += m2;
+          if (k <= N - 1) c1 += m2;
+          if (k <= N - 2) c2 += m2;
+        }
+      } else {
+        double t[n1][n1];  // t[k][jj] = sum_i w_i L_k(xi_i) q(i, jj)
+#pragma unroll
+        for (int k = 0; k < n1; ++k)
+#pragma unroll
+          for (int jj = 0; jj < n1; ++jj) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < n1; ++i) s += kp.w[i] * kp.Leg[k][i] * q[i + n1 * jj];
+            t[k][jj] = s;
+          }
+#pragma unroll
+        for (int l = 0; l < n1; ++l)
+#pragma unroll
+          for (int k = 0; k < n1; ++k) {
+            double m = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < n1; ++jj) m += kp.w[jj] * kp.Leg[l][jj] * t[k][jj];
+            const double m2 = m * m;
+            const int deg = k > l ? k : l;
+            tot += m2;
+            if (deg <= N - 1) c1 += m2;
+            if (deg <= N - 2) c2 += m2;
+          }
+      }
+      double En = tot > 0.0 ? (tot - c1) / tot : 0.0;
+      if (N >= 2) {
+        const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
+        En = En >= e2 ? En : e2;
+      }
+      double a = 1.0 / (1.0 + exp(-(kp.ind_s / kp.ind_T) * (En - kp.ind_T)));
+      if (a < kp.alpha_min) a = 0.0;
+      if (a > 1.0 - kp.alpha_min) a = 1.0;
+      a = fmin(a, kp.alpha_max);
+      kp.alpha_raw[e] = a;
+    }
+  }
+  s_max[threadIdx.x] = lam;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) kp.part[blockIdx.x] = s_max[0];
+}
+
+// k_dt: one block; Lambda and dt
+__global__ void __launch_bounds__(256) k_dt(const KParams kp, double* d_dt_ch, int has_ch) {
+  __shared__ double s_max[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < kp.nblk_pre; i += blockDim.x) m = fmax(m, kp.part[i]);
+  s_max[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double lam = s_max[0];
+    const double dt = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
+    kp.scal[0] = dt;
+    kp.scal[2] = lam;
+    if (!has_ch) {
+      kp.scal[1] = 0.0;
+      if (d_dt_ch) { d_dt_ch[0] = dt; d_dt_ch[1] = 0.0; }
+    }
+  }
+}
+
+// k_ch: GLM speed candidate of each element: the largest c with
+// wx max(c_x, c) + wy max(c_y, c) <= Lambda - (wx |v_x| + wy |v_y|)
+__global__ void __launch_bounds__(256) k_ch(const KParams kp) {
+  __shared__ double s_min[256];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double ce = INFINITY;
+  if (e < kp.E) {
+    const double* sp = kp.speeds + (size_t)e * 4;
+    const double wx = kp.inv_dx[0], wy = kp.inv_dx[1];
+    const double R = kp.scal[2] - (sp[0] * wx + sp[2] * wy);
+    double lo = sp[1], hi = sp[3], wlo = wx, whi = wy;
+    if (lo > hi) { double t = lo; lo = hi; hi = t; t = wlo; wlo = whi; whi = t; }
+    ce = (wlo + whi) * hi >= R ? (R - whi * hi) / wlo : R / (wlo + whi);
+  }
+  s_min[threadIdx.x] = ce;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) kp.part2[blockIdx.x] = s_min[0];
+}
+
+__global__ void __launch_bounds__(256) k_ch_fin(const KParams kp, double* d_dt_ch) {
+  __shared__ double s_min[256];
+  double m = INFINITY;
+  for (int i = threadIdx.x; i < kp.nblk_pre; i += blockDim.x) m = fmin(m, kp.part2[i]);
+  s_min[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    kp.scal[1] = s_min[0];
+    if (d_dt_ch) { d_dt_ch[0] = kp.scal[0]; d_dt_ch[1] = s_min[0]; }
+  }
+}
+
+// ------------------------------------------------------------------------
+// k_stages: one thread per solution point, EPB elements per block.
+// Inner stages u^(s) = u^n - dt sum_{k<s} a_sk L^(k) with the local operator
+// L = sum_d [D_d f_d(u) + B_d(u) D_d u]/dx_d (paper §3, stages above eq.
+// crkfr.non.cons.final); F_d, U and B^loc accumulate with the weights b_s.
+// Output: the volume part R_vol = B^loc + sum_d D_d F_d/dx_d of the high order
+// residual (written to the output state buffer) and the face traces of F_d, U, u^n.
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+    k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
+  using Tab = Tableau<N>;
+  constexpr int S = Tab::S;
+  constexpr int NBUF = (DIM * M + DIM * NCD) > (DIM * M + M) ? (DIM * M + DIM * NCD) : (DIM * M + M);
+  __shared__ double s_buf[EPB][NBUF][P];
+
+  const int tid = threadIdx.x;
+  const int le = tid / P, p = tid - le * P;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = e < kp.E;
+  const int i = p % n1, j = p / n1;
+  const double dt = kp.scal[0];
+  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+
+  double un[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) un[v] = act ? un_g[((size_t)v * kp.E + e) * P + p] : 1.0;
+  double Drow[DIM][n1];
+#pragma unroll
+  for (int r = 0; r < n1; ++r) {
+    Drow[0][r] = kp.D[i][r];
+    if constexpr (DIM == 2) Drow[1][r] = kp.D[j][r];
+  }
+
+  double Fa[DIM][M], Ua[M], Bl[M], Lk[S][M], u[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    Ua[v] = 0.0; Bl[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Fa[d][v] = 0.0;
+  }
+
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double acc = 0.0;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < st; ++k)
+        if (Tab::a(st, k) != 0.0) { acc = any ? acc + Tab::a(st, k) * Lk[k][v] : Tab::a(st, k) * Lk[k][v]; any = true; }
+      u[v] = any ? un[v] - dt * acc : un[v];
+    }
+    double f[DIM][M];
+    Ph::template flux<0>(u, f[0], pp);
+    if constexpr (DIM == 2) Ph::template flux<1>(u, f[1], pp);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+      for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = f[d][v];
+    if constexpr (Ph::NCD > 0) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int c = 0; c < Ph::NCD; ++c) s_buf[le][DIM * M + d * NCD + c][p] = u[Ph::nc_comp(d, c)];
+    }
+    __syncthreads();
+    double Ls[M], Bs[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) { Ls[v] = 0.0; Bs[v] = 0.0; }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int q = d == 0 ? j : i;
+      double df[M], w[M], nc[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) s += Drow[d][r] * s_buf[le][d * M + v][node_at<n1>(d, q, r)];
+        df[v] = s;
+        w[v] = 0.0;
+      }
+      if constexpr (Ph::NCD > 0) {
+#pragma unroll
+        for (int c = 0; c < Ph::NCD; ++c) {
+          double s = 0.0;
+#pragma unroll
+          for (int r = 0; r < n1; ++r) s += Drow[d][r] * s_buf[le][DIM * M + d * NCD + c][node_at<n1>(d, q, r)];
+          w[Ph::nc_comp(d, c)] = s;
+        }
+      }
+      if (d == 0) Ph::template ncprod<0>(u, w, nc, pp);
+      else Ph::template ncprod<(DIM > 1 ? 1 : 0)>(u, w, nc, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        Ls[v] += (df[v] + nc[v]) * kp.inv_dx[d];
+        Bs[v] += nc[v] * kp.inv_dx[d];
+      }
+    }
+    __syncthreads();
+    constexpr double dummy = 0.0;
+    (void)dummy;
+    const double bs = Tab::b(st);
+    if (bs != 0.0) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        Ua[v] += bs * u[v];
+        Bl[v] += bs * Bs[v];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Fa[d][v] += bs * f[d][v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) Lk[st][v] = Ls[v];
+  }
+
+  // time-averaged flux and solution to LDS
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = Fa[d][v];
+#pragma unroll
+  for (int v = 0; v < M; ++v) s_buf[le][DIM * M + v][p] = Ua[v];
+  __syncthreads();
+
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double R = Bl[v];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int q = d == 0 ? j : i;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) s += Drow[d][r] * s_buf[le][d * M + v][node_at<n1>(d, q, r)];
+        R += s * kp.inv_dx[d];
+      }
+      rvol_g[((size_t)v * kp.E + e) * P + p] = R;
+    }
+    // face traces: 2*DIM*NFP face points per element, strided over the element's threads
+    constexpr int NFT = 2 * DIM * NFP;
+    for (int t = p; t < NFT; t += P) {
+      const int d = t / (2 * NFP);
+      const int rem = t - d * 2 * NFP;
+      const int side = rem / NFP;
+      const int q = rem - side * NFP;
+      const double* V = side ? kp.VR : kp.VL;
+      const size_t nf = (size_t)kp.E * NFP;
+      const size_t fo = (size_t)e * NFP + q;
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double tf = 0.0, tu = 0.0, tn = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+          const int nd = d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r);
+          tf += V[r] * s_buf[le][d * M + v][nd];
+          tu += V[r] * s_buf[le][DIM * M + v][nd];
+          tn += V[r] * un_g[((size_t)v * kp.E + e) * P + nd];
+        }
+        const size_t o = ((size_t)(d * 2 + side) * M + v) * nf + fo;
+        kp.Ftr[o] = tf;
+        kp.Utr[o] = tu;
+        kp.untr[o] = tn;
+      }
+    }
+    // blending coefficient of the element (smoothed over face neighbours)
+    if (p == 0) {
+      double a;
+      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
+      else if (kp.blending == 0) a = 0.0;
+      else {
+        a = kp.alpha_raw[e];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[nbr_elem(kp, e, d, sd)]);
+      }
+      kp.alpha[e] = a;
+      if (d_alpha_out) d_alpha_out[e] = a;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// lower order fluxes f^{num,-}, f^{num,+}(uL, uR) of eq. combined.num.flux
+template <class Ph, int d>
+__device__ inline void low_flux(const double* uL, const double* uR, double* fm, double* fp, const PhysParams& pp) {
+  constexpr int M = Ph::M;
+  double fL[M], fR[M], avg[M], bL[M], bR[M];
+  const double sl = Ph::template sigma<d>(uL, pp), sr = Ph::template sigma<d>(uR, pp);
+  const double lam = sl >= sr ? sl : sr;
+  Ph::template flux<d>(uL, fL, pp);
+  Ph::template flux<d>(uR, fR, pp);
+#pragma unroll
+  for (int v = 0; v < M; ++v) avg[v] = 0.5 * (uL[v] + uR[v]);
+  Ph::template ncprod<d>(uL, avg, bL, pp);
+  Ph::template ncprod<d>(uR, avg, bR, pp);
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const double fc = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+    if (fm) fm[v] = fc + bL[v];
+    if (fp) fp[v] = fc + bR[v];
+  }
+}
+
+template <class Ph>
+__device__ inline bool admissible(const double* x, const PhysParams& pp) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < Ph::K; ++k) ok = ok && (Ph::constraint(k, x, pp) > 0.0);
+  return ok;
+}
+
+// one face point of direction d between element e (minus side) and en (plus side)
+template <class Ph, int N, int d>
+__device__ inline void face_point(const KParams& kp, const double* __restrict__ un_g, int e, int q, double dt,
+                                  const PhysParams& pp) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  const int en = nbr_elem(kp, e, d, 1);
+  const size_t nf = (size_t)kp.E * NFP;
+  const size_t fiL = (size_t)e * NFP + q, fiR = (size_t)en * NFP + q;
+  double a[M], b[M], FL[M], FR[M], UL[M], UR[M], sL[M], sR[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const size_t oL = ((size_t)(d * 2 + 1) * M + v) * nf + fiL;
+    const size_t oR = ((size_t)(d * 2 + 0) * M + v) * nf + fiR;
+    a[v] = kp.untr[oL]; b[v] = kp.untr[oR];
+    FL[v] = kp.Ftr[oL]; FR[v] = kp.Ftr[oR];
+    UL[v] = kp.Utr[oL]; UR[v] = kp.Utr[oR];
+    sL[v] = un_g[((size_t)v * kp.E + e) * P + node_at<n1>(d, q, N)];
+    sR[v] = un_g[((size_t)v * kp.E + en) * P + node_at<n1>(d, q, 0)];
+  }
+  // wave speed from the face values of u^n; an inadmissible face value uses
+  // its neighbouring solution point instead
+  const double sa = admissible<Ph>(a, pp) ? Ph::template sigma<d>(a, pp) : Ph::template sigma<d>(sL, pp);
+  const double sb = admissible<Ph>(b, pp) ? Ph::template sigma<d>(b, pp) : Ph::template sigma<d>(sR, pp);
+  const double lam = sa >= sb ? sa : sb;
+  double Fnum[M], Unum[M], Ba[M], Bb[M], Fm[M], Fp[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    Fnum[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (UR[v] - UL[v]);
+    Unum[v] = 0.5 * (UL[v] + UR[v]);
+  }
+  Ph::template ncprod<d>(a, Unum, Ba, pp);
+  Ph::template ncprod<d>(b, Unum, Bb, pp);
+  const double af = kp.blending == 0 ? 0.0 : 0.5 * (kp.alpha[e] + kp.alpha[en]);
+  double Theta = 1.0;
+  bool guard = false;
+  if (af == 0.0 && kp.blending != 2) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) { Fm[v] = Fnum[v] + Ba[v]; Fp[v] = Fnum[v] + Bb[v]; }
+  } else {
+    double fLOm[M], fLOp[M];
+    low_flux<Ph, d>(sL, sR, fLOm, fLOp, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      Fm[v] = (1.0 - af) * (Fnum[v] + Ba[v]) + af * fLOm[v];
+      Fp[v] = (1.0 - af) * (Fnum[v] + Bb[v]) + af * fLOp[v];
+    }
+    if (kp.blending == 2 && N >= 1) {
+      // Algorithm 1 with DIM*dt in the candidate updates of the two subcells
+      // next to the face
+      double sLi[M], sRi[M], finL[M], finR[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        sLi[v] = un_g[((size_t)v * kp.E + e) * P + node_at<n1>(d, q, N - 1)];
+        sRi[v] = un_g[((size_t)v * kp.E + en) * P + node_at<n1>(d, q, 1)];
+      }
+      low_flux<Ph, d>(sLi, sL, nullptr, finL, pp);
+      low_flux<Ph, d>(sR, sRi, finR, nullptr, pp);
+      const double cN = DIM * dt * kp.inv_wdx[d][N], c0 = DIM * dt * kp.inv_wdx[d][0];
+      double uNlo[M], u0lo[M], uN[M], u0[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        uNlo[v] = sL[v] - cN * (fLOm[v] - finL[v]);
+        u0lo[v] = sR[v] - c0 * (finR[v] - fLOp[v]);
+        uN[v] = sL[v] - cN * (Fm[v] - finL[v]);
+        u0[v] = sR[v] - c0 * (finR[v] - Fp[v]);
+      }
+#pragma unroll
+      for (int k = 0; k < Ph::K; ++k) {
+        const double PN = Ph::constraint(k, uNlo, pp), P0 = Ph::constraint(k, u0lo, pp);
+        const double th0 = theta_limit(0.1 * P0, P0, Ph::constraint(k, u0, pp), guard);
+        const double thN = theta_limit(0.1 * PN, PN, Ph::constraint(k, uN, pp), guard);
+        const double th = th0 <= thN ? th0 : thN;
+        if (th < 1.0) {
+#pragma unroll
+          for (int v = 0; v < M; ++v) {
+            Fm[v] = th * Fm[v] + (1.0 - th) * fLOm[v];
+            Fp[v] = th * Fp[v] + (1.0 - th) * fLOp[v];
+            uN[v] = sL[v] - cN * (Fm[v] - finL[v]);
+            u0[v] = sR[v] - c0 * (finR[v] - Fp[v]);
+          }
+        }
+        Theta *= th;
+      }
+    }
+  }
+  // outputs: F^± and the correction differences F^± - F_tr^± - B(u^{n,±}) U^±
+  double nca[M], ncb[M];
+  Ph::template ncprod<d>(a, UL, nca, pp);
+  Ph::template ncprod<d>(b, UR, ncb, pp);
+  const size_t fo = (size_t)d * nf + fiL;
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const size_t o = ((size_t)d * M + v) * nf + fiL;
+    kp.Fm[o] = Fm[v];
+    kp.Fp[o] = Fp[v];
+    kp.Dm[o] = Fm[v] - FL[v] - nca[v];
+    kp.Dp[o] = Fp[v] - FR[v] - ncb[v];
+  }
+  kp.theta_face[fo] = Theta;
+  kp.guard_face[fo] = guard ? 1u : 0u;
+}
+
+template <class Ph, int N>
+__global__ void __launch_bounds__(256) k_faces(const KParams kp, const double* __restrict__ un_g) {
+  constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
+  const int nf = kp.E * NFP;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= DIM * nf) return;
+  const int d = gid / nf;
+  const int fi = gid - d * nf;
+  const int e = fi / NFP, q = fi - (fi / NFP) * NFP;
+  const double dt = kp.scal[0];
+  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  if (d == 0) face_point<Ph, N, 0>(kp, un_g, e, q, dt, pp);
+  else if constexpr (DIM == 2) face_point<Ph, N, 1>(kp, un_g, e, q, dt, pp);
+}
+
+// ------------------------------------------------------------------------
+// k_update: one thread per solution point.  High order update (eq.
+// crkfr.non.cons.final), subcell FV update (eq. low.order.update), blend
+// (eq. blended.scheme) and Algorithm 2.  io holds R_vol on entry and u^{n+1}
+// on exit.
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+    k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  __shared__ double s_u[EPB][M][P];
+  __shared__ double s_red[EPB][P];
+  __shared__ uint32_t s_fl[EPB][P];
+
+  const int tid = threadIdx.x;
+  const int le = tid / P, p = tid - le * P;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = e < kp.E;
+  const int i = p % n1, j = p / n1;
+  const double dt = kp.scal[0];
+  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const size_t nf = (size_t)kp.E * NFP;
+
+  double un[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    un[v] = act ? un_g[((size_t)v * kp.E + e) * P + p] : 1.0;
+    s_u[le][v][p] = un[v];
+  }
+  int eL[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) eL[d] = act ? nbr_elem(kp, e, d, 0) : 0;
+  uint32_t fl = 0;
+  // high order update
+  double uH[M];
+  {
+    double R[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) R[v] = act ? io[((size_t)v * kp.E + e) * P + p] : 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
+      const size_t fR = (size_t)e * NFP + q, fL = (size_t)eL[d] * NFP + q;
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        const double dm = act ? kp.Dm[((size_t)d * M + v) * nf + fR] : 0.0;
+        const double dp = act ? kp.Dp[((size_t)d * M + v) * nf + fL] : 0.0;
+        R[v] += (dm * kp.gR[ii] + dp * kp.gL[ii]) * kp.inv_dx[d];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) uH[v] = un[v] - dt * R[v];
+  }
+  __syncthreads();
+  double us[M];
+  if (kp.blending == 0) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) us[v] = uH[v];
+  } else {
+    // lower order subcell update
+    double RL[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) RL[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
+      double right[M], left[M], nb[M];
+      if (ii < N) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) nb[v] = s_u[le][v][node_at<n1>(d, q, ii < N ? ii + 1 : ii)];
+        if (d == 0) low_flux<Ph, 0>(un, nb, right, nullptr, pp);
+        else low_flux<Ph, (DIM > 1 ? 1 : 0)>(un, nb, right, nullptr, pp);
+      } else {
+        const size_t fR = (size_t)e * NFP + q;
+#pragma unroll
+        for (int v = 0; v < M; ++v) right[v] = act ? kp.Fm[((size_t)d * M + v) * nf + fR] : 0.0;
+      }
+      if (ii > 0) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) nb[v] = s_u[le][v][node_at<n1>(d, q, ii > 0 ? ii - 1 : ii)];
+        if (d == 0) low_flux<Ph, 0>(nb, un, nullptr, left, pp);
+        else low_flux<Ph, (DIM > 1 ? 1 : 0)>(nb, un, nullptr, left, pp);
+      } else {
+        const size_t fL = (size_t)eL[d] * NFP + q;
+#pragma unroll
+        for (int v = 0; v < M; ++v) left[v] = act ? kp.Fp[((size_t)d * M + v) * nf + fL] : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < M; ++v) RL[v] += (right[v] - left[v]) * kp.inv_wdx[d][ii];
+    }
+    double uL[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) uL[v] = un[v] - dt * RL[v];
+    const double al = act ? kp.alpha[e] : 0.0;
+#pragma unroll
+    for (int v = 0; v < M; ++v) us[v] = (1.0 - al) * uH[v] + al * uL[v];
+    // Algorithm 2
+    double Theta = 1.0;
+#pragma unroll
+    for (int k = 0; k < Ph::K; ++k) {
+      const double Pa = Ph::constraint(k, uL, pp);
+      s_red[le][p] = Pa;
+      __syncthreads();
+      double Pmin = s_red[le][0];
+#pragma unroll
+      for (int r = 1; r < P; ++r) Pmin = fmin(Pmin, s_red[le][r]);
+      __syncthreads();
+      if (Pmin <= 0.0) fl |= 2u;
+      if (kp.blending == 2) {
+        bool guard = false;
+        const double th_p = theta_limit(0.1 * Pmin, Pa, Ph::constraint(k, us, pp), guard);
+        s_red[le][p] = th_p;
+        __syncthreads();
+        double th = s_red[le][0];
+#pragma unroll
+        for (int r = 1; r < P; ++r) th = fmin(th, s_red[le][r]);
+        __syncthreads();
+        if (th < 1.0) {
+#pragma unroll
+          for (int v = 0; v < M; ++v) us[v] = th * us[v] + (1.0 - th) * uL[v];
+        }
+        Theta *= th;
+      }
+    }
+    if (Theta < 1.0) fl |= 1u;
+    if (act && p == 0) kp.theta_elem[e] = Theta;
+  }
+  bool finite = true;
+#pragma unroll
+  for (int v = 0; v < M; ++v) finite = finite && isfinite(us[v]);
+  if (!finite) fl |= 8u;
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) io[((size_t)v * kp.E + e) * P + p] = us[v];
+  }
+  s_fl[le][p] = fl;
+  __syncthreads();
+  if (act && p == 0) {
+    uint32_t f = 0;
+#pragma unroll
+    for (int r = 0; r < P; ++r) f |= s_fl[le][r];
+    // Algorithm 1 activity on the element's faces
+    if (kp.blending == 2) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int q = 0; q < NFP; ++q) {
+          const size_t fu = (size_t)d * nf + (size_t)e * NFP + q;
+          const size_t fd = (size_t)d * nf + (size_t)eL[d] * NFP + q;
+          if (kp.theta_face[fu] < 1.0 || kp.theta_face[fd] < 1.0) f |= 4u;
+          if (kp.guard_face[fu] || kp.guard_face[fd]) f |= 16u;
+        }
+    }
+    if (d_flags) d_flags[e] = f;
+    if (f & 10u) atomicOr(kp.flag_or, f);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_residual(const double* __restrict__ u, double* __restrict__ R, size_t n,
+                                                  const double* __restrict__ scal) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) R[k] = (u[k] - R[k]) / scal[0];
+}
+
+}  // namespace lwfr

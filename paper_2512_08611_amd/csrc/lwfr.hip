@@ -1,0 +1,325 @@
+// C ABI of the time step (declarations and contracts in include/lwfr.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/lwfr.h"
+#include "kernels.hpp"
+
+using namespace lwfr;
+
+namespace {
+
+thread_local std::string g_err;
+
+lwfr_status fail(lwfr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct lwfr_ctx {
+  lwfr_config cfg;
+  int M = 0, DIM = 0, K = 0, N = 0, n1 = 0, P = 0, NFP = 0, E = 0;
+  int nblk_pre = 0;
+  RefData rd;
+  double cfl = 0.0;
+  KParams kp;
+  // workspace carving (byte offsets)
+  size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr, off_untr,
+      off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_flag, ws_bytes;
+  void* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+};
+
+namespace {
+
+struct EqInfo {
+  int M, DIM, K;
+};
+
+bool eq_info(int eq, EqInfo& info) {
+  switch (eq) {
+    case LWFR_EQ_SW1D: info = {SW1D::M, SW1D::DIM, SW1D::K}; return true;
+    case LWFR_EQ_SW2D: info = {SW2D::M, SW2D::DIM, SW2D::K}; return true;
+    case LWFR_EQ_GLMMHD2D: info = {MHD2D::M, MHD2D::DIM, MHD2D::K}; return true;
+    case LWFR_EQ_LINADV1D: info = {LinAdv1D::M, LinAdv1D::DIM, LinAdv1D::K}; return true;
+    case LWFR_EQ_VARADV1D: info = {VarAdv1D::M, VarAdv1D::DIM, VarAdv1D::K}; return true;
+  }
+  return false;
+}
+
+template <int N>
+constexpr int epb_for(int DIM) {
+  return 256 / ipow(N + 1, DIM);
+}
+
+#define LWFR_CHECK_LAUNCH(name)                                                   \
+  do {                                                                            \
+    hipError_t err_ = hipGetLastError();                                          \
+    if (err_ != hipSuccess)                                                       \
+      return fail(LWFR_E_HIP, std::string(name) + ": " + hipGetErrorString(err_)); \
+  } while (0)
+
+// The launch sequence of one step for system Ph at degree N.
+template <class Ph, int N>
+lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
+                        double* d_alpha, uint32_t* d_flags) {
+  constexpr int DIM = Ph::DIM, P = ipow(N + 1, DIM), NFP = DIM == 1 ? 1 : N + 1;
+  constexpr int EPB = epb_for<N>(DIM);
+  const int E = c->E;
+  hipStream_t s = c->stream;
+  const bool has_ch = std::is_same<Ph, MHD2D>::value;
+  hipLaunchKernelGGL((k_pre<Ph, N>), dim3(c->nblk_pre), dim3(256), 0, s, kp, u_in);
+  LWFR_CHECK_LAUNCH("k_pre");
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
+  LWFR_CHECK_LAUNCH("k_dt");
+  if (has_ch) {
+    hipLaunchKernelGGL(k_ch, dim3(c->nblk_pre), dim3(256), 0, s, kp);
+    LWFR_CHECK_LAUNCH("k_ch");
+    hipLaunchKernelGGL(k_ch_fin, dim3(1), dim3(256), 0, s, kp, d_dt_ch);
+    LWFR_CHECK_LAUNCH("k_ch_fin");
+  }
+  const int nblk_el = (E + EPB - 1) / EPB;
+  hipLaunchKernelGGL((k_stages<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out, d_alpha);
+  LWFR_CHECK_LAUNCH("k_stages");
+  const int nfp_total = DIM * E * NFP;
+  hipLaunchKernelGGL((k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
+  LWFR_CHECK_LAUNCH("k_faces");
+  hipLaunchKernelGGL((k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out, d_flags);
+  LWFR_CHECK_LAUNCH("k_update");
+  return LWFR_OK;
+}
+
+template <class Ph>
+lwfr_status launch_step_n(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
+                          double* d_alpha, uint32_t* d_flags) {
+  switch (c->N) {
+    case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+  }
+  return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
+}
+
+lwfr_status dispatch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
+                          double* d_alpha, uint32_t* d_flags) {
+  switch (c->cfg.equation) {
+    case LWFR_EQ_SW1D: return launch_step_n<SW1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case LWFR_EQ_SW2D: return launch_step_n<SW2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case LWFR_EQ_GLMMHD2D: return launch_step_n<MHD2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case LWFR_EQ_LINADV1D: return launch_step_n<LinAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case LWFR_EQ_VARADV1D: return launch_step_n<VarAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+  }
+  return fail(LWFR_E_UNSUPPORTED, "unknown equation");
+}
+
+bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lwfr_last_error(void) { return g_err.c_str(); }
+
+lwfr_status lwfr_cfl_number(int32_t degree, double* cfl) {
+  if (!cfl) return fail(LWFR_E_INVALID_ARG, "cfl is null");
+  if (degree < 1 || degree > 4) return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
+  *cfl = fourier_cfl(degree);
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
+  if (!cfg || !out) return fail(LWFR_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (cfg->abi_version != LWFR_ABI_VERSION) return fail(LWFR_E_INVALID_ARG, "abi_version mismatch");
+  EqInfo info;
+  if (!eq_info(cfg->equation, info)) return fail(LWFR_E_INVALID_ARG, "unknown equation");
+  if (cfg->degree < 1 || cfg->degree > 4) return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
+  const int ny = info.DIM == 2 ? cfg->nelem[1] : 1;
+  if (cfg->nelem[0] < 1 || ny < 1) return fail(LWFR_E_INVALID_ARG, "nelem must be positive");
+  if ((long long)cfg->nelem[0] * ny > (1LL << 26)) return fail(LWFR_E_INVALID_ARG, "too many elements");
+  for (int d = 0; d < info.DIM; ++d)
+    if (!(cfg->hi[d] > cfg->lo[d]) || !std::isfinite(cfg->hi[d] - cfg->lo[d]))
+      return fail(LWFR_E_INVALID_ARG, "domain box must have hi > lo");
+  if (cfg->blending < 0 || cfg->blending > 2) return fail(LWFR_E_INVALID_ARG, "blending must be 0, 1 or 2");
+  if (!(cfg->cfl_safety > 0.0)) return fail(LWFR_E_INVALID_ARG, "cfl_safety must be positive");
+  if (!(cfg->alpha_max >= 0.0 && cfg->alpha_max <= 1.0)) return fail(LWFR_E_INVALID_ARG, "alpha_max in [0,1]");
+  if (!(cfg->alpha_min >= 0.0 && cfg->alpha_min < 0.5)) return fail(LWFR_E_INVALID_ARG, "alpha_min in [0,0.5)");
+  if (cfg->alpha_force > 1.0) return fail(LWFR_E_INVALID_ARG, "alpha_force must be <= 1");
+  if (cfg->equation == LWFR_EQ_GLMMHD2D && !(cfg->gamma > 1.0)) return fail(LWFR_E_INVALID_ARG, "gamma > 1");
+  if ((cfg->equation == LWFR_EQ_SW1D || cfg->equation == LWFR_EQ_SW2D) && !(cfg->gravity > 0.0))
+    return fail(LWFR_E_INVALID_ARG, "gravity > 0");
+
+  lwfr_ctx* c = new lwfr_ctx();
+  c->cfg = *cfg;
+  c->M = info.M; c->DIM = info.DIM; c->K = info.K;
+  c->N = cfg->degree; c->n1 = c->N + 1;
+  c->P = info.DIM == 1 ? c->n1 : c->n1 * c->n1;
+  c->NFP = info.DIM == 1 ? 1 : c->n1;
+  c->E = cfg->nelem[0] * ny;
+  c->nblk_pre = (c->E + 255) / 256;
+  c->rd = make_refdata(c->N);
+  c->cfl = cfg->cfl_number > 0.0 ? cfg->cfl_number : fourier_cfl(c->N);
+
+  KParams& kp = c->kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.nx = cfg->nelem[0]; kp.ny = ny; kp.E = c->E; kp.nblk_pre = c->nblk_pre;
+  for (int d = 0; d < 2; ++d) {
+    kp.dx[d] = d < info.DIM ? (cfg->hi[d] - cfg->lo[d]) / (d == 0 ? cfg->nelem[0] : ny) : 1.0;
+    kp.inv_dx[d] = 1.0 / kp.dx[d];
+  }
+  for (int a = 0; a < c->n1; ++a) {
+    for (int b = 0; b < c->n1; ++b) { kp.D[a][b] = c->rd.D[a][b]; kp.Leg[a][b] = c->rd.Leg[a][b]; }
+    kp.VL[a] = c->rd.VL[a]; kp.VR[a] = c->rd.VR[a]; kp.w[a] = c->rd.w[a];
+    kp.gR[a] = c->rd.gR[a]; kp.gL[a] = c->rd.gL[a];
+    for (int d = 0; d < 2; ++d) kp.inv_wdx[d][a] = 1.0 / (c->rd.w[a] * kp.dx[d]);
+  }
+  kp.g = cfg->gravity; kp.gamma = cfg->gamma;
+  kp.blending = cfg->blending;
+  kp.alpha_max = cfg->alpha_max; kp.alpha_min = cfg->alpha_min; kp.alpha_force = cfg->alpha_force;
+  kp.ind_T = 0.5 * std::pow(10.0, -1.8 * std::pow(c->N + 1.0, 0.25));
+  kp.ind_s = std::log(9999.0);
+  kp.cs_cfl = cfg->cfl_safety * c->cfl;
+
+  // workspace carving
+  const size_t nfpt = (size_t)c->DIM * c->E * c->NFP;  // face points over all directions
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  c->off_scal = take(8 * sizeof(double));
+  c->off_part = take((size_t)c->nblk_pre * sizeof(double));
+  c->off_part2 = take((size_t)c->nblk_pre * sizeof(double));
+  c->off_speeds = take((size_t)c->E * 2 * c->DIM * sizeof(double));
+  c->off_araw = take((size_t)c->E * sizeof(double));
+  c->off_alpha = take((size_t)c->E * sizeof(double));
+  c->off_thel = take((size_t)c->E * sizeof(double));
+  c->off_Ftr = take(nfpt * 2 * c->M * sizeof(double));
+  c->off_Utr = take(nfpt * 2 * c->M * sizeof(double));
+  c->off_untr = take(nfpt * 2 * c->M * sizeof(double));
+  c->off_Fm = take(nfpt * c->M * sizeof(double));
+  c->off_Fp = take(nfpt * c->M * sizeof(double));
+  c->off_Dm = take(nfpt * c->M * sizeof(double));
+  c->off_Dp = take(nfpt * c->M * sizeof(double));
+  c->off_thf = take(nfpt * sizeof(double));
+  c->off_guard = take(nfpt * sizeof(uint32_t));
+  c->off_flag = take(sizeof(uint32_t));
+  c->ws_bytes = off;
+  *out = c;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_workspace_bytes(const lwfr_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(LWFR_E_INVALID_ARG, "null argument");
+  *bytes = c->ws_bytes;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_state_size(const lwfr_ctx* c, size_t* n) {
+  if (!c || !n) return fail(LWFR_E_INVALID_ARG, "null argument");
+  *n = (size_t)c->M * c->E * c->P;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_reference_nodes(const lwfr_ctx* c, double* xi, double* w) {
+  if (!c || !xi || !w) return fail(LWFR_E_INVALID_ARG, "null argument");
+  for (int p = 0; p < c->n1; ++p) { xi[p] = c->rd.xi[p]; w[p] = c->rd.w[p]; }
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_bind(lwfr_ctx* c, void* d_ws, size_t bytes, void* stream) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!d_ws) return fail(LWFR_E_WORKSPACE, "workspace is null");
+  if (bytes < c->ws_bytes) return fail(LWFR_E_WORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return fail(LWFR_E_WORKSPACE, "workspace not 256-byte aligned");
+  c->ws = d_ws;
+  c->stream = static_cast<hipStream_t>(stream);
+  char* b = static_cast<char*>(d_ws);
+  KParams& kp = c->kp;
+  kp.scal = reinterpret_cast<double*>(b + c->off_scal);
+  kp.part = reinterpret_cast<double*>(b + c->off_part);
+  kp.part2 = reinterpret_cast<double*>(b + c->off_part2);
+  kp.speeds = reinterpret_cast<double*>(b + c->off_speeds);
+  kp.alpha_raw = reinterpret_cast<double*>(b + c->off_araw);
+  kp.alpha = reinterpret_cast<double*>(b + c->off_alpha);
+  kp.theta_elem = reinterpret_cast<double*>(b + c->off_thel);
+  kp.Ftr = reinterpret_cast<double*>(b + c->off_Ftr);
+  kp.Utr = reinterpret_cast<double*>(b + c->off_Utr);
+  kp.untr = reinterpret_cast<double*>(b + c->off_untr);
+  kp.Fm = reinterpret_cast<double*>(b + c->off_Fm);
+  kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
+  kp.Dm = reinterpret_cast<double*>(b + c->off_Dm);
+  kp.Dp = reinterpret_cast<double*>(b + c->off_Dp);
+  kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
+  kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
+  kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
+  hipError_t err = hipMemsetAsync(kp.flag_or, 0, sizeof(uint32_t), c->stream);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(err));
+  c->bound = true;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_step(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
+                      double* d_alpha, uint32_t* d_flags) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (!d_u_in || !d_u_out) return fail(LWFR_E_INVALID_ARG, "null state pointer");
+  const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
+  if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
+  if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
+  KParams kp = c->kp;
+  kp.dt_in = dt > 0.0 ? dt : 0.0;
+  return dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, d_alpha, d_flags);
+}
+
+lwfr_status lwfr_residual(lwfr_ctx* c, const double* d_u, double dt, int32_t mode, double* d_R) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (!d_u || !d_R) return fail(LWFR_E_INVALID_ARG, "null state pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt must be positive and finite");
+  if (mode < 0 || mode > 2) return fail(LWFR_E_INVALID_ARG, "mode must be 0, 1 or 2");
+  const size_t n = (size_t)c->M * c->E * c->P;
+  if (ranges_overlap(d_u, d_R, n * sizeof(double))) return fail(LWFR_E_INVALID_ARG, "R aliases u");
+  KParams kp = c->kp;
+  kp.dt_in = dt;
+  if (mode == 0) { kp.blending = 0; kp.alpha_force = -1.0; }
+  if (mode == 1) { kp.blending = 1; kp.alpha_force = 1.0; }
+  lwfr_status st = dispatch_step(c, kp, d_u, d_R, nullptr, nullptr, nullptr);
+  if (st != LWFR_OK) return st;
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d_u, d_R, n,
+                     (const double*)kp.scal);
+  LWFR_CHECK_LAUNCH("k_residual");
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_query(lwfr_ctx* c, uint32_t* flags_or) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  uint32_t h = 0;
+  hipError_t err = hipMemcpyAsync(&h, c->kp.flag_or, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+  if (err == hipSuccess) err = hipMemsetAsync(c->kp.flag_or, 0, sizeof(uint32_t), c->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("lwfr_query: ") + hipGetErrorString(err));
+  if (flags_or) *flags_or = h;
+  if (h & LWFR_FLAG_NONFINITE) return fail(LWFR_E_NONFINITE, "a step produced a non-finite value");
+  if (h & LWFR_FLAG_LOW_INADM) return fail(LWFR_E_INADMISSIBLE, "a lower order update was not admissible");
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_destroy(lwfr_ctx* c) {
+  delete c;
+  return LWFR_OK;
+}
+
+}  // extern "C"

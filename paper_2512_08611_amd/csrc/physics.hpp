@@ -1,0 +1,192 @@
+// Device equation systems for u_t + sum_d [ f_d(u)_{x_d} + B_d(u) u_{x_d} ] = 0
+// (paper §3 eq. flux.and.non.cons; §5 2-D form above eq. time.step.2d).
+//
+// Every system is a struct with compile-time sizes and static device functions:
+//   M, DIM, K         variables, space dimensions, admissibility constraints
+//   NCD, nc_comp(d,i) the components of u_{x_d} that B_d(u) u_{x_d} reads
+//   flux<d>(u, f)     f_d(u)
+//   ncprod<d>(u,w,o)  B_d(u) w   (only the nc_comp components of w are read)
+//   sigma<d>(u)       spectral radius of f_d' + B_d (eq. combined.wave.speed)
+//   constraint(k,u)   P_k(u) of the admissible set (eq. uad.form)
+//   indicator(u)      variable seen by the smoothness indicator
+//   speeds<d>(u,|v|,c) ideal wave speeds used for the time step
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lwfr {
+
+struct PhysParams {
+  double g;       // gravity
+  double gamma;   // ratio of specific heats
+  double ch;      // GLM cleaning speed (device value for the current step)
+};
+
+// Shallow water with the bed b carried as a variable: B u_x = (0, g h b_x, 0).
+struct SW1D {
+  static constexpr int M = 3, DIM = 1, K = 1, NCD = 1;
+  __host__ __device__ static constexpr int nc_comp(int, int) { return 2; }
+  template <int d>
+  __device__ static void flux(const double* u, double* f, const PhysParams& pp) {
+    const double v = u[1] / u[0];
+    f[0] = u[1];
+    f[1] = u[1] * v + 0.5 * pp.g * u[0] * u[0];
+    f[2] = 0.0;
+  }
+  template <int d>
+  __device__ static void ncprod(const double* u, const double* w, double* o, const PhysParams& pp) {
+    o[0] = 0.0; o[1] = pp.g * u[0] * w[2]; o[2] = 0.0;
+  }
+  template <int d>
+  __device__ static double sigma(const double* u, const PhysParams& pp) {
+    return fabs(u[1] / u[0]) + sqrt(pp.g * u[0]);
+  }
+  __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
+  __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
+  template <int d>
+  __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
+    av = fabs(u[1] / u[0]); c = sqrt(pp.g * u[0]);
+  }
+};
+
+struct SW2D {
+  static constexpr int M = 4, DIM = 2, K = 1, NCD = 1;
+  __host__ __device__ static constexpr int nc_comp(int, int) { return 3; }
+  template <int d>
+  __device__ static void flux(const double* u, double* f, const PhysParams& pp) {
+    const double hu = u[1 + d];
+    const double vel = hu / u[0];
+    f[0] = hu;
+    f[1] = u[1] * vel;
+    f[2] = u[2] * vel;
+    f[1 + d] += 0.5 * pp.g * u[0] * u[0];
+    f[3] = 0.0;
+  }
+  template <int d>
+  __device__ static void ncprod(const double* u, const double* w, double* o, const PhysParams& pp) {
+    o[0] = 0.0; o[1] = 0.0; o[2] = 0.0; o[3] = 0.0;
+    o[1 + d] = pp.g * u[0] * w[3];
+  }
+  template <int d>
+  __device__ static double sigma(const double* u, const PhysParams& pp) {
+    return fabs(u[1 + d] / u[0]) + sqrt(pp.g * u[0]);
+  }
+  __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
+  __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
+  template <int d>
+  __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
+    av = fabs(u[1 + d] / u[0]); c = sqrt(pp.g * u[0]);
+  }
+};
+
+// Ideal GLM-MHD with the Godunov-Powell and GLM non-conservative terms (§5.5
+// eq. glm.mhd) in the complete form of the source the paper cites: the energy
+// flux is v_d(rho|v|^2/2 + gamma p/(gamma-1) + |B|^2) - B_d (v.B) + c_h psi B_d,
+// the normal induction flux is c_h psi and the psi flux is c_h B_d.
+// u = (rho, m1, m2, m3, E, B1, B2, B3, psi).
+struct MHD2D {
+  static constexpr int M = 9, DIM = 2, K = 2, NCD = 2;
+  __host__ __device__ static constexpr int nc_comp(int d, int i) { return i == 0 ? 5 + d : 8; }
+  __device__ static double pressure(const double* u, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double mm = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    const double bb = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+    return (pp.gamma - 1.0) * (u[4] - 0.5 * mm * ir - 0.5 * bb - 0.5 * u[8] * u[8]);
+  }
+  template <int d>
+  __device__ static void flux(const double* u, double* f, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+    const double B1 = u[5], B2 = u[6], B3 = u[7], psi = u[8];
+    const double bb = B1 * B1 + B2 * B2 + B3 * B3;
+    const double vv = v1 * v1 + v2 * v2 + v3 * v3;
+    const double p = (pp.gamma - 1.0) * (u[4] - 0.5 * u[0] * vv - 0.5 * bb - 0.5 * psi * psi);
+    const double vB = v1 * B1 + v2 * B2 + v3 * B3;
+    const double vd = d == 0 ? v1 : v2;
+    const double Bd = d == 0 ? B1 : B2;
+    const double md = u[1 + d];
+    f[0] = md;
+    f[1] = md * v1 - Bd * B1;
+    f[2] = md * v2 - Bd * B2;
+    f[3] = md * v3 - Bd * B3;
+    f[1 + d] += p + 0.5 * bb;
+    f[4] = vd * (0.5 * u[0] * vv + pp.gamma / (pp.gamma - 1.0) * p + bb) - Bd * vB + pp.ch * psi * Bd;
+    f[5] = vd * B1 - Bd * v1;
+    f[6] = vd * B2 - Bd * v2;
+    f[7] = vd * B3 - Bd * v3;
+    f[5 + d] = pp.ch * psi;
+    f[8] = pp.ch * Bd;
+  }
+  // B_d(u) w = w_{B_d} (0, B, v.B, v, 0) + w_psi (0, 0, 0, 0, v_d psi, 0, 0, 0, v_d)
+  template <int d>
+  __device__ static void ncprod(const double* u, const double* w, double* o, const PhysParams&) {
+    const double ir = 1.0 / u[0];
+    const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+    const double vd = d == 0 ? v1 : v2;
+    const double dB = w[5 + d], dpsi = w[8];
+    const double vB = v1 * u[5] + v2 * u[6] + v3 * u[7];
+    o[0] = 0.0;
+    o[1] = dB * u[5];
+    o[2] = dB * u[6];
+    o[3] = dB * u[7];
+    o[4] = dB * vB + dpsi * vd * u[8];
+    o[5] = dB * v1;
+    o[6] = dB * v2;
+    o[7] = dB * v3;
+    o[8] = dpsi * vd;
+  }
+  template <int d>
+  __device__ static double cfast(const double* u, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double p = pressure(u, pp);
+    const double a2 = pp.gamma * p * ir;
+    const double b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+    const double bd2 = u[5 + d] * u[5 + d] * ir;
+    const double s = a2 + b2;
+    return sqrt(0.5 * (s + sqrt(s * s - 4.0 * a2 * bd2)));
+  }
+  // waves v_d, v_d ± c_a, v_d ± c_s, v_d ± c_f and the GLM pair v_d ± c_h
+  template <int d>
+  __device__ static double sigma(const double* u, const PhysParams& pp) {
+    const double cf = cfast<d>(u, pp);
+    return fabs(u[1 + d] / u[0]) + (cf >= pp.ch ? cf : pp.ch);
+  }
+  __device__ static double constraint(int k, const double* u, const PhysParams& pp) {
+    return k == 0 ? u[0] : pressure(u, pp);
+  }
+  __device__ static double indicator(const double* u, const PhysParams& pp) { return u[0] * pressure(u, pp); }
+  template <int d>
+  __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
+    av = fabs(u[1 + d] / u[0]); c = cfast<d>(u, pp);
+  }
+};
+
+// Linear advection u_t + u_x = 0.
+struct LinAdv1D {
+  static constexpr int M = 1, DIM = 1, K = 0, NCD = 0;
+  __host__ __device__ static constexpr int nc_comp(int, int) { return 0; }
+  template <int d> __device__ static void flux(const double* u, double* f, const PhysParams&) { f[0] = u[0]; }
+  template <int d> __device__ static void ncprod(const double*, const double*, double* o, const PhysParams&) { o[0] = 0.0; }
+  template <int d> __device__ static double sigma(const double*, const PhysParams&) { return 1.0; }
+  __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
+  __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
+  template <int d> __device__ static void speeds(const double*, double& av, double& c, const PhysParams&) { av = 0.0; c = 1.0; }
+};
+
+// Variable-coefficient advection as a non-conservative system: u = (v, a),
+// f = 0, B(u) w = (u_2 w_1, 0) (§5.1 eq. var.coeff.adv.non.cons).
+struct VarAdv1D {
+  static constexpr int M = 2, DIM = 1, K = 0, NCD = 1;
+  __host__ __device__ static constexpr int nc_comp(int, int) { return 0; }
+  template <int d> __device__ static void flux(const double*, double* f, const PhysParams&) { f[0] = 0.0; f[1] = 0.0; }
+  template <int d> __device__ static void ncprod(const double* u, const double* w, double* o, const PhysParams&) {
+    o[0] = u[1] * w[0]; o[1] = 0.0;
+  }
+  template <int d> __device__ static double sigma(const double* u, const PhysParams&) { return fabs(u[1]); }
+  __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
+  __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
+  template <int d> __device__ static void speeds(const double* u, double& av, double& c, const PhysParams&) {
+    av = 0.0; c = fabs(u[1]);
+  }
+};
+
+}  // namespace lwfr

@@ -1,0 +1,211 @@
+"""Python binding of the C ABI in include/lwfr.h (argument marshalling only).
+
+Every function mirrors the C entry point of the same name.  Device buffers are
+torch tensors on a ROCm device; torch provides memory and the HIP stream, all
+arithmetic of the step runs in the HIP kernels of liblwfr.so.  The module
+raises at import of the library if it is not built: there is no fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "liblwfr.so")
+ABI_VERSION = 1
+
+LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
+LWFR_E_INADMISSIBLE, LWFR_E_NONFINITE, LWFR_E_WORKSPACE, LWFR_E_STATE = 4, 5, 6, 7
+LWFR_EQ_SW1D, LWFR_EQ_SW2D, LWFR_EQ_GLMMHD2D, LWFR_EQ_LINADV1D, LWFR_EQ_VARADV1D = 1, 2, 3, 4, 5
+LWFR_FLAG_ALG2, LWFR_FLAG_LOW_INADM, LWFR_FLAG_ALG1, LWFR_FLAG_NONFINITE, LWFR_FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
+
+NVARS = {1: 3, 2: 4, 3: 9, 4: 1, 5: 2}
+DIMS = {1: 1, 2: 2, 3: 2, 4: 1, 5: 1}
+
+
+class LwfrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lwfr status {status}: {msg}")
+        self.status = status
+
+
+class lwfr_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("equation", ctypes.c_int32),
+        ("degree", ctypes.c_int32),
+        ("nelem", ctypes.c_int32 * 2),
+        ("lo", ctypes.c_double * 2),
+        ("hi", ctypes.c_double * 2),
+        ("gamma", ctypes.c_double),
+        ("gravity", ctypes.c_double),
+        ("cfl_safety", ctypes.c_double),
+        ("cfl_number", ctypes.c_double),
+        ("blending", ctypes.c_int32),
+        ("alpha_max", ctypes.c_double),
+        ("alpha_min", ctypes.c_double),
+        ("alpha_force", ctypes.c_double),
+    ]
+
+
+_lib = None
+_SIGS = {
+    "lwfr_init": [ctypes.POINTER(lwfr_config), ctypes.POINTER(ctypes.c_void_p)],
+    "lwfr_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lwfr_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lwfr_reference_nodes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "lwfr_cfl_number": [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "lwfr_bind": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "lwfr_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p],
+    "lwfr_residual": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p],
+    "lwfr_query": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],
+    "lwfr_destroy": [ctypes.c_void_p],
+}
+
+
+def lib():
+    """The loaded liblwfr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIBPATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.lwfr_last_error.argtypes = []
+        L.lwfr_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def lwfr_last_error():
+    return lib().lwfr_last_error().decode()
+
+
+def _check(status):
+    if status != LWFR_OK:
+        raise LwfrError(status, lwfr_last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81,
+                cfl_safety=0.9, cfl_number=0.0, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0):
+    c = lwfr_config()
+    c.abi_version = ABI_VERSION
+    c.equation, c.degree = equation, degree
+    nel = (nelem, 1) if isinstance(nelem, int) else tuple(nelem)
+    c.nelem[0], c.nelem[1] = nel[0], (nel[1] if len(nel) > 1 else 1)
+    c.lo[0], c.lo[1] = lo
+    c.hi[0], c.hi[1] = hi
+    c.gamma, c.gravity, c.cfl_safety, c.cfl_number = gamma, gravity, cfl_safety, cfl_number
+    c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
+    return c
+
+
+def lwfr_init(cfg):
+    ctx = ctypes.c_void_p()
+    _check(lib().lwfr_init(ctypes.byref(cfg), ctypes.byref(ctx)))
+    return ctx
+
+
+def lwfr_workspace_bytes(ctx):
+    n = ctypes.c_size_t()
+    _check(lib().lwfr_workspace_bytes(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def lwfr_state_size(ctx):
+    n = ctypes.c_size_t()
+    _check(lib().lwfr_state_size(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def lwfr_reference_nodes(ctx, n1):
+    xi = (ctypes.c_double * n1)()
+    w = (ctypes.c_double * n1)()
+    _check(lib().lwfr_reference_nodes(ctx, xi, w))
+    return list(xi), list(w)
+
+
+def lwfr_cfl_number(degree):
+    c = ctypes.c_double()
+    _check(lib().lwfr_cfl_number(degree, ctypes.byref(c)))
+    return c.value
+
+
+def lwfr_bind(ctx, workspace, stream=None):
+    """workspace: a device tensor of at least lwfr_workspace_bytes(ctx) bytes, 256-byte aligned."""
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(workspace.device)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().lwfr_bind(ctx, ctypes.c_void_p(workspace.data_ptr()), nbytes, ctypes.c_void_p(stream.cuda_stream)))
+
+
+def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
+    _check(lib().lwfr_step(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(alpha), _ptr(flags)))
+
+
+def lwfr_residual(ctx, u, dt, mode, R):
+    _check(lib().lwfr_residual(ctx, _ptr(u), float(dt), int(mode), _ptr(R)))
+
+
+def lwfr_query(ctx):
+    """(status, flags_or) without raising."""
+    f = ctypes.c_uint32()
+    st = lib().lwfr_query(ctx, ctypes.byref(f))
+    return st, f.value
+
+
+def lwfr_destroy(ctx):
+    _check(lib().lwfr_destroy(ctx))
+
+
+class Stepper:
+    """Owns a context, a workspace tensor and the stream binding for one configuration."""
+
+    def __init__(self, cfg, device="cuda:0", stream=None):
+        import torch
+
+        self.cfg = cfg
+        self.ctx = lwfr_init(cfg)
+        self.device = torch.device(device)
+        self.nbytes = lwfr_workspace_bytes(self.ctx)
+        # 256-byte aligned workspace from the caching allocator
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off: off + self.nbytes]
+        self.stream = stream
+        lwfr_bind(self.ctx, self.ws, stream)
+        n1 = cfg.degree + 1
+        self.dim = DIMS[cfg.equation]
+        self.nvars = NVARS[cfg.equation]
+        self.nelem = cfg.nelem[0] * (cfg.nelem[1] if self.dim == 2 else 1)
+        self.npts = n1 ** self.dim
+        self.shape = (self.nvars, self.nelem, self.npts)
+        self.xi, self.w = lwfr_reference_nodes(self.ctx, n1)
+
+    def step(self, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
+        lwfr_step(self.ctx, u_in, u_out, dt, dt_ch, alpha, flags)
+
+    def residual(self, u, dt, mode, R):
+        lwfr_residual(self.ctx, u, dt, mode, R)
+
+    def query(self):
+        return lwfr_query(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            lwfr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

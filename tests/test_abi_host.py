@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+function include/lwfr.h declares, validates configurations, and its host-built
+reference data and Fourier CFL numbers agree with the oracle's independent ones."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_08611_amd import lwfr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lwfr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lwfr_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = lwfr.lib()
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_init_validation():
+    good = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (4, 4))
+    ctx = lwfr.lwfr_init(good)
+    assert lwfr.lwfr_workspace_bytes(ctx) > 0
+    assert lwfr.lwfr_state_size(ctx) == 9 * 16 * 16
+    lwfr.lwfr_destroy(ctx)
+    bad = [
+        dict(degree=0), dict(degree=5), dict(nelem=(0, 4)), dict(blending=3), dict(alpha_max=1.5),
+        dict(cfl_safety=0.0), dict(hi=(0.0, 1.0)), dict(gamma=1.0), dict(alpha_force=2.0),
+    ]
+    for kw in bad:
+        args = dict(equation=lwfr.LWFR_EQ_GLMMHD2D, degree=3, nelem=(4, 4))
+        args.update(kw)
+        cfg = lwfr.make_config(**args)
+        with pytest.raises(lwfr.LwfrError) as ei:
+            lwfr.lwfr_init(cfg)
+        assert ei.value.status in (lwfr.LWFR_E_INVALID_ARG, lwfr.LWFR_E_UNSUPPORTED)
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 10)
+    cfg.abi_version = 99
+    with pytest.raises(lwfr.LwfrError):
+        lwfr.lwfr_init(cfg)
+    cfg = lwfr.make_config(7, 3, 10)
+    with pytest.raises(lwfr.LwfrError):
+        lwfr.lwfr_init(cfg)
+
+
+def test_step_before_bind_is_a_state_error():
+    ctx = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 10))
+    st = lwfr.lib().lwfr_step(ctx, ctypes.c_void_p(256), ctypes.c_void_p(4096), 0.0, None, None, None)
+    assert st == lwfr.LWFR_E_STATE
+    assert "bind" in lwfr.lwfr_last_error()
+    st = lwfr.lib().lwfr_bind(ctx, None, 0, None)
+    assert st == lwfr.LWFR_E_WORKSPACE
+    st = lwfr.lib().lwfr_bind(ctx, ctypes.c_void_p(256), 16, None)
+    assert st == lwfr.LWFR_E_WORKSPACE
+    lwfr.lwfr_destroy(ctx)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_reference_nodes_match_oracle(N):
+    ctx = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_SW1D, N, 4))
+    xi, w = lwfr.lwfr_reference_nodes(ctx, N + 1)
+    re_ = oracle.refel(N)
+    np.testing.assert_allclose(xi, re_["xi"], atol=2e-16)
+    np.testing.assert_allclose(w, re_["w"], atol=2e-16)
+    lwfr.lwfr_destroy(ctx)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_fourier_cfl_matches_oracle(N):
+    assert abs(lwfr.lwfr_cfl_number(N) - oracle.cfl_number(N)) < 2e-6 * oracle.cfl_number(N)
