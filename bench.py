@@ -1,0 +1,173 @@
+"""Throughput of the time step on one MI355X, with roofline and CPU-oracle baseline.
+
+Workload (the metric's 1-GPU configuration): 2-D ideal GLM-MHD, Orszag-Tang
+vortex plus seeded Fourier perturbations of amplitude 1e-2 (seed 0), periodic
+256 x 256 elements, N = 4 (25 Gauss-Legendre points per element, 1,638,400
+solution points), FP64, C_s = 0.9 with CFL(N) from the library's Fourier
+analysis, subcell blending with Algorithms 1 and 2, dt computed on the device
+every step.
+
+One "step" is one full time step (means/indicator, dt and c_h, element stages,
+faces, update).  The state is resident in HBM before the timed region; the
+timed region is K consecutive steps bracketed by device synchronisation.
+
+Output: one JSON line (see the keys below).  value = DOF-updates/s =
+elements * points per element * K / wall time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FP64 DOF-updates/s per LWFR step (1 GPU, % roofline); adjoint/forward time"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X FP64 vector, published
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+
+# Algorithmic floating point operations per solution point of the element-local
+# stage loop (inner stages, local operator, time averages F, U, B^loc), counted
+# by the oracle's counting scalar (+, -, *, / each one operation) over the
+# tableau's non-zero entries and the non-zero columns of B_d.  They are the
+# work of the dominant kernel, k_stages (which also forms the volume residual
+# and the face traces; those are not counted here, so the achieved rate is a
+# lower bound).  tests/test_bench_contract.py re-counts them with the oracle.
+STAGE_LOOP_FLOPS_PER_DOF = {
+    ("GLMMHD2D", 4): 3561,
+    ("GLMMHD2D", 3): 2153,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nelem", type=int, default=256)
+    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(u0, n, N, steps):
+    """The oracle, as it stands, on the host: `steps` steps of the same workload."""
+    import numpy as np
+
+    import oracle
+
+    c = oracle.make_cfg(oracle.EQ_MHD2D, N, n, n, blending=2, cs=0.9)
+    u = np.ascontiguousarray(u0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u = oracle.step(c, u)["u"]
+    dt = time.perf_counter() - t0
+    dofs = u.shape[1] * u.shape[2]
+    return {
+        "value": dofs * steps / dt,
+        "unit": "DOF-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} steps of the full {n}x{n} N={N} GLM-MHD workload, single-threaded C++ oracle "
+                  f"({dt:.1f} s)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the step has no multi-GPU path "
+              f"in this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2512_08611_amd import lwfr, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lwfr.lib()  # raises if the HIP library is not built
+    n, N, K, Wm = args.nelem, args.degree, args.steps, args.warmup
+    dev = torch.device("cuda:0")
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), cfl_safety=0.9, blending=2)
+    st = lwfr.Stepper(cfg, dev)
+    u0 = workloads.mhd_smooth(np.array(st.xi), n, n, seed=0)
+    ua = torch.tensor(u0, dtype=torch.float64, device=dev)
+    ub = torch.empty_like(ua)
+    dtch = torch.zeros(2, dtype=torch.float64, device=dev)
+    E, P = n * n, (N + 1) ** 2
+    dofs = E * P
+
+    for _ in range(Wm):
+        st.step(ua, ub, 0.0, dtch)
+        ua, ub = ub, ua
+    torch.cuda.synchronize()
+    status, _ = st.query()
+
+    lwfr.lwfr_timing_begin(st.ctx, 8 * K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        st.step(ua, ub, 0.0, dtch)
+        ua, ub = ub, ua
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = lwfr.lwfr_timing_end(st.ctx)
+    status, flags = st.query()
+    wall = t1 - t0
+    value = dofs * K / wall
+
+    per_kernel = {k: {"ms_per_launch": (ms / cnt if cnt else None), "launches": cnt, "ms_total": ms}
+                  for k, (ms, cnt) in kern.items() if cnt}
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
+    avg_ms = per_kernel["k_stages"]["ms_per_launch"]
+    flops = STAGE_LOOP_FLOPS_PER_DOF.get(("GLMMHD2D", N))
+    achieved = flops * dofs / (avg_ms * 1e-3) / 1e12 if flops else None
+    roofline = {
+        "kernel": "k_stages",
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": FP64_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / FP64_VECTOR_PEAK_TFLOPS if achieved else None,
+        "traffic": None,
+        "algorithmic_flops_per_launch": flops * dofs if flops else None,
+        "dominant_kernel_by_time": dom,
+    }
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": wall / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2-D GLM-MHD Orszag-Tang + 1e-2 seeded Fourier perturbations, {n}x{n} periodic elements, "
+                        f"N={N} Gauss-Legendre ({dofs} DOF, 9 variables), blending + Algorithms 1-2, C_s=0.9",
+            "elements": E,
+            "degree": N,
+            "dof": dofs,
+        },
+        "roofline": roofline,
+        "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in per_kernel.items()},
+        "step_status": int(status),
+        "flags_or": int(flags),
+        "adjoint_over_forward": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(u0, n, N, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,18 @@ lwfr_status lwfr_residual(lwfr_ctx* ctx, const double* d_u, double dt, int32_t m
  * LWFR_OK otherwise.  flags_or (nullable) receives the raw OR. */
 lwfr_status lwfr_query(lwfr_ctx* ctx, uint32_t* flags_or);
 
+/* Per-kernel timing with HIP events recorded on the bound stream around every
+ * launch of the following calls, for at most max_launches launches (the rest
+ * are not timed).  lwfr_timing_end synchronises the stream and fills, for each
+ * kernel id (0 per-element means/indicator, 1 time step, 2 GLM speed candidates,
+ * 3 GLM speed, 4 element stages, 5 faces, 6 update, 7 residual), the summed
+ * milliseconds ms[k] and the number of timed launches launches[k]; both arrays
+ * hold LWFR_TIMING_KERNELS entries.  Events are created on the host by the
+ * library and released by lwfr_destroy. */
+#define LWFR_TIMING_KERNELS 8
+lwfr_status lwfr_timing_begin(lwfr_ctx* ctx, int32_t max_launches);
+lwfr_status lwfr_timing_end(lwfr_ctx* ctx, double* ms, uint32_t* launches);
+
 lwfr_status lwfr_destroy(lwfr_ctx* ctx);
 
 /* Thread-local message of the last failing call ("" if none). */

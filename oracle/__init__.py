@@ -114,6 +114,14 @@ def physics(eq, what, d, u, w=None, gamma=5.0 / 3.0, gravity=9.81, ch=0.0):
     return out[:n]
 
 
+def ncols(eq, d):
+    """Columns of B_d the oracle treats as not identically zero."""
+    out = np.zeros(16, dtype=np.int32)
+    n = lib().ora_ncols(eq, d, _p(out, ctypes.c_int))
+    assert n >= 0
+    return sorted(out[:n].tolist())
+
+
 def dt_ch(c, u):
     u = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros(2)
@@ -171,9 +179,9 @@ def jvp(c, u, v, dt, ch):
 
 
 def count_ops(c, u, dt, ch):
-    """Operation counts [phase][add, mul, div, sqrt, exp] for phases (stages, faces, update)."""
+    """Operation counts [phase][add, mul, div, sqrt, exp] for phases (stage loop, face traces, faces, update)."""
     u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
-    counts = np.zeros(15, dtype=np.uint64)
+    counts = np.zeros(20, dtype=np.uint64)
     assert lib().ora_count_ops(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch),
                                _p(counts, ctypes.c_uint64)) == 0
-    return counts.reshape(3, 5)
+    return counts.reshape(4, 5)

@@ -96,6 +96,23 @@ int ora_physics(int eq, double gamma, double gravity, double ch, int what, int d
   return 2;
 }
 
+// Columns of B_d the oracle treats as not identically zero; returns their count.
+int ora_ncols(int eq, int d, int* cols) {
+  auto run = [&](const auto& ph) {
+    using P = std::decay_t<decltype(ph)>;
+    for (int i = 0; i < P::NCOL; ++i) cols[i] = P::ncol(d, i);
+    return P::NCOL;
+  };
+  switch (eq) {
+    case EQ_SW1D: return run(SW1D{9.81});
+    case EQ_SW2D: return run(SW2D{9.81});
+    case EQ_MHD2D: return run(MHD2D{5.0 / 3.0});
+    case EQ_LINADV1D: return run(LinAdv1D{});
+    case EQ_VARADV1D: return run(VarAdv1D{});
+  }
+  return -1;
+}
+
 int ora_dt_ch(const ora_cfg* c, const double* u, double* dt_ch) {
   return dispatch(c, [&](auto& s) { s.dt_ch(u, dt_ch[0], dt_ch[1]); });
 }
@@ -169,8 +186,8 @@ int ora_jvp(const ora_cfg* c, const double* u, const double* v, double dt, doubl
 }
 
 // Algorithmic operation counts of one step, split into the element-local
-// stages, the interface fluxes and the element update:
-// counts[phase*5 + {add, mul, div, sqrt, exp}].
+// stages, the face traces (with F^nc), the interface fluxes and the element
+// update: counts[phase*5 + {add, mul, div, sqrt, exp}], phase 0..3.
 int ora_count_ops(const ora_cfg* c, const double* u, double dt, double ch, uint64_t* counts) {
   return dispatch(c, [&](auto& s) {
     using S = std::decay_t<decltype(s)>;
@@ -190,10 +207,12 @@ int ora_count_ops(const ora_cfg* c, const double* u, double dt, double ch, uint6
     FlopCounter::reset();
     s.template stages<Counting>(x.data(), dt, ch, L);
     grab(0);
-    s.template faces<Counting>(x.data(), L, alpha, dt, ch, Fc);
+    s.template face_traces<Counting>(x.data(), L);
     grab(1);
-    s.template update<Counting>(x.data(), L, Fc, alpha, dt, ch, y.data(), nullptr, nullptr);
+    s.template faces<Counting>(x.data(), L, alpha, dt, ch, Fc);
     grab(2);
+    s.template update<Counting>(x.data(), L, Fc, alpha, dt, ch, y.data(), nullptr, nullptr);
+    grab(3);
   });
 }
 

@@ -24,6 +24,9 @@ enum { EQ_SW1D = 1, EQ_SW2D = 2, EQ_MHD2D = 3, EQ_LINADV1D = 4, EQ_VARADV1D = 5 
 // (b_t = 0), hence its row of f and B is zero.
 struct SW1D {
   static constexpr int M = 3, DIM = 1, K = 1;
+  // columns of B_d that are not identically zero (B_d(u) w reads only these w_c)
+  static constexpr int NCOL = 1;
+  static int ncol(int, int) { return 2; }
   double g;
   template <class T> void flux(int, const T* u, T* f, double) const {
     T v = u[1] / u[0];
@@ -46,6 +49,8 @@ struct SW1D {
 
 struct SW2D {
   static constexpr int M = 4, DIM = 2, K = 1;
+  static constexpr int NCOL = 1;
+  static int ncol(int, int) { return 3; }
   double g;
   template <class T> void flux(int d, const T* u, T* f, double) const {
     T v1 = u[1] / u[0], v2 = u[2] / u[0];
@@ -80,6 +85,8 @@ struct SW2D {
 // p = (gamma-1)(E - rho|v|^2/2 - |B|^2/2 - psi^2/2).
 struct MHD2D {
   static constexpr int M = 9, DIM = 2, K = 2;
+  static constexpr int NCOL = 2;
+  static int ncol(int d, int i) { return i == 0 ? 5 + d : 8; }
   double gamma;
   template <class T> T pressure(const T* u) const {
     T kin = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
@@ -151,6 +158,8 @@ struct MHD2D {
 // eq. scalar.cons.law with f = u).
 struct LinAdv1D {
   static constexpr int M = 1, DIM = 1, K = 0;
+  static constexpr int NCOL = 0;
+  static int ncol(int, int) { return 0; }
   template <class T> void flux(int, const T* u, T* f, double) const { f[0] = u[0]; }
   template <class T> void ncprod(int, const T*, const T*, T* o) const { o[0] = T(0.0); }
   template <class T> T sigma(int, const T*, double) const { return T(1.0); }
@@ -163,6 +172,8 @@ struct LinAdv1D {
 // eq. var.coeff.adv.non.cons): u = (v, a), f = 0, B(u) w = (u_2 w_1, 0).
 struct VarAdv1D {
   static constexpr int M = 2, DIM = 1, K = 0;
+  static constexpr int NCOL = 1;
+  static int ncol(int, int) { return 0; }
   template <class T> void flux(int, const T*, T* f, double) const { f[0] = T(0.0); f[1] = T(0.0); }
   template <class T> void ncprod(int, const T* u, const T* w, T* o) const { o[0] = u[1] * w[0]; o[1] = T(0.0); }
   template <class T> T sigma(int, const T* u, double) const { return fabs(u[1]); }

@@ -226,12 +226,18 @@ struct Scheme {
     std::vector<T> a(M), fo(M), w(M), o(M), du(M), nc(M);
     for (int e = 0; e < E; ++e) {
       for (int j = 0; j < s; ++j) {
-        // inner stage u^(j) = u^n - dt sum_{k<j} a_jk L^(k)
+        // inner stage u^(j) = u^n - dt sum_{k<j} a_jk L^(k) (sum over the tableau's non-zero a_jk)
         for (int v = 0; v < M; ++v)
           for (int p = 0; p < P; ++p) {
             T acc = T(0.0);
-            for (int k = 0; k < j; ++k) acc = acc + T(tb.A[j * s + k]) * Lst[((size_t)k * M + v) * P + p];
-            uj[(size_t)v * P + p] = j == 0 ? un[idx(v, e, p)] : un[idx(v, e, p)] - T(dt) * acc;
+            bool any = false;
+            for (int k = 0; k < j; ++k)
+              if (tb.A[j * s + k] != 0.0) {
+                T t = T(tb.A[j * s + k]) * Lst[((size_t)k * M + v) * P + p];
+                acc = any ? acc + t : t;
+                any = true;
+              }
+            uj[(size_t)v * P + p] = any ? un[idx(v, e, p)] - T(dt) * acc : un[idx(v, e, p)];
           }
         // fluxes at the solution points
         for (int p = 0; p < P; ++p) {
@@ -249,13 +255,16 @@ struct Scheme {
           for (int d = 0; d < DIM; ++d) {
             int i = pos(d, p), q = line(d, p);
             for (int v = 0; v < M; ++v) {
-              T df = T(0.0), dv = T(0.0);
-              for (int r = 0; r < n1; ++r) {
-                T Dir = T(re.D[i * n1 + r]);
-                df = df + Dir * f[((size_t)d * M + v) * P + node(d, q, r)];
-                dv = dv + Dir * uj[(size_t)v * P + node(d, q, r)];
-              }
+              T df = T(0.0);
+              for (int r = 0; r < n1; ++r) df = df + T(re.D[i * n1 + r]) * f[((size_t)d * M + v) * P + node(d, q, r)];
               fo[v] = df;
+              du[v] = T(0.0);
+            }
+            // D_d u for the columns of B_d that are not identically zero
+            for (int c = 0; c < Phys::NCOL; ++c) {
+              const int v = Phys::ncol(d, c);
+              T dv = T(0.0);
+              for (int r = 0; r < n1; ++r) dv = dv + T(re.D[i * n1 + r]) * uj[(size_t)v * P + node(d, q, r)];
               du[v] = dv;
             }
             ph.ncprod(d, a.data(), du.data(), nc.data());
@@ -266,6 +275,7 @@ struct Scheme {
           }
           for (int v = 0; v < M; ++v) {
             Lst[((size_t)j * M + v) * P + p] = Lp[v];
+            if (tb.b[j] == 0.0) continue;  // stage with zero weight adds nothing
             T bj = T(tb.b[j]);
             L.U[idx(v, e, p)] = L.U[idx(v, e, p)] + bj * a[v];
             L.Bl[idx(v, e, p)] = L.Bl[idx(v, e, p)] + bj * Bp[v];
@@ -275,7 +285,14 @@ struct Scheme {
           }
         }
       }
-      // traces of F_d, U and u^n at the faces
+    }
+  }
+
+  // traces of F_d, U and u^n at the faces, and F^nc
+  template <class T>
+  void face_traces(const T* un, Local<T>& L) const {
+    std::vector<T> a(M), w(M), o(M);
+    for (int e = 0; e < E; ++e) {
       for (int d = 0; d < DIM; ++d)
         for (int side = 0; side < 2; ++side) {
           const std::vector<double>& V = side ? re.VR : re.VL;
@@ -540,6 +557,7 @@ struct Scheme {
     Local<T> L;
     Faces<T> Fc;
     stages(un, dt, ch, L);
+    face_traces(un, L);
     faces(un, L, alpha, dt, ch, Fc);
     if (theta_face) std::copy(Fc.theta.begin(), Fc.theta.end(), theta_face);
     update(un, L, Fc, alpha, dt, ch, unew, flags, theta_elem);

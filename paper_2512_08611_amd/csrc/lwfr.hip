@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/lwfr.h"
 #include "kernels.hpp"
@@ -37,6 +38,11 @@ struct lwfr_ctx {
   void* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
+  // optional per-kernel timing with HIP events on the bound stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kernel;  // kernel id of the launch between event 2i and 2i+1
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -68,6 +74,38 @@ constexpr int epb_for(int DIM) {
       return fail(LWFR_E_HIP, std::string(name) + ": " + hipGetErrorString(err_)); \
   } while (0)
 
+// kernel ids reported by lwfr_timing_end
+enum { KID_PRE = 0, KID_DT, KID_CH, KID_CHFIN, KID_STAGES, KID_FACES, KID_UPDATE, KID_RESIDUAL, KID_COUNT };
+
+// Records an event before (open) and after (close) a launch when timing is on.
+struct TimedLaunch {
+  lwfr_ctx* c;
+  int kid;
+  bool on;
+  TimedLaunch(lwfr_ctx* c_, int kid_) : c(c_), kid(kid_), on(false) {
+    if (c->timing && c->ev_used + 2 <= c->ev.size()) {
+      on = true;
+      (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+    }
+  }
+  void close() {
+    if (on) {
+      (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+      c->ev_kernel[c->ev_used / 2] = kid;
+      c->ev_used += 2;
+      on = false;
+    }
+  }
+};
+
+#define LWFR_LAUNCH(kid, name, ...)          \
+  do {                                       \
+    TimedLaunch tl_(c, kid);                 \
+    hipLaunchKernelGGL(__VA_ARGS__);         \
+    tl_.close();                             \
+    LWFR_CHECK_LAUNCH(name);                 \
+  } while (0)
+
 // The launch sequence of one step for system Ph at degree N.
 template <class Ph, int N>
 lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
@@ -77,24 +115,19 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   const int E = c->E;
   hipStream_t s = c->stream;
   const bool has_ch = std::is_same<Ph, MHD2D>::value;
-  hipLaunchKernelGGL((k_pre<Ph, N>), dim3(c->nblk_pre), dim3(256), 0, s, kp, u_in);
-  LWFR_CHECK_LAUNCH("k_pre");
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
-  LWFR_CHECK_LAUNCH("k_dt");
+  LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N>), dim3(c->nblk_pre), dim3(256), 0, s, kp, u_in);
+  LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(256), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
   if (has_ch) {
-    hipLaunchKernelGGL(k_ch, dim3(c->nblk_pre), dim3(256), 0, s, kp);
-    LWFR_CHECK_LAUNCH("k_ch");
-    hipLaunchKernelGGL(k_ch_fin, dim3(1), dim3(256), 0, s, kp, d_dt_ch);
-    LWFR_CHECK_LAUNCH("k_ch_fin");
+    LWFR_LAUNCH(KID_CH, "k_ch", k_ch, dim3(c->nblk_pre), dim3(256), 0, s, kp);
+    LWFR_LAUNCH(KID_CHFIN, "k_ch_fin", k_ch_fin, dim3(1), dim3(256), 0, s, kp, d_dt_ch);
   }
   const int nblk_el = (E + EPB - 1) / EPB;
-  hipLaunchKernelGGL((k_stages<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out, d_alpha);
-  LWFR_CHECK_LAUNCH("k_stages");
+  LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
+              d_alpha);
   const int nfp_total = DIM * E * NFP;
-  hipLaunchKernelGGL((k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
-  LWFR_CHECK_LAUNCH("k_faces");
-  hipLaunchKernelGGL((k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out, d_flags);
-  LWFR_CHECK_LAUNCH("k_update");
+  LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
+  LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
+              d_flags);
   return LWFR_OK;
 }
 
@@ -297,9 +330,8 @@ lwfr_status lwfr_residual(lwfr_ctx* c, const double* d_u, double dt, int32_t mod
   if (mode == 1) { kp.blending = 1; kp.alpha_force = 1.0; }
   lwfr_status st = dispatch_step(c, kp, d_u, d_R, nullptr, nullptr, nullptr);
   if (st != LWFR_OK) return st;
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d_u, d_R, n,
-                     (const double*)kp.scal);
-  LWFR_CHECK_LAUNCH("k_residual");
+  LWFR_LAUNCH(KID_RESIDUAL, "k_residual", k_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+              d_u, d_R, n, (const double*)kp.scal);
   return LWFR_OK;
 }
 
@@ -317,7 +349,43 @@ lwfr_status lwfr_query(lwfr_ctx* c, uint32_t* flags_or) {
   return LWFR_OK;
 }
 
+lwfr_status lwfr_timing_begin(lwfr_ctx* c, int32_t max_launches) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(LWFR_E_INVALID_ARG, "max_launches out of range");
+  const size_t need = 2 * (size_t)max_launches;
+  while (c->ev.size() < need) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
+    c->ev.push_back(e);
+  }
+  c->ev_kernel.assign(c->ev.size() / 2, -1);
+  c->ev_used = 0;
+  c->timing = true;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_timing_end(lwfr_ctx* c, double* ms, uint32_t* launches) {
+  if (!c || !ms || !launches) return fail(LWFR_E_INVALID_ARG, "null argument");
+  if (!c->timing) return fail(LWFR_E_STATE, "lwfr_timing_begin has not been called");
+  c->timing = false;
+  hipError_t err = hipStreamSynchronize(c->stream);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("lwfr_timing_end: ") + hipGetErrorString(err));
+  for (int k = 0; k < LWFR_TIMING_KERNELS; ++k) { ms[k] = 0.0; launches[k] = 0; }
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float t = 0.0f;
+    err = hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]);
+    if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(err));
+    const int kid = c->ev_kernel[i / 2];
+    if (kid >= 0 && kid < LWFR_TIMING_KERNELS) { ms[kid] += t; launches[kid] += 1; }
+  }
+  return LWFR_OK;
+}
+
 lwfr_status lwfr_destroy(lwfr_ctx* c) {
+  if (c)
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
   return LWFR_OK;
 }

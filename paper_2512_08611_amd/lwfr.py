@@ -58,8 +58,11 @@ _SIGS = {
                   ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_residual": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p],
     "lwfr_query": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],
+    "lwfr_timing_begin": [ctypes.c_void_p, ctypes.c_int32],
+    "lwfr_timing_end": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32)],
     "lwfr_destroy": [ctypes.c_void_p],
 }
+TIMING_KERNELS = ("k_pre", "k_dt", "k_ch", "k_ch_fin", "k_stages", "k_faces", "k_update", "k_residual")
 
 
 def lib():
@@ -160,6 +163,19 @@ def lwfr_query(ctx):
     f = ctypes.c_uint32()
     st = lib().lwfr_query(ctx, ctypes.byref(f))
     return st, f.value
+
+
+def lwfr_timing_begin(ctx, max_launches):
+    _check(lib().lwfr_timing_begin(ctx, int(max_launches)))
+
+
+def lwfr_timing_end(ctx):
+    """{kernel name: (total ms, launches)} of the launches since lwfr_timing_begin."""
+    n = len(TIMING_KERNELS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_uint32 * n)()
+    _check(lib().lwfr_timing_end(ctx, ms, cnt))
+    return {TIMING_KERNELS[k]: (ms[k], cnt[k]) for k in range(n)}
 
 
 def lwfr_destroy(ctx):

@@ -1,0 +1,33 @@
+"""The benchmark's stated constants agree with the oracle, and its CLI contract holds on the CPU."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_08611_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("key", sorted(bench.STAGE_LOOP_FLOPS_PER_DOF))
+def test_stage_loop_flop_counts(key):
+    _, N = key
+    n = 3
+    re = oracle.refel(N)
+    u = W.mhd_smooth(re["xi"], n)
+    c = oracle.make_cfg(oracle.EQ_MHD2D, N, n, n, blending=2)
+    dt, ch = oracle.dt_ch(c, u)
+    counts = oracle.count_ops(c, u, dt, ch).astype(float)
+    per_dof = counts[0].sum() / (u.shape[1] * u.shape[2])
+    assert per_dof == bench.STAGE_LOOP_FLOPS_PER_DOF[key]
+
+
+def test_multi_gpu_request_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -71,6 +71,21 @@ def test_sigma_is_spectral_radius(eq, dim):
                 assert abs(lam - sig) <= 1e-6 * max(1.0, sig), (trial, d, ch, lam, sig)
 
 
+@pytest.mark.parametrize("eq,dim", [(oracle.EQ_SW1D, 1), (oracle.EQ_SW2D, 2), (oracle.EQ_MHD2D, 2),
+                                    (oracle.EQ_LINADV1D, 1), (oracle.EQ_VARADV1D, 1)])
+def test_nonzero_columns_of_B(eq, dim):
+    """The columns of B_d the stage loop differentiates are exactly the non-zero ones."""
+    rng = np.random.default_rng(2)
+    n = oracle.NVARS[eq]
+    for d in range(dim):
+        nz = np.zeros(n, dtype=bool)
+        for _ in range(20):
+            u = rand_mhd(rng) if eq == oracle.EQ_MHD2D else (
+                rand_sw(rng, dim) if eq in (oracle.EQ_SW1D, oracle.EQ_SW2D) else rng.uniform(0.5, 2, n))
+            nz |= np.abs(bmatrix(eq, d, u)).max(axis=0) > 0
+        assert sorted(np.nonzero(nz)[0].tolist()) == oracle.ncols(eq, d)
+
+
 def test_varadv_sigma_and_structure():
     u = np.array([0.3, -1.7])
     A = bmatrix(oracle.EQ_VARADV1D, 0, u)
