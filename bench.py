@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 256 MiB (reference kernel for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -164,6 +166,12 @@ def main():
         "flags_or": int(flags),
         "adjoint_over_forward": None,
     }
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(u0, n, N, args.cpu_steps)
     print(json.dumps(out), flush=True)

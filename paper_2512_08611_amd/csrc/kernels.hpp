@@ -22,9 +22,13 @@ namespace lwfr {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+#ifndef STAGES_WAVES_PER_EU
+#define STAGES_WAVES_PER_EU 1
+#endif
+
 // everything a kernel needs besides the state pointers, passed by value
 struct KParams {
-  int nx, ny, E, nblk_pre;
+  int nx, ny, E, nblk_pre, nblk_ch;
   double dx[2], inv_dx[2];
   double D[kMaxN1][kMaxN1], VL[kMaxN1], VR[kMaxN1], w[kMaxN1], gR[kMaxN1], gL[kMaxN1];
   double Leg[kMaxN1][kMaxN1];
@@ -74,105 +78,117 @@ __device__ inline double theta_limit(double eps, double Pa, double Pb, bool& gua
 }
 
 // ------------------------------------------------------------------------
-// k_pre: one thread per element
-template <class Ph, int N>
-__global__ void __launch_bounds__(256) k_pre(const KParams kp, const double* __restrict__ un) {
+// k_pre: one thread per solution point, EPB elements per block (coalesced
+// loads); per element: mean state, ideal wave speeds, Lambda_e and the raw
+// smoothness indicator; per block: the maximum of Lambda_e.
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams kp, const double* __restrict__ un) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
-  __shared__ double s_max[256];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double s_u[EPB][M][P];
+  __shared__ double s_q[EPB][P];
+  __shared__ double s_ub[EPB][M];
+  __shared__ double s_lam[EPB];
+  const int tid = threadIdx.x;
+  const int le = tid / P, p = tid - le * P;
+  const int e = blockIdx.x * EPB + le;
+  const bool act = e < kp.E;
   const PhysParams pp{kp.g, kp.gamma, 0.0};
-  double lam = 0.0;
-  if (e < kp.E) {
-    double ub[M];
+  const bool want_alpha = kp.blending >= 1 && kp.alpha_force < 0.0;
+  double x[M];
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-      const double* src = un + ((size_t)v * kp.E + e) * P;
-      double s = 0.0;
+  for (int v = 0; v < M; ++v) {
+    x[v] = act ? un[((size_t)v * kp.E + e) * P + p] : 1.0;
+    s_u[le][v][p] = x[v];
+  }
+  if (want_alpha) s_q[le][p] = Ph::indicator(x, pp);
+  __syncthreads();
+  // element mean of each variable, summed over the nodes in order
+  for (int v = p; v < M; v += P) {
+    double s = 0.0;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const double wp = DIM == 1 ? kp.w[p] : kp.w[p % n1] * kp.w[p / n1];
-        s += wp * src[p];
+    for (int r = 0; r < P; ++r) {
+      const double wr = DIM == 1 ? kp.w[r] : kp.w[r % n1] * kp.w[r / n1];
+      s += wr * s_u[le][v][r];
+    }
+    s_ub[le][v] = s;
+  }
+  __syncthreads();
+  if (p == 0) {
+    double lam = 0.0;
+    if (act) {
+      double ub[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) ub[v] = s_ub[le][v];
+      double av, c;
+      Ph::template speeds<0>(ub, av, c, pp);
+      lam = (av + c) * kp.inv_dx[0];
+      kp.speeds[(size_t)e * 2 * DIM + 0] = av;
+      kp.speeds[(size_t)e * 2 * DIM + 1] = c;
+      if constexpr (DIM == 2) {
+        Ph::template speeds<1>(ub, av, c, pp);
+        lam += (av + c) * kp.inv_dx[1];
+        kp.speeds[(size_t)e * 4 + 2] = av;
+        kp.speeds[(size_t)e * 4 + 3] = c;
       }
-      ub[v] = s;
     }
-    double av, c;
-    Ph::template speeds<0>(ub, av, c, pp);
-    lam = (av + c) * kp.inv_dx[0];
-    kp.speeds[(size_t)e * 2 * DIM + 0] = av;
-    kp.speeds[(size_t)e * 2 * DIM + 1] = c;
-    if constexpr (DIM == 2) {
-      Ph::template speeds<1>(ub, av, c, pp);
-      lam += (av + c) * kp.inv_dx[1];
-      kp.speeds[(size_t)e * 4 + 2] = av;
-      kp.speeds[(size_t)e * 4 + 3] = c;
-    }
+    s_lam[le] = lam;
+  } else if (p == 1 % P && want_alpha && act) {
     // smoothness indicator: energy fractions of the highest modes of q in the
     // orthonormal Legendre basis, logistic map, clip and cap
-    if (kp.blending >= 1 && kp.alpha_force < 0.0) {
-      double q[P];
+    double tot = 0.0, c1 = 0.0, c2 = 0.0;
+    if constexpr (DIM == 1) {
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        double x[M];
+      for (int k = 0; k < n1; ++k) {
+        double m = 0.0;
 #pragma unroll
-        for (int v = 0; v < M; ++v) x[v] = un[((size_t)v * kp.E + e) * P + p];
-        q[p] = Ph::indicator(x, pp);
+        for (int r = 0; r < n1; ++r) m += kp.w[r] * s_q[le][r] * kp.Leg[k][r];
+        const double m2 = m * m;
+        tot += m2;
+        if (k <= N - 1) c1 += m2;
+        if (k <= N - 2) c2 += m2;
       }
-      double tot = 0.0, c1 = 0.0, c2 = 0.0;
-      if constexpr (DIM == 1) {
+    } else {
+      double t[n1][n1];  // t[k][jj] = sum_i w_i L_k(xi_i) q(i, jj)
+#pragma unroll
+      for (int k = 0; k < n1; ++k)
+#pragma unroll
+        for (int jj = 0; jj < n1; ++jj) {
+          double s = 0.0;
+#pragma unroll
+          for (int i = 0; i < n1; ++i) s += kp.w[i] * kp.Leg[k][i] * s_q[le][i + n1 * jj];
+          t[k][jj] = s;
+        }
+#pragma unroll
+      for (int l = 0; l < n1; ++l)
 #pragma unroll
         for (int k = 0; k < n1; ++k) {
           double m = 0.0;
 #pragma unroll
-          for (int p = 0; p < n1; ++p) m += kp.w[p] * q[p] * kp.Leg[k][p];
+          for (int jj = 0; jj < n1; ++jj) m += kp.w[jj] * kp.Leg[l][jj] * t[k][jj];
           const double m2 = m * m;
+          const int deg = k > l ? k : l;
           tot += m2;
-          if (k <= N - 1) c1 += m2;
-          if (k <= N - 2) c2 += m2;
+          if (deg <= N - 1) c1 += m2;
+          if (deg <= N - 2) c2 += m2;
         }
-      } else {
-        double t[n1][n1];  // t[k][jj] = sum_i w_i L_k(xi_i) q(i, jj)
-#pragma unroll
-        for (int k = 0; k < n1; ++k)
-#pragma unroll
-          for (int jj = 0; jj < n1; ++jj) {
-            double s = 0.0;
-#pragma unroll
-            for (int i = 0; i < n1; ++i) s += kp.w[i] * kp.Leg[k][i] * q[i + n1 * jj];
-            t[k][jj] = s;
-          }
-#pragma unroll
-        for (int l = 0; l < n1; ++l)
-#pragma unroll
-          for (int k = 0; k < n1; ++k) {
-            double m = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < n1; ++jj) m += kp.w[jj] * kp.Leg[l][jj] * t[k][jj];
-            const double m2 = m * m;
-            const int deg = k > l ? k : l;
-            tot += m2;
-            if (deg <= N - 1) c1 += m2;
-            if (deg <= N - 2) c2 += m2;
-          }
-      }
-      double En = tot > 0.0 ? (tot - c1) / tot : 0.0;
-      if (N >= 2) {
-        const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
-        En = En >= e2 ? En : e2;
-      }
-      double a = 1.0 / (1.0 + exp(-(kp.ind_s / kp.ind_T) * (En - kp.ind_T)));
-      if (a < kp.alpha_min) a = 0.0;
-      if (a > 1.0 - kp.alpha_min) a = 1.0;
-      a = fmin(a, kp.alpha_max);
-      kp.alpha_raw[e] = a;
     }
+    double En = tot > 0.0 ? (tot - c1) / tot : 0.0;
+    if (N >= 2) {
+      const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
+      En = En >= e2 ? En : e2;
+    }
+    double a = 1.0 / (1.0 + exp(-(kp.ind_s / kp.ind_T) * (En - kp.ind_T)));
+    if (a < kp.alpha_min) a = 0.0;
+    if (a > 1.0 - kp.alpha_min) a = 1.0;
+    a = fmin(a, kp.alpha_max);
+    kp.alpha_raw[e] = a;
   }
-  s_max[threadIdx.x] = lam;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
-    __syncthreads();
+  if (tid == 0) {
+    double m = s_lam[0];
+    for (int l = 1; l < EPB; ++l) m = fmax(m, s_lam[l]);
+    kp.part[blockIdx.x] = m;
   }
-  if (threadIdx.x == 0) kp.part[blockIdx.x] = s_max[0];
 }
 
 // k_dt: one block; Lambda and dt
@@ -224,7 +240,7 @@ __global__ void __launch_bounds__(256) k_ch(const KParams kp) {
 __global__ void __launch_bounds__(256) k_ch_fin(const KParams kp, double* d_dt_ch) {
   __shared__ double s_min[256];
   double m = INFINITY;
-  for (int i = threadIdx.x; i < kp.nblk_pre; i += blockDim.x) m = fmin(m, kp.part2[i]);
+  for (int i = threadIdx.x; i < kp.nblk_ch; i += blockDim.x) m = fmin(m, kp.part2[i]);
   s_min[threadIdx.x] = m;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -241,11 +257,21 @@ __global__ void __launch_bounds__(256) k_ch_fin(const KParams kp, double* d_dt_c
 // k_stages: one thread per solution point, EPB elements per block.
 // Inner stages u^(s) = u^n - dt sum_{k<s} a_sk L^(k) with the local operator
 // L = sum_d [D_d f_d(u) + B_d(u) D_d u]/dx_d (paper §3, stages above eq.
-// crkfr.non.cons.final); F_d, U and B^loc accumulate with the weights b_s.
-// Output: the volume part R_vol = B^loc + sum_d D_d F_d/dx_d of the high order
-// residual (written to the output state buffer) and the face traces of F_d, U, u^n.
+// crkfr.non.cons.final); F_d and U accumulate with the weights b_s.  The sums
+// S_t = sum_k a_tk L^(k) of later stages are carried as running partial sums
+// (same order of summation), so only the partial sums still needed stay live.
+// Output: the volume part of the high order residual, B^loc + sum_d D_d F_d/dx_d,
+// which by linearity of D_d equals sum_s b_s L^(s) (written to the output state
+// buffer), and the face traces of F_d, U and u^n.
+template <int N>
+__host__ __device__ constexpr int first_nz(int t) {
+  for (int k = 0; k < t; ++k)
+    if (Tableau<N>::a(t, k) != 0.0) return k;
+  return -1;
+}
+
 template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
     k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
   constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
@@ -272,10 +298,10 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
     if constexpr (DIM == 2) Drow[1][r] = kp.D[j][r];
   }
 
-  double Fa[DIM][M], Ua[M], Bl[M], Lk[S][M], u[M];
+  double Fa[DIM][M], Ua[M], Ra[M], Sp[S][M], u[M];
 #pragma unroll
   for (int v = 0; v < M; ++v) {
-    Ua[v] = 0.0; Bl[v] = 0.0;
+    Ua[v] = 0.0; Ra[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Fa[d][v] = 0.0;
   }
@@ -283,14 +309,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 #pragma unroll
   for (int st = 0; st < S; ++st) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-      double acc = 0.0;
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < st; ++k)
-        if (Tab::a(st, k) != 0.0) { acc = any ? acc + Tab::a(st, k) * Lk[k][v] : Tab::a(st, k) * Lk[k][v]; any = true; }
-      u[v] = any ? un[v] - dt * acc : un[v];
-    }
+    for (int v = 0; v < M; ++v) u[v] = first_nz<N>(st) >= 0 ? un[v] - dt * Sp[st][v] : un[v];
     double f[DIM][M];
     Ph::template flux<0>(u, f[0], pp);
     if constexpr (DIM == 2) Ph::template flux<1>(u, f[1], pp);
@@ -304,57 +323,62 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 #pragma unroll
         for (int c = 0; c < Ph::NCD; ++c) s_buf[le][DIM * M + d * NCD + c][p] = u[Ph::nc_comp(d, c)];
     }
-    __syncthreads();
-    double Ls[M], Bs[M];
+    const double bs = Tab::b(st);
+    if (bs != 0.0) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) { Ls[v] = 0.0; Bs[v] = 0.0; }
+      for (int v = 0; v < M; ++v) {
+        Ua[v] += bs * u[v];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Fa[d][v] += bs * f[d][v];
+      }
+    }
+    __syncthreads();
+    double Ls[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) Ls[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int q = d == 0 ? j : i;
       double df[M], w[M], nc[M];
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        double s = 0.0;
+        double sacc = 0.0;
 #pragma unroll
-        for (int r = 0; r < n1; ++r) s += Drow[d][r] * s_buf[le][d * M + v][node_at<n1>(d, q, r)];
-        df[v] = s;
+        for (int r = 0; r < n1; ++r) sacc += Drow[d][r] * s_buf[le][d * M + v][node_at<n1>(d, q, r)];
+        df[v] = sacc;
         w[v] = 0.0;
       }
       if constexpr (Ph::NCD > 0) {
 #pragma unroll
         for (int c = 0; c < Ph::NCD; ++c) {
-          double s = 0.0;
+          double sacc = 0.0;
 #pragma unroll
-          for (int r = 0; r < n1; ++r) s += Drow[d][r] * s_buf[le][DIM * M + d * NCD + c][node_at<n1>(d, q, r)];
-          w[Ph::nc_comp(d, c)] = s;
+          for (int r = 0; r < n1; ++r) sacc += Drow[d][r] * s_buf[le][DIM * M + d * NCD + c][node_at<n1>(d, q, r)];
+          w[Ph::nc_comp(d, c)] = sacc;
         }
       }
       if (d == 0) Ph::template ncprod<0>(u, w, nc, pp);
       else Ph::template ncprod<(DIM > 1 ? 1 : 0)>(u, w, nc, pp);
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        Ls[v] += (df[v] + nc[v]) * kp.inv_dx[d];
-        Bs[v] += nc[v] * kp.inv_dx[d];
-      }
+      for (int v = 0; v < M; ++v) Ls[v] += (df[v] + nc[v]) * kp.inv_dx[d];
     }
     __syncthreads();
-    constexpr double dummy = 0.0;
-    (void)dummy;
-    const double bs = Tab::b(st);
     if (bs != 0.0) {
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        Ua[v] += bs * u[v];
-        Bl[v] += bs * Bs[v];
+      for (int v = 0; v < M; ++v) Ra[v] += bs * Ls[v];
+    }
+    // fold L^(st) into the running sums of the later stages that use it
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) Fa[d][v] += bs * f[d][v];
+    for (int t = st + 1; t < S; ++t) {
+      const double a = Tab::a(t, st);
+      if (a != 0.0) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) Sp[t][v] = first_nz<N>(t) == st ? a * Ls[v] : Sp[t][v] + a * Ls[v];
       }
     }
-#pragma unroll
-    for (int v = 0; v < M; ++v) Lk[st][v] = Ls[v];
   }
 
-  // time-averaged flux and solution to LDS
+  // time-averaged flux and solution to LDS for the face traces
 #pragma unroll
   for (int d = 0; d < DIM; ++d)
 #pragma unroll
@@ -365,18 +389,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 
   if (act) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) {
-      double R = Bl[v];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const int q = d == 0 ? j : i;
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < n1; ++r) s += Drow[d][r] * s_buf[le][d * M + v][node_at<n1>(d, q, r)];
-        R += s * kp.inv_dx[d];
-      }
-      rvol_g[((size_t)v * kp.E + e) * P + p] = R;
-    }
+    for (int v = 0; v < M; ++v) rvol_g[((size_t)v * kp.E + e) * P + p] = Ra[v];
     // face traces: 2*DIM*NFP face points per element, strided over the element's threads
     constexpr int NFT = 2 * DIM * NFP;
     for (int t = p; t < NFT; t += P) {
@@ -578,7 +591,9 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
     k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
   __shared__ double s_u[EPB][M][P];
-  __shared__ double s_red[EPB][P];
+  __shared__ double s_f[EPB][M][P];     // f_d at the nodes (one direction at a time)
+  __shared__ double s_left[EPB][M][P];  // f^{num,+} of the subface left of each node
+  __shared__ double s_red[EPB][P];      // sigma_d at the nodes / reductions
   __shared__ uint32_t s_fl[EPB][P];
 
   const int tid = threadIdx.x;
@@ -626,29 +641,53 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 #pragma unroll
     for (int v = 0; v < M; ++v) us[v] = uH[v];
   } else {
-    // lower order subcell update
+    // lower order subcell update: per direction, every node evaluates f_d and
+    // sigma_d once; the node left of each interior subface forms its two
+    // fluxes f^{num,-}, f^{num,+} (eq. combined.num.flux) and passes f^{num,+}
+    // to the node on its right
     double RL[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) RL[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
-      double right[M], left[M], nb[M];
-      if (ii < N) {
+      double fo[M];
+      double sg;
+      if (d == 0) { Ph::template flux<0>(un, fo, pp); sg = Ph::template sigma<0>(un, pp); }
+      else { Ph::template flux<(DIM > 1 ? 1 : 0)>(un, fo, pp); sg = Ph::template sigma<(DIM > 1 ? 1 : 0)>(un, pp); }
 #pragma unroll
-        for (int v = 0; v < M; ++v) nb[v] = s_u[le][v][node_at<n1>(d, q, ii < N ? ii + 1 : ii)];
-        if (d == 0) low_flux<Ph, 0>(un, nb, right, nullptr, pp);
-        else low_flux<Ph, (DIM > 1 ? 1 : 0)>(un, nb, right, nullptr, pp);
+      for (int v = 0; v < M; ++v) s_f[le][v][p] = fo[v];
+      s_red[le][p] = sg;
+      __syncthreads();
+      double right[M];
+      if (ii < N) {
+        const int pn = node_at<n1>(d, q, ii < N ? ii + 1 : ii);
+        double un2[M], avg[M], bL[M], bR[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) { un2[v] = s_u[le][v][pn]; avg[v] = 0.5 * (un[v] + un2[v]); }
+        const double sr = s_red[le][pn];
+        const double lam = sg >= sr ? sg : sr;
+        if (d == 0) { Ph::template ncprod<0>(un, avg, bL, pp); Ph::template ncprod<0>(un2, avg, bR, pp); }
+        else {
+          Ph::template ncprod<(DIM > 1 ? 1 : 0)>(un, avg, bL, pp);
+          Ph::template ncprod<(DIM > 1 ? 1 : 0)>(un2, avg, bR, pp);
+        }
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          const double fc = 0.5 * (fo[v] + s_f[le][v][pn]) - 0.5 * lam * (un2[v] - un[v]);
+          right[v] = fc + bL[v];
+          s_left[le][v][pn] = fc + bR[v];
+        }
       } else {
         const size_t fR = (size_t)e * NFP + q;
 #pragma unroll
         for (int v = 0; v < M; ++v) right[v] = act ? kp.Fm[((size_t)d * M + v) * nf + fR] : 0.0;
       }
+      __syncthreads();
+      double left[M];
       if (ii > 0) {
 #pragma unroll
-        for (int v = 0; v < M; ++v) nb[v] = s_u[le][v][node_at<n1>(d, q, ii > 0 ? ii - 1 : ii)];
-        if (d == 0) low_flux<Ph, 0>(nb, un, nullptr, left, pp);
-        else low_flux<Ph, (DIM > 1 ? 1 : 0)>(nb, un, nullptr, left, pp);
+        for (int v = 0; v < M; ++v) left[v] = s_left[le][v][p];
       } else {
         const size_t fL = (size_t)eL[d] * NFP + q;
 #pragma unroll
@@ -656,6 +695,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
       }
 #pragma unroll
       for (int v = 0; v < M; ++v) RL[v] += (right[v] - left[v]) * kp.inv_wdx[d][ii];
+      __syncthreads();
     }
     double uL[M];
 #pragma unroll

@@ -28,7 +28,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 struct lwfr_ctx {
   lwfr_config cfg;
   int M = 0, DIM = 0, K = 0, N = 0, n1 = 0, P = 0, NFP = 0, E = 0;
-  int nblk_pre = 0;
+  int nblk_pre = 0, nblk_ch = 0;
   RefData rd;
   double cfl = 0.0;
   KParams kp;
@@ -62,9 +62,23 @@ bool eq_info(int eq, EqInfo& info) {
   return false;
 }
 
+// Elements per workgroup of the per-point kernels (k_pre, k_stages, k_update).
+#ifndef LWFR_EPB_OVERRIDE
+#define LWFR_EPB_OVERRIDE 0
+#endif
+// Default: 256 threads per workgroup; 2-D degree 4 with 9 variables uses 5
+// elements (125 threads): measured fastest for the register-bound stage kernel.
 template <int N>
-constexpr int epb_for(int DIM) {
-  return 256 / ipow(N + 1, DIM);
+constexpr int epb_for(int DIM, int M) {
+  return LWFR_EPB_OVERRIDE > 0 ? LWFR_EPB_OVERRIDE : (DIM == 2 && N == 4 && M >= 9) ? 5 : 256 / ipow(N + 1, DIM);
+}
+inline int epb_runtime(int N, int DIM, int M) {
+  switch (N) {
+    case 1: return epb_for<1>(DIM, M);
+    case 2: return epb_for<2>(DIM, M);
+    case 3: return epb_for<3>(DIM, M);
+    default: return epb_for<4>(DIM, M);
+  }
 }
 
 #define LWFR_CHECK_LAUNCH(name)                                                   \
@@ -111,14 +125,14 @@ template <class Ph, int N>
 lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
                         double* d_alpha, uint32_t* d_flags) {
   constexpr int DIM = Ph::DIM, P = ipow(N + 1, DIM), NFP = DIM == 1 ? 1 : N + 1;
-  constexpr int EPB = epb_for<N>(DIM);
+  constexpr int EPB = epb_for<N>(DIM, Ph::M);
   const int E = c->E;
   hipStream_t s = c->stream;
   const bool has_ch = std::is_same<Ph, MHD2D>::value;
-  LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N>), dim3(c->nblk_pre), dim3(256), 0, s, kp, u_in);
+  LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N, EPB>), dim3(c->nblk_pre), dim3(EPB * P), 0, s, kp, u_in);
   LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(256), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
   if (has_ch) {
-    LWFR_LAUNCH(KID_CH, "k_ch", k_ch, dim3(c->nblk_pre), dim3(256), 0, s, kp);
+    LWFR_LAUNCH(KID_CH, "k_ch", k_ch, dim3(c->nblk_ch), dim3(256), 0, s, kp);
     LWFR_LAUNCH(KID_CHFIN, "k_ch_fin", k_ch_fin, dim3(1), dim3(256), 0, s, kp, d_dt_ch);
   }
   const int nblk_el = (E + EPB - 1) / EPB;
@@ -203,13 +217,17 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->P = info.DIM == 1 ? c->n1 : c->n1 * c->n1;
   c->NFP = info.DIM == 1 ? 1 : c->n1;
   c->E = cfg->nelem[0] * ny;
-  c->nblk_pre = (c->E + 255) / 256;
+  {
+    const int epb = epb_runtime(c->N, c->DIM, c->M);
+    c->nblk_pre = (c->E + epb - 1) / epb;  // k_pre: 256/P elements per block
+    c->nblk_ch = (c->E + 255) / 256;       // k_ch: one thread per element
+  }
   c->rd = make_refdata(c->N);
   c->cfl = cfg->cfl_number > 0.0 ? cfg->cfl_number : fourier_cfl(c->N);
 
   KParams& kp = c->kp;
   std::memset(&kp, 0, sizeof(kp));
-  kp.nx = cfg->nelem[0]; kp.ny = ny; kp.E = c->E; kp.nblk_pre = c->nblk_pre;
+  kp.nx = cfg->nelem[0]; kp.ny = ny; kp.E = c->E; kp.nblk_pre = c->nblk_pre; kp.nblk_ch = c->nblk_ch;
   for (int d = 0; d < 2; ++d) {
     kp.dx[d] = d < info.DIM ? (cfg->hi[d] - cfg->lo[d]) / (d == 0 ? cfg->nelem[0] : ny) : 1.0;
     kp.inv_dx[d] = 1.0 / kp.dx[d];
@@ -233,7 +251,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   c->off_scal = take(8 * sizeof(double));
   c->off_part = take((size_t)c->nblk_pre * sizeof(double));
-  c->off_part2 = take((size_t)c->nblk_pre * sizeof(double));
+  c->off_part2 = take((size_t)c->nblk_ch * sizeof(double));
   c->off_speeds = take((size_t)c->E * 2 * c->DIM * sizeof(double));
   c->off_araw = take((size_t)c->E * sizeof(double));
   c->off_alpha = take((size_t)c->E * sizeof(double));

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(_HERE, "liblwfr.so")
+# LWFR_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIBPATH = os.environ.get("LWFR_LIBRARY", os.path.join(_HERE, "liblwfr.so"))
 ABI_VERSION = 1
 
 LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
