@@ -86,7 +86,11 @@ typedef struct {
   double alpha_max;      /* cap of the blending coefficient (0.5) */
   double alpha_min;      /* indicator clip threshold (1e-3) */
   double alpha_force;    /* >= 0: every alpha_e is this value; < 0: smoothness indicator */
+  uint32_t flags;        /* LWFR_CFG_* bits */
 } lwfr_config;
+
+/* lwfr_config.flags: reserve the workspace of lwfr_adjoint_step */
+#define LWFR_CFG_ADJOINT 1u
 
 /* Validates cfg and builds the reference element, tableau and launch shapes on
  * the host.  No device work.  *out receives a context owned by the caller
@@ -129,6 +133,17 @@ lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, doub
  * scheme only (alpha = 1, no limiting); 2: as configured.  d_R must not alias d_u. */
 lwfr_status lwfr_residual(lwfr_ctx* ctx, const double* d_u, double dt, int32_t mode, double* d_R);
 
+/* Adjoint of one step (reverse mode, hand-written): d_lam_n = (d u^{n+1}/d u^n)^T
+ * d_lam_np1 for the step from d_u_n with the time step dt > 0 (the one the
+ * forward step used), holding c_h, every alpha_e, the thetas of Algorithms 1
+ * and 2 and every max/abs branch at their values in that forward step
+ * (frozen switches).  The call re-runs the forward step internally (same
+ * result as lwfr_step with this dt), then sweeps it backwards.  All arrays
+ * have the state layout; d_lam_n must not alias d_u_n or d_lam_np1.  Needs a
+ * context created with LWFR_CFG_ADJOINT (else LWFR_E_STATE). */
+lwfr_status lwfr_adjoint_step(lwfr_ctx* ctx, const double* d_u_n, double dt, const double* d_lam_np1,
+                              double* d_lam_n);
+
 /* Synchronises the bound stream and returns the OR of the flags of every step
  * since the previous query (then clears it): LWFR_E_NONFINITE if a non-finite
  * value appeared, LWFR_E_INADMISSIBLE if a lower order update was inadmissible,
@@ -139,11 +154,12 @@ lwfr_status lwfr_query(lwfr_ctx* ctx, uint32_t* flags_or);
  * launch of the following calls, for at most max_launches launches (the rest
  * are not timed).  lwfr_timing_end synchronises the stream and fills, for each
  * kernel id (0 per-element means/indicator, 1 time step, 2 GLM speed candidates,
- * 3 GLM speed, 4 element stages, 5 faces, 6 update, 7 residual), the summed
+ * 3 GLM speed, 4 element stages, 5 faces, 6 update, 7 residual, 8 update adjoint,
+ * 9 face adjoint, 10 stage adjoint), the summed
  * milliseconds ms[k] and the number of timed launches launches[k]; both arrays
  * hold LWFR_TIMING_KERNELS entries.  Events are created on the host by the
  * library and released by lwfr_destroy. */
-#define LWFR_TIMING_KERNELS 8
+#define LWFR_TIMING_KERNELS 11
 lwfr_status lwfr_timing_begin(lwfr_ctx* ctx, int32_t max_launches);
 lwfr_status lwfr_timing_end(lwfr_ctx* ctx, double* ms, uint32_t* launches);
 

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/lwfr.h"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace lwfr;
@@ -35,6 +36,11 @@ struct lwfr_ctx {
   // workspace carving (byte offsets)
   size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr, off_untr,
       off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_flag, ws_bytes;
+  // adjoint workspace (only with LWFR_CFG_ADJOINT)
+  bool adjoint = false;
+  size_t off_uscr, off_grvol, off_gun, off_gFm, off_gFp, off_gDm, off_gDp, off_gFtr, off_gUtr, off_guntr, off_gsL,
+      off_gsR;
+  AdjParams ap;
   void* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -89,7 +95,10 @@ inline int epb_runtime(int N, int DIM, int M) {
   } while (0)
 
 // kernel ids reported by lwfr_timing_end
-enum { KID_PRE = 0, KID_DT, KID_CH, KID_CHFIN, KID_STAGES, KID_FACES, KID_UPDATE, KID_RESIDUAL, KID_COUNT };
+enum {
+  KID_PRE = 0, KID_DT, KID_CH, KID_CHFIN, KID_STAGES, KID_FACES, KID_UPDATE, KID_RESIDUAL,
+  KID_ADJ_UPDATE, KID_ADJ_FACES, KID_ADJ_STAGES, KID_COUNT
+};
 
 // Records an event before (open) and after (close) a launch when timing is on.
 struct TimedLaunch {
@@ -143,6 +152,51 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
               d_flags);
   return LWFR_OK;
+}
+
+// elements per workgroup of the adjoint kernels: about one wave
+template <int N>
+constexpr int epb_adj(int DIM) {
+  return DIM == 1 ? 64 / (N + 1) : (N == 1 ? 16 : N == 2 ? 7 : N == 3 ? 4 : 2);
+}
+
+template <class Ph, int N>
+lwfr_status launch_adjoint(lwfr_ctx* c, const KParams& kp, const double* u_n, const double* lam1, double* lam0) {
+  constexpr int DIM = Ph::DIM, P = ipow(N + 1, DIM), NFP = DIM == 1 ? 1 : N + 1;
+  constexpr int EPB = epb_adj<N>(DIM);
+  const int E = c->E;
+  hipStream_t s = c->stream;
+  const int nblk = (E + EPB - 1) / EPB;
+  LWFR_LAUNCH(KID_ADJ_UPDATE, "k_adj_update", (k_adj_update<Ph, N, EPB>), dim3(nblk), dim3(EPB * P), 0, s, kp, c->ap,
+              u_n, lam1);
+  const int nfp_total = DIM * E * NFP;
+  LWFR_LAUNCH(KID_ADJ_FACES, "k_adj_faces", (k_adj_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp,
+              c->ap, u_n);
+  LWFR_LAUNCH(KID_ADJ_STAGES, "k_adj_stages", (k_adj_stages<Ph, N, EPB>), dim3(nblk), dim3(EPB * P), 0, s, kp, c->ap,
+              u_n, lam0);
+  return LWFR_OK;
+}
+
+template <class Ph>
+lwfr_status launch_adjoint_n(lwfr_ctx* c, const KParams& kp, const double* u_n, const double* lam1, double* lam0) {
+  switch (c->N) {
+    case 1: return launch_adjoint<Ph, 1>(c, kp, u_n, lam1, lam0);
+    case 2: return launch_adjoint<Ph, 2>(c, kp, u_n, lam1, lam0);
+    case 3: return launch_adjoint<Ph, 3>(c, kp, u_n, lam1, lam0);
+    case 4: return launch_adjoint<Ph, 4>(c, kp, u_n, lam1, lam0);
+  }
+  return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
+}
+
+lwfr_status dispatch_adjoint(lwfr_ctx* c, const KParams& kp, const double* u_n, const double* lam1, double* lam0) {
+  switch (c->cfg.equation) {
+    case LWFR_EQ_SW1D: return launch_adjoint_n<SW1D>(c, kp, u_n, lam1, lam0);
+    case LWFR_EQ_SW2D: return launch_adjoint_n<SW2D>(c, kp, u_n, lam1, lam0);
+    case LWFR_EQ_GLMMHD2D: return launch_adjoint_n<MHD2D>(c, kp, u_n, lam1, lam0);
+    case LWFR_EQ_LINADV1D: return launch_adjoint_n<LinAdv1D>(c, kp, u_n, lam1, lam0);
+    case LWFR_EQ_VARADV1D: return launch_adjoint_n<VarAdv1D>(c, kp, u_n, lam1, lam0);
+  }
+  return fail(LWFR_E_UNSUPPORTED, "unknown equation");
 }
 
 template <class Ph>
@@ -266,6 +320,22 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_thf = take(nfpt * sizeof(double));
   c->off_guard = take(nfpt * sizeof(uint32_t));
   c->off_flag = take(sizeof(uint32_t));
+  c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
+  if (c->adjoint) {
+    const size_t nst = (size_t)c->M * c->E * c->P * sizeof(double);
+    c->off_uscr = take(nst);
+    c->off_grvol = take(nst);
+    c->off_gun = take(nst);
+    c->off_gFm = take(nfpt * c->M * sizeof(double));
+    c->off_gFp = take(nfpt * c->M * sizeof(double));
+    c->off_gDm = take(nfpt * c->M * sizeof(double));
+    c->off_gDp = take(nfpt * c->M * sizeof(double));
+    c->off_gFtr = take(nfpt * 2 * c->M * sizeof(double));
+    c->off_gUtr = take(nfpt * 2 * c->M * sizeof(double));
+    c->off_guntr = take(nfpt * 2 * c->M * sizeof(double));
+    c->off_gsL = take(nfpt * c->M * sizeof(double));
+    c->off_gsR = take(nfpt * c->M * sizeof(double));
+  }
   c->ws_bytes = off;
   *out = c;
   return LWFR_OK;
@@ -315,6 +385,20 @@ lwfr_status lwfr_bind(lwfr_ctx* c, void* d_ws, size_t bytes, void* stream) {
   kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
   kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
   kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
+  if (c->adjoint) {
+    AdjParams& ap = c->ap;
+    ap.g_rvol = reinterpret_cast<double*>(b + c->off_grvol);
+    ap.g_un = reinterpret_cast<double*>(b + c->off_gun);
+    ap.gFm = reinterpret_cast<double*>(b + c->off_gFm);
+    ap.gFp = reinterpret_cast<double*>(b + c->off_gFp);
+    ap.gDm = reinterpret_cast<double*>(b + c->off_gDm);
+    ap.gDp = reinterpret_cast<double*>(b + c->off_gDp);
+    ap.gFtr = reinterpret_cast<double*>(b + c->off_gFtr);
+    ap.gUtr = reinterpret_cast<double*>(b + c->off_gUtr);
+    ap.guntr = reinterpret_cast<double*>(b + c->off_guntr);
+    ap.gsL = reinterpret_cast<double*>(b + c->off_gsL);
+    ap.gsR = reinterpret_cast<double*>(b + c->off_gsR);
+  }
   hipError_t err = hipMemsetAsync(kp.flag_or, 0, sizeof(uint32_t), c->stream);
   if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(err));
   c->bound = true;
@@ -351,6 +435,24 @@ lwfr_status lwfr_residual(lwfr_ctx* c, const double* d_u, double dt, int32_t mod
   LWFR_LAUNCH(KID_RESIDUAL, "k_residual", k_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
               d_u, d_R, n, (const double*)kp.scal);
   return LWFR_OK;
+}
+
+lwfr_status lwfr_adjoint_step(lwfr_ctx* c, const double* d_u_n, double dt, const double* d_lam_np1,
+                              double* d_lam_n) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (!c->adjoint) return fail(LWFR_E_STATE, "context was created without LWFR_CFG_ADJOINT");
+  if (!d_u_n || !d_lam_np1 || !d_lam_n) return fail(LWFR_E_INVALID_ARG, "null pointer");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt must be positive and finite");
+  const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
+  if (ranges_overlap(d_lam_n, d_u_n, bytes) || ranges_overlap(d_lam_n, d_lam_np1, bytes))
+    return fail(LWFR_E_INVALID_ARG, "lam_n aliases an input");
+  KParams kp = c->kp;
+  kp.dt_in = dt;
+  double* uscr = reinterpret_cast<double*>(static_cast<char*>(c->ws) + c->off_uscr);
+  lwfr_status st = dispatch_step(c, kp, d_u_n, uscr, nullptr, nullptr, nullptr);
+  if (st != LWFR_OK) return st;
+  return dispatch_adjoint(c, kp, d_u_n, d_lam_np1, d_lam_n);
 }
 
 lwfr_status lwfr_query(lwfr_ctx* c, uint32_t* flags_or) {

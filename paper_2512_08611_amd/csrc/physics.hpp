@@ -46,6 +46,28 @@ struct SW1D {
   __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
     av = fabs(u[1] / u[0]); c = sqrt(pp.g * u[0]);
   }
+  // reverse mode: ub += (d f/d u)^T fb
+  template <int d>
+  __device__ static void flux_vjp(const double* u, const double* fb, double* ub, const PhysParams& pp) {
+    const double v = u[1] / u[0];
+    ub[0] += fb[1] * (-v * v + pp.g * u[0]);
+    ub[1] += fb[0] + fb[1] * 2.0 * v;
+  }
+  // ub += (d(B(u)w)/du)^T ob, wb += B(u)^T ob
+  template <int d>
+  __device__ static void ncprod_vjp(const double* u, const double* w, const double* ob, double* ub, double* wb,
+                                    const PhysParams& pp) {
+    ub[0] += ob[1] * pp.g * w[2];
+    wb[2] += ob[1] * pp.g * u[0];
+  }
+  template <int d>
+  __device__ static void sigma_vjp(const double* u, double sb, double* ub, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double v = u[1] * ir;
+    const double sg = v < 0.0 ? -1.0 : 1.0;
+    ub[0] += sb * (-sg * v * ir + 0.5 * pp.g / sqrt(pp.g * u[0]));
+    ub[1] += sb * sg * ir;
+  }
 };
 
 struct SW2D {
@@ -75,6 +97,31 @@ struct SW2D {
   template <int d>
   __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
     av = fabs(u[1 + d] / u[0]); c = sqrt(pp.g * u[0]);
+  }
+  template <int d>
+  __device__ static void flux_vjp(const double* u, const double* fb, double* ub, const PhysParams& pp) {
+    const double vel = u[1 + d] / u[0];
+    double velb = 0.0;
+    ub[1 + d] += fb[0];
+    ub[1] += fb[1] * vel; velb += fb[1] * u[1];
+    ub[2] += fb[2] * vel; velb += fb[2] * u[2];
+    ub[0] += fb[1 + d] * pp.g * u[0];
+    ub[1 + d] += velb / u[0];
+    ub[0] -= velb * vel / u[0];
+  }
+  template <int d>
+  __device__ static void ncprod_vjp(const double* u, const double* w, const double* ob, double* ub, double* wb,
+                                    const PhysParams& pp) {
+    ub[0] += ob[1 + d] * pp.g * w[3];
+    wb[3] += ob[1 + d] * pp.g * u[0];
+  }
+  template <int d>
+  __device__ static void sigma_vjp(const double* u, double sb, double* ub, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double v = u[1 + d] * ir;
+    const double sg = v < 0.0 ? -1.0 : 1.0;
+    ub[0] += sb * (-sg * v * ir + 0.5 * pp.g / sqrt(pp.g * u[0]));
+    ub[1 + d] += sb * sg * ir;
   }
 };
 
@@ -158,6 +205,149 @@ struct MHD2D {
   __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
     av = fabs(u[1 + d] / u[0]); c = cfast<d>(u, pp);
   }
+
+  // ---- reverse mode (hand-written adjoints of flux, ncprod and sigma above)
+  template <int d>
+  __device__ static void flux_vjp(const double* u, const double* fb, double* ub, const PhysParams& pp) {
+    const double rho = u[0], ir = 1.0 / rho;
+    const double v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    const double* B = u + 5;
+    const double psi = u[8];
+    const double bb = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double gm1 = pp.gamma - 1.0, g1 = pp.gamma / gm1;
+    const double p = gm1 * (u[4] - 0.5 * rho * vv - 0.5 * bb - 0.5 * psi * psi);
+    const double vB = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    const double vd = v[d], Bd = B[d], md = u[1 + d];
+    double vb[3] = {0.0, 0.0, 0.0}, Bb[3] = {0.0, 0.0, 0.0};
+    double rhob = 0.0, mdb = 0.0, pb = 0.0, bbb = 0.0, vvb = 0.0, vBb = 0.0, psib = 0.0, Eb = 0.0;
+    mdb += fb[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      mdb += fb[1 + k] * v[k];
+      vb[k] += fb[1 + k] * md;
+      Bb[d] -= fb[1 + k] * B[k];
+      Bb[k] -= fb[1 + k] * Bd;
+    }
+    pb += fb[1 + d];
+    bbb += 0.5 * fb[1 + d];
+    const double T = 0.5 * rho * vv + g1 * p + bb;
+    vb[d] += fb[4] * T;
+    rhob += fb[4] * vd * 0.5 * vv;
+    vvb += fb[4] * vd * 0.5 * rho;
+    pb += fb[4] * vd * g1;
+    bbb += fb[4] * vd;
+    Bb[d] -= fb[4] * vB;
+    vBb -= fb[4] * Bd;
+    psib += fb[4] * pp.ch * Bd;
+    Bb[d] += fb[4] * pp.ch * psi;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k == d) continue;
+      vb[d] += fb[5 + k] * B[k];
+      Bb[k] += fb[5 + k] * vd;
+      Bb[d] -= fb[5 + k] * v[k];
+      vb[k] -= fb[5 + k] * Bd;
+    }
+    psib += fb[5 + d] * pp.ch;
+    Bb[d] += fb[8] * pp.ch;
+    // intermediates
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { vb[k] += vBb * B[k]; Bb[k] += vBb * v[k]; }
+    Eb += pb * gm1;
+    rhob -= pb * gm1 * 0.5 * vv;
+    vvb -= pb * gm1 * 0.5 * rho;
+    bbb -= pb * gm1 * 0.5;
+    psib -= pb * gm1 * psi;
+    double irb = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      vb[k] += 2.0 * vvb * v[k];
+      Bb[k] += 2.0 * bbb * B[k];
+    }
+    double mb[3] = {0.0, 0.0, 0.0};
+    mb[d] += mdb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { mb[k] += vb[k] * ir; irb += vb[k] * u[1 + k]; }
+    rhob -= irb * ir * ir;
+    ub[0] += rhob;
+    ub[1] += mb[0]; ub[2] += mb[1]; ub[3] += mb[2];
+    ub[4] += Eb;
+    ub[5] += Bb[0]; ub[6] += Bb[1]; ub[7] += Bb[2];
+    ub[8] += psib;
+  }
+  template <int d>
+  __device__ static void ncprod_vjp(const double* u, const double* w, const double* ob, double* ub, double* wb,
+                                    const PhysParams&) {
+    const double ir = 1.0 / u[0];
+    const double v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    const double vd = v[d];
+    const double dB = w[5 + d], dpsi = w[8];
+    const double vB = v[0] * u[5] + v[1] * u[6] + v[2] * u[7];
+    double dBb = 0.0, dpsib = 0.0, vBb = 0.0;
+    double vb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      dBb += ob[1 + k] * u[5 + k] + ob[5 + k] * v[k];
+      ub[5 + k] += ob[1 + k] * dB;
+      vb[k] += ob[5 + k] * dB;
+    }
+    dBb += ob[4] * vB;
+    vBb += ob[4] * dB;
+    dpsib += ob[4] * vd * u[8] + ob[8] * vd;
+    vb[d] += ob[4] * dpsi * u[8] + ob[8] * dpsi;
+    ub[8] += ob[4] * dpsi * vd;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { vb[k] += vBb * u[5 + k]; ub[5 + k] += vBb * v[k]; }
+    double irb = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { ub[1 + k] += vb[k] * ir; irb += vb[k] * u[1 + k]; }
+    ub[0] -= irb * ir * ir;
+    wb[5 + d] += dBb;
+    wb[8] += dpsib;
+  }
+  template <int d>
+  __device__ static void sigma_vjp(const double* u, double sb, double* ub, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double vdv = u[1 + d] * ir;
+    const double sg = vdv < 0.0 ? -1.0 : 1.0;
+    double irb = 0.0;
+    ub[1 + d] += sb * sg * ir;
+    irb += sb * sg * u[1 + d];
+    const double cf = cfast<d>(u, pp);
+    if (cf >= pp.ch) {
+      // cf = sqrt(X), X = (s + R)/2, R = sqrt(s^2 - 4 a2 bd2), s = a2 + b2
+      const double mm = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+      const double bb = u[5] * u[5] + u[6] * u[6] + u[7] * u[7];
+      const double gm1 = pp.gamma - 1.0;
+      const double p = gm1 * (u[4] - 0.5 * mm * ir - 0.5 * bb - 0.5 * u[8] * u[8]);
+      const double a2 = pp.gamma * p * ir, b2 = bb * ir, bd2 = u[5 + d] * u[5 + d] * ir;
+      const double s = a2 + b2;
+      const double R = sqrt(s * s - 4.0 * a2 * bd2);
+      const double Xb = sb / (2.0 * cf);
+      double sbar = 0.5 * Xb;
+      const double Rb = 0.5 * Xb;
+      const double Db = R > 0.0 ? Rb / (2.0 * R) : 0.0;
+      sbar += 2.0 * s * Db;
+      const double a2b = -4.0 * bd2 * Db + sbar;
+      const double bd2b = -4.0 * a2 * Db;
+      const double b2b = sbar;
+      double pb = a2b * pp.gamma * ir;
+      irb += a2b * pp.gamma * p + b2b * bb + bd2b * u[5 + d] * u[5 + d];
+      double bbb = b2b * ir;
+      ub[5 + d] += bd2b * 2.0 * u[5 + d] * ir;
+      // p = (gamma-1)(E - mm ir/2 - bb/2 - psi^2/2)
+      ub[4] += pb * gm1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ub[1 + k] -= pb * gm1 * u[1 + k] * ir;
+      irb -= pb * gm1 * 0.5 * mm;
+      bbb -= pb * gm1 * 0.5;
+      ub[8] -= pb * gm1 * u[8];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ub[5 + k] += 2.0 * bbb * u[5 + k];
+    }
+    ub[0] -= irb * ir * ir;
+  }
 };
 
 // Linear advection u_t + u_x = 0.
@@ -170,6 +360,12 @@ struct LinAdv1D {
   __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
   __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
   template <int d> __device__ static void speeds(const double*, double& av, double& c, const PhysParams&) { av = 0.0; c = 1.0; }
+  template <int d> __device__ static void flux_vjp(const double*, const double* fb, double* ub, const PhysParams&) {
+    ub[0] += fb[0];
+  }
+  template <int d>
+  __device__ static void ncprod_vjp(const double*, const double*, const double*, double*, double*, const PhysParams&) {}
+  template <int d> __device__ static void sigma_vjp(const double*, double, double*, const PhysParams&) {}
 };
 
 // Variable-coefficient advection as a non-conservative system: u = (v, a),
@@ -186,6 +382,16 @@ struct VarAdv1D {
   __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
   template <int d> __device__ static void speeds(const double* u, double& av, double& c, const PhysParams&) {
     av = 0.0; c = fabs(u[1]);
+  }
+  template <int d> __device__ static void flux_vjp(const double*, const double*, double*, const PhysParams&) {}
+  template <int d>
+  __device__ static void ncprod_vjp(const double* u, const double* w, const double* ob, double* ub, double* wb,
+                                    const PhysParams&) {
+    ub[1] += ob[0] * w[0];
+    wb[0] += ob[0] * u[1];
+  }
+  template <int d> __device__ static void sigma_vjp(const double* u, double sb, double* ub, const PhysParams&) {
+    ub[1] += sb * (u[1] < 0.0 ? -1.0 : 1.0);
   }
 };
 

@@ -16,6 +16,7 @@ ABI_VERSION = 1
 LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
 LWFR_E_INADMISSIBLE, LWFR_E_NONFINITE, LWFR_E_WORKSPACE, LWFR_E_STATE = 4, 5, 6, 7
 LWFR_EQ_SW1D, LWFR_EQ_SW2D, LWFR_EQ_GLMMHD2D, LWFR_EQ_LINADV1D, LWFR_EQ_VARADV1D = 1, 2, 3, 4, 5
+LWFR_CFG_ADJOINT = 1
 LWFR_FLAG_ALG2, LWFR_FLAG_LOW_INADM, LWFR_FLAG_ALG1, LWFR_FLAG_NONFINITE, LWFR_FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
 
 NVARS = {1: 3, 2: 4, 3: 9, 4: 1, 5: 2}
@@ -44,6 +45,7 @@ class lwfr_config(ctypes.Structure):
         ("alpha_max", ctypes.c_double),
         ("alpha_min", ctypes.c_double),
         ("alpha_force", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -59,11 +61,13 @@ _SIGS = {
                   ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_residual": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p],
     "lwfr_query": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],
+    "lwfr_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_timing_begin": [ctypes.c_void_p, ctypes.c_int32],
     "lwfr_timing_end": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32)],
     "lwfr_destroy": [ctypes.c_void_p],
 }
-TIMING_KERNELS = ("k_pre", "k_dt", "k_ch", "k_ch_fin", "k_stages", "k_faces", "k_update", "k_residual")
+TIMING_KERNELS = ("k_pre", "k_dt", "k_ch", "k_ch_fin", "k_stages", "k_faces", "k_update", "k_residual",
+                  "k_adj_update", "k_adj_faces", "k_adj_stages")
 
 
 def lib():
@@ -97,7 +101,8 @@ def _ptr(t):
 
 
 def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81,
-                cfl_safety=0.9, cfl_number=0.0, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0):
+                cfl_safety=0.9, cfl_number=0.0, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0,
+                flags=0):
     c = lwfr_config()
     c.abi_version = ABI_VERSION
     c.equation, c.degree = equation, degree
@@ -107,6 +112,7 @@ def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0
     c.hi[0], c.hi[1] = hi
     c.gamma, c.gravity, c.cfl_safety, c.cfl_number = gamma, gravity, cfl_safety, cfl_number
     c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
+    c.flags = flags
     return c
 
 
@@ -157,6 +163,10 @@ def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
 
 def lwfr_residual(ctx, u, dt, mode, R):
     _check(lib().lwfr_residual(ctx, _ptr(u), float(dt), int(mode), _ptr(R)))
+
+
+def lwfr_adjoint_step(ctx, u_n, dt, lam_np1, lam_n):
+    _check(lib().lwfr_adjoint_step(ctx, _ptr(u_n), float(dt), _ptr(lam_np1), _ptr(lam_n)))
 
 
 def lwfr_query(ctx):
@@ -215,6 +225,9 @@ class Stepper:
 
     def query(self):
         return lwfr_query(self.ctx)
+
+    def adjoint_step(self, u_n, dt, lam_np1, lam_n):
+        lwfr_adjoint_step(self.ctx, u_n, dt, lam_np1, lam_n)
 
     def close(self):
         if self.ctx is not None:
