@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline sample")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 256 MiB (reference kernel for the HBM byte counters)")
     return ap.parse_args()
@@ -76,6 +77,35 @@ def cpu_baseline(u0, n, N, steps):
         "sample": f"{steps} steps of the full {n}x{n} N={N} GLM-MHD workload, single-threaded C++ oracle "
                   f"({dt:.1f} s)",
     }
+
+
+def adjoint_over_forward(torch, lwfr, workloads, np, n=128, N=3, steps=20, every=5, reps=3):
+    """Backward (checkpoint recomputation + adjoint steps) time over forward time of a
+    differentiable rollout: GLM-MHD n x n, degree N, `steps` steps, checkpoint every `every`."""
+    from paper_2512_08611_amd import rollout
+
+    dev = torch.device("cuda:0")
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), blending=2, flags=lwfr.LWFR_CFG_ADJOINT)
+    st = lwfr.Stepper(cfg, dev)
+    u0 = torch.tensor(workloads.mhd_smooth(np.array(st.xi), n, n, seed=0), dtype=torch.float64, device=dev)
+    tf, tb = [], []
+    for r in range(reps + 1):
+        x = u0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        y = rollout.rollout(x, st, steps, every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * torch.sum(y[0] ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r > 0:  # the first repetition warms up
+            tf.append(t1 - t0)
+            tb.append(t2 - t1)
+    f, b = min(tf), min(tb)
+    return {"ratio": b / f, "forward_ms": f * 1e3, "backward_ms": b * 1e3,
+            "workload": f"GLM-MHD {n}x{n} N={N}, {steps} steps, checkpoint every {every}"}
 
 
 def main():
@@ -166,6 +196,8 @@ def main():
         "flags_or": int(flags),
         "adjoint_over_forward": None,
     }
+    if not args.no_adjoint:
+        out["adjoint_over_forward"] = adjoint_over_forward(torch, lwfr, workloads, np)
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

@@ -128,21 +128,38 @@ lwfr_status lwfr_bind(lwfr_ctx* ctx, void* d_workspace, size_t bytes, void* stre
 lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
                       double* d_alpha, uint32_t* d_flags);
 
+/* One time step with both dt > 0 and the GLM cleaning speed ch >= 0 given
+ * (ignored by systems without GLM), e.g. to replay a step sequence with the
+ * values of an earlier run.  Otherwise as lwfr_step. */
+lwfr_status lwfr_step_fixed(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double ch,
+                            double* d_alpha, uint32_t* d_flags);
+
 /* Residual R = (u^n - u^{n+1})/dt of one step with the given dt > 0.
  * mode 0: high order only (alpha = 0, no limiting); 1: lower order subcell
  * scheme only (alpha = 1, no limiting); 2: as configured.  d_R must not alias d_u. */
 lwfr_status lwfr_residual(lwfr_ctx* ctx, const double* d_u, double dt, int32_t mode, double* d_R);
 
+/* Bytes of one step's tape: the values a forward step hands to the adjoint
+ * (dt and c_h, alpha_e, the thetas of Algorithms 1 and 2, the face traces of
+ * u^n and of the time-averaged solution U).  256-byte alignment required. */
+lwfr_status lwfr_tape_bytes(const lwfr_ctx* ctx, size_t* bytes);
+
+/* A forward step like lwfr_step (dt > 0 given, <= 0 from eq. time.step.2d)
+ * that writes its tape to d_tape (caller-owned device memory of
+ * lwfr_tape_bytes), for a later lwfr_adjoint_step of the same step. */
+lwfr_status lwfr_step_taped(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
+                            void* d_tape);
+
 /* Adjoint of one step (reverse mode, hand-written): d_lam_n = (d u^{n+1}/d u^n)^T
  * d_lam_np1 for the step from d_u_n with the time step dt > 0 (the one the
  * forward step used), holding c_h, every alpha_e, the thetas of Algorithms 1
  * and 2 and every max/abs branch at their values in that forward step
- * (frozen switches).  The call re-runs the forward step internally (same
- * result as lwfr_step with this dt), then sweeps it backwards.  All arrays
- * have the state layout; d_lam_n must not alias d_u_n or d_lam_np1.  Needs a
- * context created with LWFR_CFG_ADJOINT (else LWFR_E_STATE). */
+ * (frozen switches).  d_tape: the tape lwfr_step_taped wrote for this very
+ * step, or NULL, in which case the call re-runs the forward step internally
+ * first.  All arrays have the state layout; d_lam_n must not alias d_u_n or
+ * d_lam_np1.  Needs a context created with LWFR_CFG_ADJOINT (else LWFR_E_STATE). */
 lwfr_status lwfr_adjoint_step(lwfr_ctx* ctx, const double* d_u_n, double dt, const double* d_lam_np1,
-                              double* d_lam_n);
+                              double* d_lam_n, const void* d_tape);
 
 /* Synchronises the bound stream and returns the OR of the flags of every step
  * since the previous query (then clears it): LWFR_E_NONFINITE if a non-finite

@@ -39,6 +39,7 @@ struct KParams {
   double ind_T, ind_s;        // indicator threshold T(N) and logistic sharpness s
   double cs_cfl;              // C_s * CFL(N)
   double dt_in;               // > 0: fixed time step
+  double ch_in;               // >= 0: fixed GLM cleaning speed
   // workspace
   double* scal;               // [0] dt, [1] c_h, [2] Lambda
   double* part;               // per-block partial maxima / minima
@@ -208,8 +209,9 @@ __global__ void __launch_bounds__(256) k_dt(const KParams kp, double* d_dt_ch, i
     kp.scal[0] = dt;
     kp.scal[2] = lam;
     if (!has_ch) {
-      kp.scal[1] = 0.0;
-      if (d_dt_ch) { d_dt_ch[0] = dt; d_dt_ch[1] = 0.0; }
+      const double ch = kp.ch_in >= 0.0 ? kp.ch_in : 0.0;
+      kp.scal[1] = ch;
+      if (d_dt_ch) { d_dt_ch[0] = dt; d_dt_ch[1] = ch; }
     }
   }
 }

@@ -41,6 +41,8 @@ struct lwfr_ctx {
   size_t off_uscr, off_grvol, off_gun, off_gFm, off_gFp, off_gDm, off_gDp, off_gFtr, off_gUtr, off_guntr, off_gsL,
       off_gsR;
   AdjParams ap;
+  // per-step tape: what the reverse kernels read from a forward step
+  size_t tp_scal, tp_alpha, tp_thf, tp_thel, tp_untr, tp_Utr, tape_bytes;
   void* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -137,7 +139,7 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   constexpr int EPB = epb_for<N>(DIM, Ph::M);
   const int E = c->E;
   hipStream_t s = c->stream;
-  const bool has_ch = std::is_same<Ph, MHD2D>::value;
+  const bool has_ch = std::is_same<Ph, MHD2D>::value && kp.ch_in < 0.0;
   LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N, EPB>), dim3(c->nblk_pre), dim3(EPB * P), 0, s, kp, u_in);
   LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(256), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
   if (has_ch) {
@@ -223,6 +225,18 @@ lwfr_status dispatch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, do
   return fail(LWFR_E_UNSUPPORTED, "unknown equation");
 }
 
+// kernel parameters whose switch and trace arrays live in a caller's tape
+KParams with_tape(const lwfr_ctx* c, KParams kp, void* tape) {
+  char* t = static_cast<char*>(tape);
+  kp.scal = reinterpret_cast<double*>(t + c->tp_scal);
+  kp.alpha = reinterpret_cast<double*>(t + c->tp_alpha);
+  kp.theta_face = reinterpret_cast<double*>(t + c->tp_thf);
+  kp.theta_elem = reinterpret_cast<double*>(t + c->tp_thel);
+  kp.untr = reinterpret_cast<double*>(t + c->tp_untr);
+  kp.Utr = reinterpret_cast<double*>(t + c->tp_Utr);
+  return kp;
+}
+
 bool ranges_overlap(const void* a, const void* b, size_t bytes) {
   const char* x = static_cast<const char*>(a);
   const char* y = static_cast<const char*>(b);
@@ -298,6 +312,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   kp.ind_T = 0.5 * std::pow(10.0, -1.8 * std::pow(c->N + 1.0, 0.25));
   kp.ind_s = std::log(9999.0);
   kp.cs_cfl = cfg->cfl_safety * c->cfl;
+  kp.ch_in = -1.0;
 
   // workspace carving
   const size_t nfpt = (size_t)c->DIM * c->E * c->NFP;  // face points over all directions
@@ -337,6 +352,17 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     c->off_gsR = take(nfpt * c->M * sizeof(double));
   }
   c->ws_bytes = off;
+  {
+    size_t t = 0;
+    auto tk = [&](size_t bytes) { size_t o = t; t += align256(bytes); return o; };
+    c->tp_scal = tk(8 * sizeof(double));
+    c->tp_alpha = tk((size_t)c->E * sizeof(double));
+    c->tp_thf = tk(nfpt * sizeof(double));
+    c->tp_thel = tk((size_t)c->E * sizeof(double));
+    c->tp_untr = tk(nfpt * 2 * c->M * sizeof(double));
+    c->tp_Utr = tk(nfpt * 2 * c->M * sizeof(double));
+    c->tape_bytes = t;
+  }
   *out = c;
   return LWFR_OK;
 }
@@ -415,7 +441,23 @@ lwfr_status lwfr_step(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double
   if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
   KParams kp = c->kp;
   kp.dt_in = dt > 0.0 ? dt : 0.0;
+  kp.ch_in = -1.0;
   return dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, d_alpha, d_flags);
+}
+
+lwfr_status lwfr_step_fixed(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double ch,
+                            double* d_alpha, uint32_t* d_flags) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (!d_u_in || !d_u_out) return fail(LWFR_E_INVALID_ARG, "null state pointer");
+  const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
+  if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt must be positive and finite");
+  if (!(ch >= 0.0) || !std::isfinite(ch)) return fail(LWFR_E_INVALID_ARG, "ch must be >= 0 and finite");
+  KParams kp = c->kp;
+  kp.dt_in = dt;
+  kp.ch_in = ch;
+  return dispatch_step(c, kp, d_u_in, d_u_out, nullptr, d_alpha, d_flags);
 }
 
 lwfr_status lwfr_residual(lwfr_ctx* c, const double* d_u, double dt, int32_t mode, double* d_R) {
@@ -437,8 +479,29 @@ lwfr_status lwfr_residual(lwfr_ctx* c, const double* d_u, double dt, int32_t mod
   return LWFR_OK;
 }
 
+lwfr_status lwfr_tape_bytes(const lwfr_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(LWFR_E_INVALID_ARG, "null argument");
+  *bytes = c->tape_bytes;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_step_taped(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
+                            void* d_tape) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (!d_u_in || !d_u_out || !d_tape) return fail(LWFR_E_INVALID_ARG, "null pointer");
+  if (reinterpret_cast<uintptr_t>(d_tape) % 256 != 0) return fail(LWFR_E_INVALID_ARG, "tape not 256-byte aligned");
+  const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
+  if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
+  if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
+  KParams kp = with_tape(c, c->kp, d_tape);
+  kp.dt_in = dt > 0.0 ? dt : 0.0;
+  kp.ch_in = -1.0;
+  return dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, nullptr, nullptr);
+}
+
 lwfr_status lwfr_adjoint_step(lwfr_ctx* c, const double* d_u_n, double dt, const double* d_lam_np1,
-                              double* d_lam_n) {
+                              double* d_lam_n, const void* d_tape) {
   if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
   if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
   if (!c->adjoint) return fail(LWFR_E_STATE, "context was created without LWFR_CFG_ADJOINT");
@@ -449,9 +512,14 @@ lwfr_status lwfr_adjoint_step(lwfr_ctx* c, const double* d_u_n, double dt, const
     return fail(LWFR_E_INVALID_ARG, "lam_n aliases an input");
   KParams kp = c->kp;
   kp.dt_in = dt;
-  double* uscr = reinterpret_cast<double*>(static_cast<char*>(c->ws) + c->off_uscr);
-  lwfr_status st = dispatch_step(c, kp, d_u_n, uscr, nullptr, nullptr, nullptr);
-  if (st != LWFR_OK) return st;
+  if (d_tape) {
+    if (reinterpret_cast<uintptr_t>(d_tape) % 256 != 0) return fail(LWFR_E_INVALID_ARG, "tape not 256-byte aligned");
+    kp = with_tape(c, kp, const_cast<void*>(d_tape));
+  } else {
+    double* uscr = reinterpret_cast<double*>(static_cast<char*>(c->ws) + c->off_uscr);
+    lwfr_status st = dispatch_step(c, kp, d_u_n, uscr, nullptr, nullptr, nullptr);
+    if (st != LWFR_OK) return st;
+  }
   return dispatch_adjoint(c, kp, d_u_n, d_lam_np1, d_lam_n);
 }
 

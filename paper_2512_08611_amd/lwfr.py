@@ -59,9 +59,15 @@ _SIGS = {
     "lwfr_bind": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "lwfr_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p],
+    "lwfr_step_fixed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                        ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_residual": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p],
     "lwfr_query": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],
-    "lwfr_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p],
+    "lwfr_adjoint_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p],
+    "lwfr_tape_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lwfr_step_taped": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                        ctypes.c_void_p],
     "lwfr_timing_begin": [ctypes.c_void_p, ctypes.c_int32],
     "lwfr_timing_end": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32)],
     "lwfr_destroy": [ctypes.c_void_p],
@@ -161,12 +167,26 @@ def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
     _check(lib().lwfr_step(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(alpha), _ptr(flags)))
 
 
+def lwfr_step_fixed(ctx, u_in, u_out, dt, ch, alpha=None, flags=None):
+    _check(lib().lwfr_step_fixed(ctx, _ptr(u_in), _ptr(u_out), float(dt), float(ch), _ptr(alpha), _ptr(flags)))
+
+
 def lwfr_residual(ctx, u, dt, mode, R):
     _check(lib().lwfr_residual(ctx, _ptr(u), float(dt), int(mode), _ptr(R)))
 
 
-def lwfr_adjoint_step(ctx, u_n, dt, lam_np1, lam_n):
-    _check(lib().lwfr_adjoint_step(ctx, _ptr(u_n), float(dt), _ptr(lam_np1), _ptr(lam_n)))
+def lwfr_adjoint_step(ctx, u_n, dt, lam_np1, lam_n, tape=None):
+    _check(lib().lwfr_adjoint_step(ctx, _ptr(u_n), float(dt), _ptr(lam_np1), _ptr(lam_n), _ptr(tape)))
+
+
+def lwfr_tape_bytes(ctx):
+    n = ctypes.c_size_t()
+    _check(lib().lwfr_tape_bytes(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def lwfr_step_taped(ctx, u_in, u_out, dt, dt_ch, tape):
+    _check(lib().lwfr_step_taped(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(tape)))
 
 
 def lwfr_query(ctx):
@@ -220,14 +240,29 @@ class Stepper:
     def step(self, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
         lwfr_step(self.ctx, u_in, u_out, dt, dt_ch, alpha, flags)
 
+    def step_fixed(self, u_in, u_out, dt, ch, alpha=None, flags=None):
+        lwfr_step_fixed(self.ctx, u_in, u_out, dt, ch, alpha, flags)
+
     def residual(self, u, dt, mode, R):
         lwfr_residual(self.ctx, u, dt, mode, R)
 
     def query(self):
         return lwfr_query(self.ctx)
 
-    def adjoint_step(self, u_n, dt, lam_np1, lam_n):
-        lwfr_adjoint_step(self.ctx, u_n, dt, lam_np1, lam_n)
+    def adjoint_step(self, u_n, dt, lam_np1, lam_n, tape=None):
+        lwfr_adjoint_step(self.ctx, u_n, dt, lam_np1, lam_n, tape)
+
+    def new_tape(self):
+        """A 256-byte aligned device buffer for one step's tape."""
+        import torch
+
+        n = lwfr_tape_bytes(self.ctx)
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        return buf[off: off + n]
+
+    def step_taped(self, u_in, u_out, dt, tape, dt_ch=None):
+        lwfr_step_taped(self.ctx, u_in, u_out, dt, dt_ch, tape)
 
     def close(self):
         if self.ctx is not None:

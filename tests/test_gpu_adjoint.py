@@ -150,6 +150,25 @@ def test_full_jacobian_two_elements(eq, N, nx, ny, kind):
         assert np.abs(mu - ref).max() <= 1e-10 * np.abs(ref).max(), np.abs(mu - ref).max() / np.abs(ref).max()
 
 
+@pytest.mark.parametrize("eq,N,nx,ny,kind", [(oracle.EQ_MHD2D, 3, 5, 4, "blocky"), (oracle.EQ_SW1D, 4, 13, 1, "rough")])
+def test_taped_adjoint_equals_recomputing_adjoint(eq, N, nx, ny, kind):
+    st, oc = make(eq, N, nx, ny, 2)
+    u = torch.tensor(data(eq, N, nx, ny, 4, kind), dtype=torch.float64, device=DEV)
+    dt = oracle.dt_ch(oc, u.cpu().numpy())[0]
+    lam = torch.randn(u.shape, dtype=torch.float64, device=DEV, generator=torch.Generator(DEV).manual_seed(3))
+    tape = st.new_tape()
+    out = torch.empty_like(u)
+    st.step_taped(u, out, dt, tape)
+    ref = torch.empty_like(u)
+    st.step(u, ref, dt)
+    assert torch.equal(out, ref)
+    a, b = torch.empty_like(u), torch.empty_like(u)
+    st.adjoint_step(u, dt, lam, a)
+    st.adjoint_step(u, dt, lam, b, tape)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_adjoint_requires_flag():
     cfg = lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 8)
     st = lwfr.Stepper(cfg, DEV)
