@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-problem measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 256 MiB (reference kernel for the HBM byte counters)")
     return ap.parse_args()
@@ -106,6 +107,62 @@ def adjoint_over_forward(torch, lwfr, workloads, np, n=128, N=3, steps=20, every
     f, b = min(tf), min(tb)
     return {"ratio": b / f, "forward_ms": f * 1e3, "backward_ms": b * 1e3,
             "workload": f"GLM-MHD {n}x{n} N={N}, {steps} steps, checkpoint every {every}"}
+
+
+def batched(torch, lwfr, workloads, np, steps=50, count=64):
+    """64 independent 2-D shallow-water problems (sizes n ~ U{32..256}, degrees
+    N ~ U{2,3,4}, seed 0; bed and depth from seeded cosine modes), advanced with
+    one launch per phase per step, launch shapes from the library's autotuner,
+    `steps` steps captured in one HIP graph and replayed (the first replay warms up)."""
+    dev = torch.device("cuda:0")
+    specs = workloads.sw2d_batch_specs(count, seed=0)
+    cfgs = [lwfr.make_config(lwfr.LWFR_EQ_SW2D, N, (n, n), cfl_safety=0.9, blending=2) for n, N in specs]
+    stream = torch.cuda.Stream(dev)
+    b = lwfr.Batch(cfgs, dev, stream=stream)
+    u0 = b.empty()
+    for i, (n, N) in enumerate(specs):
+        xi, _ = lwfr.lwfr_reference_nodes(b.problem(i), N + 1)
+        b.view(u0, i).copy_(torch.tensor(workloads.sw2d_random(np.array(xi), n, seed=1000 + i)))
+    dofs = sum(n * n * (N + 1) ** 2 for n, N in specs)
+    scratch = b.empty()
+    torch.cuda.synchronize()
+    b.autotune(u0, scratch, reps=3)
+    shapes = {name: b.get_launch(ph) for ph, name in enumerate(("pre", "stages", "faces", "update"))}
+    # eager steps with per-kernel timing
+    b.timing_begin(64)
+    b.step(u0, scratch)
+    kern = b.timing_end()
+    ua, ub = b.empty(), b.empty()
+    ua.copy_(u0)
+    torch.cuda.synchronize()
+    b.graph_capture(ua, ub, steps)
+    b.graph_launch()  # warm-up replay
+    torch.cuda.synchronize()
+    ua.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.graph_launch()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        b.step(ua if k % 2 == 0 else ub, ub if k % 2 == 0 else ua)
+    torch.cuda.synchronize()
+    wall_eager = time.perf_counter() - t0
+    status, flags = b.query()
+    return {
+        "workload": f"{count} 2-D shallow-water problems with bathymetry, n~U{{32..256}}^2 elements, "
+                    f"N~U{{2,3,4}} (seed 0), {dofs} DOF, {steps} graph-captured steps",
+        "value": dofs * steps / wall,
+        "unit": "DOF-updates/s",
+        "ms_per_step": wall / steps * 1e3,
+        "ms_per_step_eager": wall_eager / steps * 1e3,
+        "dof": dofs,
+        "launch_shapes": {k: {"tile_threads": v[0], "grid": v[1], "xcd": v[2]} for k, v in shapes.items()},
+        "kernels_ms_per_step": {k: ms for k, (ms, cnt) in kern.items() if cnt},
+        "step_status": int(status),
+        "flags_or": int(flags),
+    }
 
 
 def main():
@@ -195,9 +252,12 @@ def main():
         "step_status": int(status),
         "flags_or": int(flags),
         "adjoint_over_forward": None,
+        "batched": None,
     }
     if not args.no_adjoint:
         out["adjoint_over_forward"] = adjoint_over_forward(torch, lwfr, workloads, np)
+    if not args.no_batch:
+        out["batched"] = batched(torch, lwfr, workloads, np)
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

@@ -172,15 +172,85 @@ lwfr_status lwfr_query(lwfr_ctx* ctx, uint32_t* flags_or);
  * are not timed).  lwfr_timing_end synchronises the stream and fills, for each
  * kernel id (0 per-element means/indicator, 1 time step, 2 GLM speed candidates,
  * 3 GLM speed, 4 element stages, 5 faces, 6 update, 7 residual, 8 update adjoint,
- * 9 face adjoint, 10 stage adjoint), the summed
- * milliseconds ms[k] and the number of timed launches launches[k]; both arrays
- * hold LWFR_TIMING_KERNELS entries.  Events are created on the host by the
- * library and released by lwfr_destroy. */
-#define LWFR_TIMING_KERNELS 11
+ * 9 face adjoint, 10 stage adjoint; batches: 11 means/indicator, 12 time steps,
+ * 13 element stages, 14 faces, 15 update), the summed milliseconds ms[k] and the
+ * number of timed launches launches[k]; both arrays hold LWFR_TIMING_KERNELS
+ * entries.  Events are created on the host by the library and released by
+ * lwfr_destroy.  Launches inside a graph capture are not timed. */
+#define LWFR_TIMING_KERNELS 16
 lwfr_status lwfr_timing_begin(lwfr_ctx* ctx, int32_t max_launches);
 lwfr_status lwfr_timing_end(lwfr_ctx* ctx, double* ms, uint32_t* launches);
 
+/* Captures nsteps consecutive steps (dt from eq. time.step.2d on the device each
+ * step, as lwfr_step with dt <= 0) into a HIP graph owned by the context,
+ * replacing any earlier one: step k reads d_u_a and writes d_u_b for even k,
+ * the reverse for odd k, so the result is in d_u_a for even nsteps.
+ * d_dt_ch_hist (nullable, device, nsteps x 2) receives each step's (dt, c_h).
+ * The graph holds kernel launches only (no memory set or copy nodes).  Needs a
+ * bound non-default stream (else LWFR_E_STATE).  Nothing runs until
+ * lwfr_graph_launch, which enqueues the whole sequence on the bound stream;
+ * the pointers are baked into the graph and must stay valid. */
+lwfr_status lwfr_graph_capture(lwfr_ctx* ctx, double* d_u_a, double* d_u_b, int32_t nsteps, double* d_dt_ch_hist);
+lwfr_status lwfr_graph_launch(lwfr_ctx* ctx);
+
 lwfr_status lwfr_destroy(lwfr_ctx* ctx);
+
+/* ---- Batches -------------------------------------------------------------
+ * Many independent problems of one equation system (currently the 2-D shallow
+ * water system), of any mix of sizes and degrees 1..4, advanced together with
+ * one launch per phase of the step (means and indicator, per-problem time
+ * steps, element stages, faces, update).  Each problem takes its own time step
+ * from eq. time.step.2d.  The batch state is the concatenation of the
+ * problems' states, problem i starting at offsets[i] doubles
+ * (lwfr_batch_state_offsets fills count+1 entries; offsets[count] is the
+ * total), each in the layout of lwfr_state_size.  Results equal those of
+ * lwfr_step on each problem alone. */
+typedef struct lwfr_batch lwfr_batch;
+
+/* Phases whose launch shape can be set (lwfr_batch_set_launch) */
+enum {
+  LWFR_PHASE_PRE = 0,    /* element means, indicator (and the per-problem time steps) */
+  LWFR_PHASE_STAGES = 1, /* element-local stages */
+  LWFR_PHASE_FACES = 2,  /* interface fluxes and Algorithm 1 */
+  LWFR_PHASE_UPDATE = 3  /* update, subcell FV, blend, Algorithm 2 */
+};
+
+/* cfgs[0..count) as for lwfr_init (same equation for all, no
+ * LWFR_CFG_ADJOINT).  Errors: those of lwfr_init (message names the problem),
+ * LWFR_E_UNSUPPORTED for another equation system. */
+lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch** out);
+lwfr_status lwfr_batch_workspace_bytes(const lwfr_batch* batch, size_t* bytes);
+lwfr_status lwfr_batch_state_offsets(const lwfr_batch* batch, int64_t* offsets);
+/* The context of problem i (owned by the batch; use it for lwfr_state_size,
+ * lwfr_reference_nodes; it is bound to the batch workspace and stream). */
+lwfr_status lwfr_batch_problem(lwfr_batch* batch, int32_t i, lwfr_ctx** ctx);
+/* Caller-owned device workspace (256-byte aligned, lwfr_batch_workspace_bytes)
+ * and stream; uploads the problem table synchronously. */
+lwfr_status lwfr_batch_bind(lwfr_batch* batch, void* d_ws, size_t bytes, void* hip_stream);
+/* One step of every problem; d_dt (nullable, device, count doubles) receives
+ * each problem's dt.  d_u_out must not overlap d_u_in. */
+lwfr_status lwfr_batch_step(lwfr_batch* batch, const double* d_u_in, double* d_u_out, double* d_dt);
+/* Launch shape of a phase: tile_threads 256 or 128 threads per tile of
+ * elements (floor(tile_threads/P) elements each; faces: 256 face points),
+ * grid workgroups walking the tiles (0: one workgroup per tile), xcd 1 to give
+ * each XCD a contiguous range of tiles.  Results do not depend on the shape. */
+lwfr_status lwfr_batch_set_launch(lwfr_batch* batch, int32_t phase, int32_t tile_threads, int32_t grid, int32_t xcd);
+lwfr_status lwfr_batch_get_launch(const lwfr_batch* batch, int32_t phase, int32_t* tile_threads, int32_t* grid,
+                                  int32_t* xcd);
+/* Autotuner: times every launch shape of every phase (tile_threads x grid in
+ * {one per tile, 1024, 2048, 4096, 8192} x xcd, best of reps launches) on the
+ * state d_u_in and keeps the fastest; d_u_out is used as scratch and holds one
+ * step from d_u_in on return.  Synchronises the stream. */
+lwfr_status lwfr_batch_autotune(lwfr_batch* batch, const double* d_u_in, double* d_u_out, int32_t reps);
+/* As lwfr_graph_capture for the batch: d_dt_hist (nullable, nsteps x count). */
+lwfr_status lwfr_batch_graph_capture(lwfr_batch* batch, double* d_u_a, double* d_u_b, int32_t nsteps,
+                                     double* d_dt_hist);
+lwfr_status lwfr_batch_graph_launch(lwfr_batch* batch);
+/* As lwfr_query, over every problem of the batch. */
+lwfr_status lwfr_batch_query(lwfr_batch* batch, uint32_t* flags_or);
+lwfr_status lwfr_batch_timing_begin(lwfr_batch* batch, int32_t max_launches);
+lwfr_status lwfr_batch_timing_end(lwfr_batch* batch, double* ms, uint32_t* launches);
+lwfr_status lwfr_batch_destroy(lwfr_batch* batch);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* lwfr_last_error(void);

@@ -1,0 +1,171 @@
+// Batched kernels: many independent problems of one equation system, of any
+// mix of sizes and degrees 1..4, advanced by one launch per phase of the step.
+//
+// The problems' states are concatenated, each in its own [var][elem][node]
+// layout at an offset.  A tile table maps every tile (one block of elements of
+// the per-point phases, or 256 face points of the face phase) to its problem
+// and to the block index within that problem; the kernels run exactly the same
+// device bodies as the single-problem kernels, selected by the problem's degree.
+//
+// Launches are persistent: a grid of G workgroups walks the tile table.  With
+// G a multiple of 8 and the XCD option set, workgroup b (dispatched to XCD
+// b mod 8) takes its tiles from the (b mod 8)-th contiguous eighth of the
+// table, so the tiles one XCD works on are neighbours in memory and their face
+// neighbours are mostly in the same L2.  The time step of each problem comes
+// from its own reduction (kb_dt, one workgroup per problem).
+#pragma once
+#include "kernels.hpp"
+
+namespace lwfr {
+
+struct BatchArgs {
+  const KParams* kps;     // [ninst] per-problem parameters (device memory)
+  const long long* uoff;  // [ninst] offset of each problem's state, in doubles
+  const int* tinst;       // [ntiles] problem of each tile
+  const int* tblk;        // [ntiles] block index of the tile within its problem
+  int ntiles;
+  int xcd;                // 1: XCD-contiguous tile ranges (needs gridDim.x % 8 == 0)
+  double* part;           // [ntiles] per-tile maximum of Lambda_e (pre phase)
+};
+
+__device__ inline void tile_range(int ntiles, int xcd, int& t0, int& t1, int& step) {
+  const int G = gridDim.x;
+  if (xcd && (G & 7) == 0) {
+    const int x = blockIdx.x & 7, w = blockIdx.x >> 3, per = (ntiles + 7) >> 3;
+    t0 = x * per + w;
+    t1 = min(ntiles, (x + 1) * per);
+    step = G >> 3;
+  } else {
+    t0 = blockIdx.x;
+    t1 = ntiles;
+    step = G;
+  }
+}
+
+// elements per tile of the batched per-point phases with NT threads
+template <int N, int NT>
+constexpr int batch_epb(int DIM) {
+  return NT / ipow(N + 1, DIM);
+}
+
+template <template <class, int, int> class Lds, class Ph, int NT>
+union LdsByDegree {
+  Lds<Ph, 1, NT> n1;
+  Lds<Ph, 2, NT> n2;
+  Lds<Ph, 3, NT> n3;
+  Lds<Ph, 4, NT> n4;
+};
+
+template <class Ph, int NT>
+__global__ void __launch_bounds__(NT) kb_pre(const BatchArgs ba, const double* __restrict__ u) {
+  constexpr int DIM = Ph::DIM;
+  __shared__ LdsByDegree<PreLds, Ph, NT> L;
+  int t0, t1, step;
+  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
+  for (int t = t0; t < t1; t += step) {
+    const int inst = ba.tinst[t], blk = ba.tblk[t];
+    const KParams& kp = ba.kps[inst];
+    const double* un = u + ba.uoff[inst];
+    double* po = ba.part + t;
+    switch (kp.N) {
+      case 1: pre_body<Ph, 1, batch_epb<1, NT>(DIM), NT>(kp, L.n1, un, blk, po); break;
+      case 2: pre_body<Ph, 2, batch_epb<2, NT>(DIM), NT>(kp, L.n2, un, blk, po); break;
+      case 3: pre_body<Ph, 3, batch_epb<3, NT>(DIM), NT>(kp, L.n3, un, blk, po); break;
+      default: pre_body<Ph, 4, batch_epb<4, NT>(DIM), NT>(kp, L.n4, un, blk, po); break;
+    }
+    __syncthreads();
+  }
+}
+
+// one workgroup per problem: Lambda = max over the problem's tiles, dt
+// (eq. time.step.2d) unless the problem's dt is fixed
+__global__ void __launch_bounds__(256) kb_dt(const BatchArgs ba, const int* __restrict__ tile_begin,
+                                             double* d_dt) {
+  __shared__ double s_max[256];
+  const int inst = blockIdx.x;
+  const KParams& kp = ba.kps[inst];
+  double m = 0.0;
+  for (int i = tile_begin[inst] + threadIdx.x; i < tile_begin[inst + 1]; i += blockDim.x) m = fmax(m, ba.part[i]);
+  s_max[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double lam = s_max[0];
+    const double dt = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
+    kp.scal[0] = dt;
+    kp.scal[1] = kp.ch_in >= 0.0 ? kp.ch_in : 0.0;
+    kp.scal[2] = lam;
+    if (d_dt) d_dt[inst] = dt;
+  }
+}
+
+// The batched kernels hold the registers of their largest degree; the hint
+// keeps the stage kernel at two waves per SIMD, as the single-problem stage
+// kernel of degree 4 (a few registers spill).
+template <class Ph, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+    kb_stages(const BatchArgs ba, const double* __restrict__ u_in, double* __restrict__ u_out) {
+  constexpr int DIM = Ph::DIM;
+  __shared__ LdsByDegree<StagesLds, Ph, NT> L;
+  int t0, t1, step;
+  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
+  for (int t = t0; t < t1; t += step) {
+    const int inst = ba.tinst[t], blk = ba.tblk[t];
+    const KParams& kp = ba.kps[inst];
+    const double* un = u_in + ba.uoff[inst];
+    double* rv = u_out + ba.uoff[inst];
+    switch (kp.N) {
+      case 1: stages_body<Ph, 1, batch_epb<1, NT>(DIM), NT>(kp, L.n1, un, rv, nullptr, blk); break;
+      case 2: stages_body<Ph, 2, batch_epb<2, NT>(DIM), NT>(kp, L.n2, un, rv, nullptr, blk); break;
+      case 3: stages_body<Ph, 3, batch_epb<3, NT>(DIM), NT>(kp, L.n3, un, rv, nullptr, blk); break;
+      default: stages_body<Ph, 4, batch_epb<4, NT>(DIM), NT>(kp, L.n4, un, rv, nullptr, blk); break;
+    }
+    __syncthreads();
+  }
+}
+
+// face phase: tiles of 256 face points
+template <class Ph>
+__global__ void __launch_bounds__(256) kb_faces(const BatchArgs ba, const double* __restrict__ u_in) {
+  int t0, t1, step;
+  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
+  for (int t = t0; t < t1; t += step) {
+    const int inst = ba.tinst[t];
+    const int gid = ba.tblk[t] * 256 + threadIdx.x;
+    const KParams& kp = ba.kps[inst];
+    const double* un = u_in + ba.uoff[inst];
+    switch (kp.N) {
+      case 1: faces_body<Ph, 1>(kp, un, gid); break;
+      case 2: faces_body<Ph, 2>(kp, un, gid); break;
+      case 3: faces_body<Ph, 3>(kp, un, gid); break;
+      default: faces_body<Ph, 4>(kp, un, gid); break;
+    }
+  }
+}
+
+template <class Ph, int NT>
+__global__ void __launch_bounds__(NT) kb_update(const BatchArgs ba, const double* __restrict__ u_in,
+                                                double* __restrict__ io) {
+  constexpr int DIM = Ph::DIM;
+  __shared__ LdsByDegree<UpdateLds, Ph, NT> L;
+  int t0, t1, step;
+  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
+  for (int t = t0; t < t1; t += step) {
+    const int inst = ba.tinst[t], blk = ba.tblk[t];
+    const KParams& kp = ba.kps[inst];
+    const double* un = u_in + ba.uoff[inst];
+    double* o = io + ba.uoff[inst];
+    switch (kp.N) {
+      case 1: update_body<Ph, 1, batch_epb<1, NT>(DIM), NT>(kp, L.n1, un, o, nullptr, blk); break;
+      case 2: update_body<Ph, 2, batch_epb<2, NT>(DIM), NT>(kp, L.n2, un, o, nullptr, blk); break;
+      case 3: update_body<Ph, 3, batch_epb<3, NT>(DIM), NT>(kp, L.n3, un, o, nullptr, blk); break;
+      default: update_body<Ph, 4, batch_epb<4, NT>(DIM), NT>(kp, L.n4, un, o, nullptr, blk); break;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace lwfr

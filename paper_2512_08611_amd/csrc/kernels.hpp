@@ -29,6 +29,7 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 // everything a kernel needs besides the state pointers, passed by value
 struct KParams {
   int nx, ny, E, nblk_pre, nblk_ch;
+  int N;                      // degree (the batched kernels dispatch on it)
   double dx[2], inv_dx[2];
   double D[kMaxN1][kMaxN1], VL[kMaxN1], VR[kMaxN1], w[kMaxN1], gR[kMaxN1], gL[kMaxN1];
   double Leg[kMaxN1][kMaxN1];
@@ -82,17 +83,33 @@ __device__ inline double theta_limit(double eps, double Pa, double Pb, bool& gua
 // k_pre: one thread per solution point, EPB elements per block (coalesced
 // loads); per element: mean state, ideal wave speeds, Lambda_e and the raw
 // smoothness indicator; per block: the maximum of Lambda_e.
-template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams kp, const double* __restrict__ un) {
+//
+// The per-point kernels are written as device bodies over one block of EPB
+// elements (block index blk) so that the single-problem kernels and the
+// batched kernels (several problems, one launch) run the same code.  A block
+// of NT threads has ceil(NT/P) element slots in LDS; slots at or beyond EPB
+// hold no element (their threads only take part in the barriers).
+template <class Ph, int N, int NT>
+struct PreLds {
+  static constexpr int P = ipow(N + 1, Ph::DIM), EL = (NT + P - 1) / P;
+  double s_u[EL][Ph::M][P];
+  double s_q[EL][P];
+  double s_ub[EL][Ph::M];
+  double s_lam[EL];
+};
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L, const double* __restrict__ un,
+                                         int blk, double* part_out) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
-  __shared__ double s_u[EPB][M][P];
-  __shared__ double s_q[EPB][P];
-  __shared__ double s_ub[EPB][M];
-  __shared__ double s_lam[EPB];
+  auto& s_u = L.s_u;
+  auto& s_q = L.s_q;
+  auto& s_ub = L.s_ub;
+  auto& s_lam = L.s_lam;
   const int tid = threadIdx.x;
   const int le = tid / P, p = tid - le * P;
-  const int e = blockIdx.x * EPB + le;
-  const bool act = e < kp.E;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
   const PhysParams pp{kp.g, kp.gamma, 0.0};
   const bool want_alpha = kp.blending >= 1 && kp.alpha_force < 0.0;
   double x[M];
@@ -188,8 +205,15 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams
   if (tid == 0) {
     double m = s_lam[0];
     for (int l = 1; l < EPB; ++l) m = fmax(m, s_lam[l]);
-    kp.part[blockIdx.x] = m;
+    part_out[0] = m;
   }
+}
+
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams kp, const double* __restrict__ un) {
+  constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
+  __shared__ PreLds<Ph, N, NT> L;
+  pre_body<Ph, N, EPB, NT>(kp, L, un, blockIdx.x, kp.part + blockIdx.x);
 }
 
 // k_dt: one block; Lambda and dt
@@ -272,20 +296,28 @@ __host__ __device__ constexpr int first_nz(int t) {
   return -1;
 }
 
-template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
-    k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
+template <class Ph, int N, int NT>
+struct StagesLds {
+  static constexpr int DIM = Ph::DIM, M = Ph::M, P = ipow(N + 1, DIM), EL = (NT + P - 1) / P;
+  static constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
+  static constexpr int NBUF = (DIM * M + DIM * NCD) > (DIM * M + M) ? (DIM * M + DIM * NCD) : (DIM * M + M);
+  double s_buf[EL][NBUF][P];
+};
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, NT>& L,
+                                            const double* __restrict__ un_g, double* __restrict__ rvol_g,
+                                            double* d_alpha_out, int blk) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
   constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
   using Tab = Tableau<N>;
   constexpr int S = Tab::S;
-  constexpr int NBUF = (DIM * M + DIM * NCD) > (DIM * M + M) ? (DIM * M + DIM * NCD) : (DIM * M + M);
-  __shared__ double s_buf[EPB][NBUF][P];
+  auto& s_buf = L.s_buf;
 
   const int tid = threadIdx.x;
   const int le = tid / P, p = tid - le * P;
-  const int e = blockIdx.x * EPB + le;
-  const bool act = e < kp.E;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
   const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
@@ -436,6 +468,14 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdg
   }
 }
 
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
+    k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
+  __shared__ StagesLds<Ph, N, NT> L;
+  stages_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // lower order fluxes f^{num,-}, f^{num,+}(uL, uR) of eq. combined.num.flux
 template <class Ph, int d>
@@ -569,10 +609,9 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
 }
 
 template <class Ph, int N>
-__global__ void __launch_bounds__(256) k_faces(const KParams kp, const double* __restrict__ un_g) {
+__device__ __forceinline__ void faces_body(const KParams& kp, const double* __restrict__ un_g, int gid) {
   constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
   const int nf = kp.E * NFP;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= DIM * nf) return;
   const int d = gid / nf;
   const int fi = gid - d * nf;
@@ -583,25 +622,41 @@ __global__ void __launch_bounds__(256) k_faces(const KParams kp, const double* _
   else if constexpr (DIM == 2) face_point<Ph, N, 1>(kp, un_g, e, q, dt, pp);
 }
 
+template <class Ph, int N>
+__global__ void __launch_bounds__(256) k_faces(const KParams kp, const double* __restrict__ un_g) {
+  faces_body<Ph, N>(kp, un_g, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // k_update: one thread per solution point.  High order update (eq.
 // crkfr.non.cons.final), subcell FV update (eq. low.order.update), blend
 // (eq. blended.scheme) and Algorithm 2.  io holds R_vol on entry and u^{n+1}
 // on exit.
-template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
-    k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
+template <class Ph, int N, int NT>
+struct UpdateLds {
+  static constexpr int M = Ph::M, P = ipow(N + 1, Ph::DIM), EL = (NT + P - 1) / P;
+  double s_u[EL][M][P];
+  double s_f[EL][M][P];     // f_d at the nodes (one direction at a time)
+  double s_left[EL][M][P];  // f^{num,+} of the subface left of each node
+  double s_red[EL][P];      // sigma_d at the nodes / reductions
+  uint32_t s_fl[EL][P];
+};
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, NT>& L,
+                                            const double* __restrict__ un_g, double* __restrict__ io,
+                                            uint32_t* d_flags, int blk) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
-  __shared__ double s_u[EPB][M][P];
-  __shared__ double s_f[EPB][M][P];     // f_d at the nodes (one direction at a time)
-  __shared__ double s_left[EPB][M][P];  // f^{num,+} of the subface left of each node
-  __shared__ double s_red[EPB][P];      // sigma_d at the nodes / reductions
-  __shared__ uint32_t s_fl[EPB][P];
+  auto& s_u = L.s_u;
+  auto& s_f = L.s_f;
+  auto& s_left = L.s_left;
+  auto& s_red = L.s_red;
+  auto& s_fl = L.s_fl;
 
   const int tid = threadIdx.x;
   const int le = tid / P, p = tid - le * P;
-  const int e = blockIdx.x * EPB + le;
-  const bool act = e < kp.E;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
   const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
@@ -765,6 +820,14 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
     if (d_flags) d_flags[e] = f;
     if (f & 10u) atomicOr(kp.flag_or, f);
   }
+}
+
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+    k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
+  constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
+  __shared__ UpdateLds<Ph, N, NT> L;
+  update_body<Ph, N, EPB, NT>(kp, L, un_g, io, d_flags, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ u, double* __restrict__ R, size_t n,

@@ -9,6 +9,7 @@
 
 #include "../../include/lwfr.h"
 #include "adjoint.hpp"
+#include "batch.hpp"
 #include "kernels.hpp"
 
 using namespace lwfr;
@@ -23,6 +24,14 @@ lwfr_status fail(lwfr_status s, const std::string& msg) {
 }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// optional per-kernel timing with HIP events on the bound stream
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kernel;  // kernel id of the launch between event 2i and 2i+1
+  size_t used = 0;
+};
 
 }  // namespace
 
@@ -46,11 +55,8 @@ struct lwfr_ctx {
   void* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
-  // optional per-kernel timing with HIP events on the bound stream
-  bool timing = false;
-  std::vector<hipEvent_t> ev;
-  std::vector<int> ev_kernel;  // kernel id of the launch between event 2i and 2i+1
-  size_t ev_used = 0;
+  Timing tm;
+  hipGraphExec_t graph = nullptr;  // captured step sequence (lwfr_graph_capture)
 };
 
 namespace {
@@ -99,25 +105,28 @@ inline int epb_runtime(int N, int DIM, int M) {
 // kernel ids reported by lwfr_timing_end
 enum {
   KID_PRE = 0, KID_DT, KID_CH, KID_CHFIN, KID_STAGES, KID_FACES, KID_UPDATE, KID_RESIDUAL,
-  KID_ADJ_UPDATE, KID_ADJ_FACES, KID_ADJ_STAGES, KID_COUNT
+  KID_ADJ_UPDATE, KID_ADJ_FACES, KID_ADJ_STAGES, KID_B_PRE, KID_B_DT, KID_B_STAGES, KID_B_FACES, KID_B_UPDATE,
+  KID_COUNT
 };
+static_assert(KID_COUNT == LWFR_TIMING_KERNELS, "kernel ids and LWFR_TIMING_KERNELS disagree");
 
 // Records an event before (open) and after (close) a launch when timing is on.
 struct TimedLaunch {
-  lwfr_ctx* c;
+  Timing& tm;
+  hipStream_t s;
   int kid;
   bool on;
-  TimedLaunch(lwfr_ctx* c_, int kid_) : c(c_), kid(kid_), on(false) {
-    if (c->timing && c->ev_used + 2 <= c->ev.size()) {
+  TimedLaunch(Timing& tm_, hipStream_t s_, int kid_) : tm(tm_), s(s_), kid(kid_), on(false) {
+    if (tm.on && tm.used + 2 <= tm.ev.size()) {
       on = true;
-      (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+      (void)hipEventRecord(tm.ev[tm.used], s);
     }
   }
   void close() {
     if (on) {
-      (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
-      c->ev_kernel[c->ev_used / 2] = kid;
-      c->ev_used += 2;
+      (void)hipEventRecord(tm.ev[tm.used + 1], s);
+      tm.kernel[tm.used / 2] = kid;
+      tm.used += 2;
       on = false;
     }
   }
@@ -125,7 +134,7 @@ struct TimedLaunch {
 
 #define LWFR_LAUNCH(kid, name, ...)          \
   do {                                       \
-    TimedLaunch tl_(c, kid);                 \
+    TimedLaunch tl_(c->tm, c->stream, kid);  \
     hipLaunchKernelGGL(__VA_ARGS__);         \
     tl_.close();                             \
     LWFR_CHECK_LAUNCH(name);                 \
@@ -243,6 +252,236 @@ bool ranges_overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
+lwfr_status timing_begin(Timing& tm, int32_t max_launches) {
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(LWFR_E_INVALID_ARG, "max_launches out of range");
+  const size_t need = 2 * (size_t)max_launches;
+  while (tm.ev.size() < need) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
+    tm.ev.push_back(e);
+  }
+  tm.kernel.assign(tm.ev.size() / 2, -1);
+  tm.used = 0;
+  tm.on = true;
+  return LWFR_OK;
+}
+
+lwfr_status timing_end(Timing& tm, hipStream_t s, double* ms, uint32_t* launches) {
+  if (!tm.on) return fail(LWFR_E_STATE, "timing was not begun");
+  tm.on = false;
+  hipError_t err = hipStreamSynchronize(s);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("timing end: ") + hipGetErrorString(err));
+  for (int k = 0; k < LWFR_TIMING_KERNELS; ++k) { ms[k] = 0.0; launches[k] = 0; }
+  for (size_t i = 0; i + 1 < tm.used; i += 2) {
+    float t = 0.0f;
+    err = hipEventElapsedTime(&t, tm.ev[i], tm.ev[i + 1]);
+    if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(err));
+    const int kid = tm.kernel[i / 2];
+    if (kid >= 0 && kid < LWFR_TIMING_KERNELS) { ms[kid] += t; launches[kid] += 1; }
+  }
+  return LWFR_OK;
+}
+
+// Captures nsteps calls of step(k) on stream s into an executable graph
+// (replacing *exec).  Timing is suspended during the capture.
+template <class F>
+lwfr_status capture(hipStream_t s, Timing& tm, hipGraphExec_t& exec, int nsteps, F&& step) {
+  if (!s) return fail(LWFR_E_STATE, "graph capture needs a non-default stream");
+  const bool timing = tm.on;
+  tm.on = false;
+  hipError_t err = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (err != hipSuccess) { tm.on = timing; return fail(LWFR_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(err)); }
+  lwfr_status st = LWFR_OK;
+  for (int k = 0; k < nsteps && st == LWFR_OK; ++k) st = step(k);
+  hipGraph_t g = nullptr;
+  err = hipStreamEndCapture(s, &g);
+  tm.on = timing;
+  if (st != LWFR_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+  if (err != hipSuccess) { if (g) (void)hipGraphDestroy(g); return fail(LWFR_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(err)); }
+  hipGraphExec_t ge = nullptr;
+  err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err));
+  if (exec) (void)hipGraphExecDestroy(exec);
+  exec = ge;
+  return LWFR_OK;
+}
+
+// points the context's workspace arrays into the buffer at b
+void carve(lwfr_ctx* c, char* b) {
+  KParams& kp = c->kp;
+  kp.scal = reinterpret_cast<double*>(b + c->off_scal);
+  kp.part = reinterpret_cast<double*>(b + c->off_part);
+  kp.part2 = reinterpret_cast<double*>(b + c->off_part2);
+  kp.speeds = reinterpret_cast<double*>(b + c->off_speeds);
+  kp.alpha_raw = reinterpret_cast<double*>(b + c->off_araw);
+  kp.alpha = reinterpret_cast<double*>(b + c->off_alpha);
+  kp.theta_elem = reinterpret_cast<double*>(b + c->off_thel);
+  kp.Ftr = reinterpret_cast<double*>(b + c->off_Ftr);
+  kp.Utr = reinterpret_cast<double*>(b + c->off_Utr);
+  kp.untr = reinterpret_cast<double*>(b + c->off_untr);
+  kp.Fm = reinterpret_cast<double*>(b + c->off_Fm);
+  kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
+  kp.Dm = reinterpret_cast<double*>(b + c->off_Dm);
+  kp.Dp = reinterpret_cast<double*>(b + c->off_Dp);
+  kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
+  kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
+  kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
+  if (c->adjoint) {
+    AdjParams& ap = c->ap;
+    ap.g_rvol = reinterpret_cast<double*>(b + c->off_grvol);
+    ap.g_un = reinterpret_cast<double*>(b + c->off_gun);
+    ap.gFm = reinterpret_cast<double*>(b + c->off_gFm);
+    ap.gFp = reinterpret_cast<double*>(b + c->off_gFp);
+    ap.gDm = reinterpret_cast<double*>(b + c->off_gDm);
+    ap.gDp = reinterpret_cast<double*>(b + c->off_gDp);
+    ap.gFtr = reinterpret_cast<double*>(b + c->off_gFtr);
+    ap.gUtr = reinterpret_cast<double*>(b + c->off_gUtr);
+    ap.guntr = reinterpret_cast<double*>(b + c->off_guntr);
+    ap.gsL = reinterpret_cast<double*>(b + c->off_gsL);
+    ap.gsR = reinterpret_cast<double*>(b + c->off_gsR);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches: independent problems of one equation system advanced together, one
+// launch per phase (batch.hpp).  Each problem keeps its own lwfr_ctx (for its
+// parameters and workspace carving); the batch workspace holds a header (the
+// problems' KParams, state offsets, tile tables, per-tile partial maxima, the
+// flag word) followed by the problems' workspaces.
+
+struct BatchTable {     // one tile table
+  int tile_threads = 0;  // threads per tile (per-point phases) or 256 (faces)
+  int ntiles = 0;
+  std::vector<int> tinst, tblk, tile_begin;  // tile_begin: [ninst+1]
+  size_t off_tinst = 0, off_tblk = 0, off_tb = 0;
+};
+
+struct BatchLaunch {    // launch shape of one phase
+  int tile_threads = 256;
+  int grid = 0;          // workgroups; 0: one per tile
+  int xcd = 1;
+};
+
+struct lwfr_batch {
+  std::vector<lwfr_ctx*> inst;
+  int equation = 0;
+  std::vector<long long> uoff;  // [ninst+1] state offsets (doubles)
+  BatchTable tab[2];            // per-point phases with 256 and 128 threads per tile
+  BatchTable ftab;              // face phase
+  size_t off_kps = 0, off_uoff = 0, off_part = 0, off_flag = 0, hdr_bytes = 0, ws_bytes = 0;
+  std::vector<size_t> off_inst;
+  std::vector<char> hdr;        // host image of the header
+  BatchLaunch launch[4];        // LWFR_PHASE_*
+  void* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  Timing tm;
+  hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+const BatchTable& table_for(const lwfr_batch* b, int phase) {
+  if (phase == LWFR_PHASE_FACES) return b->ftab;
+  return b->launch[phase].tile_threads == 128 ? b->tab[1] : b->tab[0];
+}
+
+BatchArgs batch_args(const lwfr_batch* b, const BatchTable& t, const BatchLaunch& l) {
+  char* w = static_cast<char*>(b->ws);
+  BatchArgs ba;
+  ba.kps = reinterpret_cast<const KParams*>(w + b->off_kps);
+  ba.uoff = reinterpret_cast<const long long*>(w + b->off_uoff);
+  ba.tinst = reinterpret_cast<const int*>(w + t.off_tinst);
+  ba.tblk = reinterpret_cast<const int*>(w + t.off_tblk);
+  ba.ntiles = t.ntiles;
+  ba.xcd = l.xcd;
+  ba.part = reinterpret_cast<double*>(w + b->off_part);
+  return ba;
+}
+
+dim3 batch_grid(const BatchLaunch& l, int ntiles) {
+  long long g = l.grid > 0 ? l.grid : ntiles;
+  if (l.xcd) g = (g + 7) / 8 * 8;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+template <class Ph>
+lwfr_status batch_phase(lwfr_batch* c, int phase, const double* u_in, double* u_out, double* d_dt) {
+  const BatchLaunch& l = c->launch[phase];
+  const BatchTable& t = table_for(c, phase);
+  const BatchArgs ba = batch_args(c, t, l);
+  const dim3 g = batch_grid(l, t.ntiles);
+  hipStream_t s = c->stream;
+  const bool big = l.tile_threads != 128;
+  switch (phase) {
+    case LWFR_PHASE_PRE:
+      if (big) LWFR_LAUNCH(KID_B_PRE, "kb_pre", (kb_pre<Ph, 256>), g, dim3(256), 0, s, ba, u_in);
+      else LWFR_LAUNCH(KID_B_PRE, "kb_pre", (kb_pre<Ph, 128>), g, dim3(128), 0, s, ba, u_in);
+      {
+        const int* tb = reinterpret_cast<const int*>(static_cast<char*>(c->ws) + t.off_tb);
+        LWFR_LAUNCH(KID_B_DT, "kb_dt", kb_dt, dim3((unsigned)c->inst.size()), dim3(256), 0, s, ba, tb, d_dt);
+      }
+      break;
+    case LWFR_PHASE_STAGES:
+      if (big) LWFR_LAUNCH(KID_B_STAGES, "kb_stages", (kb_stages<Ph, 256>), g, dim3(256), 0, s, ba, u_in, u_out);
+      else LWFR_LAUNCH(KID_B_STAGES, "kb_stages", (kb_stages<Ph, 128>), g, dim3(128), 0, s, ba, u_in, u_out);
+      break;
+    case LWFR_PHASE_FACES:
+      LWFR_LAUNCH(KID_B_FACES, "kb_faces", (kb_faces<Ph>), g, dim3(256), 0, s, ba, u_in);
+      break;
+    default:
+      if (big) LWFR_LAUNCH(KID_B_UPDATE, "kb_update", (kb_update<Ph, 256>), g, dim3(256), 0, s, ba, u_in, u_out);
+      else LWFR_LAUNCH(KID_B_UPDATE, "kb_update", (kb_update<Ph, 128>), g, dim3(128), 0, s, ba, u_in, u_out);
+      break;
+  }
+  return LWFR_OK;
+}
+
+lwfr_status batch_phase_any(lwfr_batch* b, int phase, const double* u_in, double* u_out, double* d_dt) {
+  switch (b->equation) {
+    case LWFR_EQ_SW2D: return batch_phase<SW2D>(b, phase, u_in, u_out, d_dt);
+  }
+  return fail(LWFR_E_UNSUPPORTED, "batches support the 2-D shallow water system");
+}
+
+lwfr_status batch_step(lwfr_batch* b, const double* u_in, double* u_out, double* d_dt) {
+  for (int ph = 0; ph < 4; ++ph) {
+    lwfr_status st = batch_phase_any(b, ph, u_in, u_out, d_dt);
+    if (st != LWFR_OK) return st;
+  }
+  return LWFR_OK;
+}
+
+// time of one launch of `phase` with launch shape l (ms), after `before` runs
+// the untimed prerequisites; minimum over reps
+template <class F>
+lwfr_status time_phase(lwfr_batch* b, int phase, const BatchLaunch& l, const double* u_in, double* u_out, int reps,
+                       F&& before, hipEvent_t e0, hipEvent_t e1, float& best) {
+  const BatchLaunch keep = b->launch[phase];
+  b->launch[phase] = l;
+  best = 1e30f;
+  lwfr_status st = LWFR_OK;
+  for (int r = 0; r < reps && st == LWFR_OK; ++r) {
+    st = before();
+    if (st != LWFR_OK) break;
+    (void)hipEventRecord(e0, b->stream);
+    st = batch_phase_any(b, phase, u_in, u_out, nullptr);
+    (void)hipEventRecord(e1, b->stream);
+    hipError_t err = hipEventSynchronize(e1);
+    if (err != hipSuccess) { st = fail(LWFR_E_HIP, std::string("autotune: ") + hipGetErrorString(err)); break; }
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    best = t < best ? t : best;
+  }
+  b->launch[phase] = keep;
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -296,6 +535,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   KParams& kp = c->kp;
   std::memset(&kp, 0, sizeof(kp));
   kp.nx = cfg->nelem[0]; kp.ny = ny; kp.E = c->E; kp.nblk_pre = c->nblk_pre; kp.nblk_ch = c->nblk_ch;
+  kp.N = c->N;
   for (int d = 0; d < 2; ++d) {
     kp.dx[d] = d < info.DIM ? (cfg->hi[d] - cfg->lo[d]) / (d == 0 ? cfg->nelem[0] : ny) : 1.0;
     kp.inv_dx[d] = 1.0 / kp.dx[d];
@@ -392,39 +632,8 @@ lwfr_status lwfr_bind(lwfr_ctx* c, void* d_ws, size_t bytes, void* stream) {
   if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return fail(LWFR_E_WORKSPACE, "workspace not 256-byte aligned");
   c->ws = d_ws;
   c->stream = static_cast<hipStream_t>(stream);
-  char* b = static_cast<char*>(d_ws);
-  KParams& kp = c->kp;
-  kp.scal = reinterpret_cast<double*>(b + c->off_scal);
-  kp.part = reinterpret_cast<double*>(b + c->off_part);
-  kp.part2 = reinterpret_cast<double*>(b + c->off_part2);
-  kp.speeds = reinterpret_cast<double*>(b + c->off_speeds);
-  kp.alpha_raw = reinterpret_cast<double*>(b + c->off_araw);
-  kp.alpha = reinterpret_cast<double*>(b + c->off_alpha);
-  kp.theta_elem = reinterpret_cast<double*>(b + c->off_thel);
-  kp.Ftr = reinterpret_cast<double*>(b + c->off_Ftr);
-  kp.Utr = reinterpret_cast<double*>(b + c->off_Utr);
-  kp.untr = reinterpret_cast<double*>(b + c->off_untr);
-  kp.Fm = reinterpret_cast<double*>(b + c->off_Fm);
-  kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
-  kp.Dm = reinterpret_cast<double*>(b + c->off_Dm);
-  kp.Dp = reinterpret_cast<double*>(b + c->off_Dp);
-  kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
-  kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
-  kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
-  if (c->adjoint) {
-    AdjParams& ap = c->ap;
-    ap.g_rvol = reinterpret_cast<double*>(b + c->off_grvol);
-    ap.g_un = reinterpret_cast<double*>(b + c->off_gun);
-    ap.gFm = reinterpret_cast<double*>(b + c->off_gFm);
-    ap.gFp = reinterpret_cast<double*>(b + c->off_gFp);
-    ap.gDm = reinterpret_cast<double*>(b + c->off_gDm);
-    ap.gDp = reinterpret_cast<double*>(b + c->off_gDp);
-    ap.gFtr = reinterpret_cast<double*>(b + c->off_gFtr);
-    ap.gUtr = reinterpret_cast<double*>(b + c->off_gUtr);
-    ap.guntr = reinterpret_cast<double*>(b + c->off_guntr);
-    ap.gsL = reinterpret_cast<double*>(b + c->off_gsL);
-    ap.gsR = reinterpret_cast<double*>(b + c->off_gsR);
-  }
+  carve(c, static_cast<char*>(d_ws));
+  const KParams& kp = c->kp;
   hipError_t err = hipMemsetAsync(kp.flag_or, 0, sizeof(uint32_t), c->stream);
   if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(err));
   c->bound = true;
@@ -540,42 +749,317 @@ lwfr_status lwfr_query(lwfr_ctx* c, uint32_t* flags_or) {
 lwfr_status lwfr_timing_begin(lwfr_ctx* c, int32_t max_launches) {
   if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
   if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
-  if (max_launches < 1 || max_launches > (1 << 20)) return fail(LWFR_E_INVALID_ARG, "max_launches out of range");
-  const size_t need = 2 * (size_t)max_launches;
-  while (c->ev.size() < need) {
-    hipEvent_t e;
-    hipError_t err = hipEventCreate(&e);
-    if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
-    c->ev.push_back(e);
-  }
-  c->ev_kernel.assign(c->ev.size() / 2, -1);
-  c->ev_used = 0;
-  c->timing = true;
-  return LWFR_OK;
+  return timing_begin(c->tm, max_launches);
 }
 
 lwfr_status lwfr_timing_end(lwfr_ctx* c, double* ms, uint32_t* launches) {
   if (!c || !ms || !launches) return fail(LWFR_E_INVALID_ARG, "null argument");
-  if (!c->timing) return fail(LWFR_E_STATE, "lwfr_timing_begin has not been called");
-  c->timing = false;
-  hipError_t err = hipStreamSynchronize(c->stream);
-  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("lwfr_timing_end: ") + hipGetErrorString(err));
-  for (int k = 0; k < LWFR_TIMING_KERNELS; ++k) { ms[k] = 0.0; launches[k] = 0; }
-  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
-    float t = 0.0f;
-    err = hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]);
-    if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(err));
-    const int kid = c->ev_kernel[i / 2];
-    if (kid >= 0 && kid < LWFR_TIMING_KERNELS) { ms[kid] += t; launches[kid] += 1; }
-  }
+  return timing_end(c->tm, c->stream, ms, launches);
+}
+
+lwfr_status lwfr_graph_capture(lwfr_ctx* c, double* d_u_a, double* d_u_b, int32_t nsteps, double* d_dt_ch_hist) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
+  if (!d_u_a || !d_u_b) return fail(LWFR_E_INVALID_ARG, "null state pointer");
+  if (nsteps < 1 || nsteps > 100000) return fail(LWFR_E_INVALID_ARG, "nsteps must be in 1..100000");
+  const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
+  if (ranges_overlap(d_u_a, d_u_b, bytes)) return fail(LWFR_E_INVALID_ARG, "u_a and u_b overlap");
+  KParams kp = c->kp;
+  kp.dt_in = 0.0;
+  kp.ch_in = -1.0;
+  return capture(c->stream, c->tm, c->graph, nsteps, [&](int k) {
+    const double* in = (k & 1) ? d_u_b : d_u_a;
+    double* out = (k & 1) ? d_u_a : d_u_b;
+    return dispatch_step(c, kp, in, out, d_dt_ch_hist ? d_dt_ch_hist + 2 * (size_t)k : nullptr, nullptr, nullptr);
+  });
+}
+
+lwfr_status lwfr_graph_launch(lwfr_ctx* c) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!c->graph) return fail(LWFR_E_STATE, "no captured graph");
+  hipError_t err = hipGraphLaunch(c->graph, c->stream);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(err));
   return LWFR_OK;
 }
 
 lwfr_status lwfr_destroy(lwfr_ctx* c) {
-  if (c)
-    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c) {
+    for (hipEvent_t e : c->tm.ev) (void)hipEventDestroy(e);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  }
   delete c;
   return LWFR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+
+lwfr_status lwfr_batch_destroy(lwfr_batch* b) {
+  if (b) {
+    for (lwfr_ctx* c : b->inst) lwfr_destroy(c);
+    for (hipEvent_t e : b->tm.ev) (void)hipEventDestroy(e);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  }
+  delete b;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch** out) {
+  if (!cfgs || !out) return fail(LWFR_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (count < 1 || count > 65536) return fail(LWFR_E_INVALID_ARG, "count must be in 1..65536");
+  lwfr_batch* b = new lwfr_batch();
+  b->equation = cfgs[0].equation;
+  if (b->equation != LWFR_EQ_SW2D) {
+    delete b;
+    return fail(LWFR_E_UNSUPPORTED, "batches support the 2-D shallow water system");
+  }
+  for (int i = 0; i < count; ++i) {
+    if (cfgs[i].equation != b->equation) {
+      lwfr_batch_destroy(b);
+      return fail(LWFR_E_INVALID_ARG, "all problems of a batch must use the same equation system");
+    }
+    if (cfgs[i].flags & LWFR_CFG_ADJOINT) {
+      lwfr_batch_destroy(b);
+      return fail(LWFR_E_UNSUPPORTED, "batches have no adjoint");
+    }
+    lwfr_ctx* c = nullptr;
+    lwfr_status st = lwfr_init(&cfgs[i], &c);
+    if (st != LWFR_OK) {
+      const std::string msg = "problem " + std::to_string(i) + ": " + g_err;
+      lwfr_batch_destroy(b);
+      return fail(st, msg);
+    }
+    b->inst.push_back(c);
+  }
+  // state offsets
+  b->uoff.assign(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    const lwfr_ctx* c = b->inst[i];
+    b->uoff[i + 1] = b->uoff[i] + (long long)c->M * c->E * c->P;
+  }
+  // tile tables
+  const int tt[2] = {256, 128};
+  for (int v = 0; v < 2; ++v) {
+    BatchTable& t = b->tab[v];
+    t.tile_threads = tt[v];
+    t.tile_begin.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      const lwfr_ctx* c = b->inst[i];
+      const int epb = tt[v] / c->P;
+      const int nb = (c->E + epb - 1) / epb;
+      for (int k = 0; k < nb; ++k) { t.tinst.push_back(i); t.tblk.push_back(k); }
+      t.tile_begin[i + 1] = (int)t.tinst.size();
+    }
+    t.ntiles = (int)t.tinst.size();
+  }
+  {
+    BatchTable& t = b->ftab;
+    t.tile_threads = 256;
+    t.tile_begin.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      const lwfr_ctx* c = b->inst[i];
+      const long long nfp = (long long)c->DIM * c->E * c->NFP;
+      const int nb = (int)((nfp + 255) / 256);
+      for (int k = 0; k < nb; ++k) { t.tinst.push_back(i); t.tblk.push_back(k); }
+      t.tile_begin[i + 1] = (int)t.tinst.size();
+    }
+    t.ntiles = (int)t.tinst.size();
+  }
+  // workspace: header, then the problems' workspaces
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  b->off_kps = take(count * sizeof(KParams));
+  b->off_uoff = take(count * sizeof(long long));
+  for (BatchTable* t : {&b->tab[0], &b->tab[1], &b->ftab}) {
+    t->off_tinst = take(t->ntiles * sizeof(int));
+    t->off_tblk = take(t->ntiles * sizeof(int));
+    t->off_tb = take((count + 1) * sizeof(int));
+  }
+  const int maxt = b->tab[0].ntiles > b->tab[1].ntiles ? b->tab[0].ntiles : b->tab[1].ntiles;
+  b->off_part = take(maxt * sizeof(double));
+  b->off_flag = take(sizeof(uint32_t));
+  b->hdr_bytes = off;
+  for (int i = 0; i < count; ++i) b->off_inst.push_back(take(b->inst[i]->ws_bytes));
+  b->ws_bytes = off;
+  for (int ph = 0; ph < 4; ++ph) b->launch[ph] = BatchLaunch();
+  *out = b;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_workspace_bytes(const lwfr_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(LWFR_E_INVALID_ARG, "null argument");
+  *bytes = b->ws_bytes;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_state_offsets(const lwfr_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return fail(LWFR_E_INVALID_ARG, "null argument");
+  for (size_t i = 0; i < b->uoff.size(); ++i) offsets[i] = b->uoff[i];
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_problem(lwfr_batch* b, int32_t i, lwfr_ctx** ctx) {
+  if (!b || !ctx) return fail(LWFR_E_INVALID_ARG, "null argument");
+  if (i < 0 || i >= (int)b->inst.size()) return fail(LWFR_E_INVALID_ARG, "problem index out of range");
+  *ctx = b->inst[i];
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_bind(lwfr_batch* b, void* d_ws, size_t bytes, void* stream) {
+  if (!b) return fail(LWFR_E_INVALID_ARG, "null batch");
+  if (!d_ws) return fail(LWFR_E_WORKSPACE, "workspace is null");
+  if (bytes < b->ws_bytes) return fail(LWFR_E_WORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return fail(LWFR_E_WORKSPACE, "workspace not 256-byte aligned");
+  b->ws = d_ws;
+  b->stream = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(d_ws);
+  const int count = (int)b->inst.size();
+  b->hdr.assign(b->hdr_bytes, 0);
+  char* h = b->hdr.data();
+  uint32_t* flag = reinterpret_cast<uint32_t*>(w + b->off_flag);
+  for (int i = 0; i < count; ++i) {
+    lwfr_ctx* c = b->inst[i];
+    c->ws = w + b->off_inst[i];
+    c->stream = b->stream;
+    carve(c, static_cast<char*>(c->ws));
+    c->kp.flag_or = flag;  // one flag word for the whole batch
+    c->kp.dt_in = 0.0;
+    c->kp.ch_in = -1.0;
+    c->bound = true;
+    std::memcpy(h + b->off_kps + i * sizeof(KParams), &c->kp, sizeof(KParams));
+    const long long o = b->uoff[i];
+    std::memcpy(h + b->off_uoff + i * sizeof(long long), &o, sizeof(long long));
+  }
+  for (const BatchTable* t : {&b->tab[0], &b->tab[1], &b->ftab}) {
+    std::memcpy(h + t->off_tinst, t->tinst.data(), t->ntiles * sizeof(int));
+    std::memcpy(h + t->off_tblk, t->tblk.data(), t->ntiles * sizeof(int));
+    std::memcpy(h + t->off_tb, t->tile_begin.data(), (count + 1) * sizeof(int));
+  }
+  hipError_t err = hipMemcpyAsync(w, h, b->hdr_bytes, hipMemcpyHostToDevice, b->stream);
+  if (err == hipSuccess) err = hipMemsetAsync(flag, 0, sizeof(uint32_t), b->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(b->stream);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("lwfr_batch_bind: ") + hipGetErrorString(err));
+  b->bound = true;
+  return LWFR_OK;
+}
+
+static lwfr_status batch_check(lwfr_batch* b, const double* u_in, const double* u_out) {
+  if (!b) return fail(LWFR_E_INVALID_ARG, "null batch");
+  if (!b->bound) return fail(LWFR_E_STATE, "lwfr_batch_bind has not been called");
+  if (!u_in || !u_out) return fail(LWFR_E_INVALID_ARG, "null state pointer");
+  if (ranges_overlap(u_in, u_out, (size_t)b->uoff.back() * sizeof(double)))
+    return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_step(lwfr_batch* b, const double* d_u_in, double* d_u_out, double* d_dt) {
+  lwfr_status st = batch_check(b, d_u_in, d_u_out);
+  if (st != LWFR_OK) return st;
+  return batch_step(b, d_u_in, d_u_out, d_dt);
+}
+
+lwfr_status lwfr_batch_set_launch(lwfr_batch* b, int32_t phase, int32_t tile_threads, int32_t grid, int32_t xcd) {
+  if (!b) return fail(LWFR_E_INVALID_ARG, "null batch");
+  if (phase < 0 || phase > 3) return fail(LWFR_E_INVALID_ARG, "phase must be 0..3");
+  if (phase == LWFR_PHASE_FACES ? tile_threads != 256 : (tile_threads != 256 && tile_threads != 128))
+    return fail(LWFR_E_INVALID_ARG, "tile_threads must be 256 or 128 (faces: 256)");
+  if (grid < 0 || grid > (1 << 24)) return fail(LWFR_E_INVALID_ARG, "grid out of range");
+  if (xcd != 0 && xcd != 1) return fail(LWFR_E_INVALID_ARG, "xcd must be 0 or 1");
+  b->launch[phase] = BatchLaunch{tile_threads, grid, xcd};
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_get_launch(const lwfr_batch* b, int32_t phase, int32_t* tile_threads, int32_t* grid,
+                                  int32_t* xcd) {
+  if (!b || !tile_threads || !grid || !xcd) return fail(LWFR_E_INVALID_ARG, "null argument");
+  if (phase < 0 || phase > 3) return fail(LWFR_E_INVALID_ARG, "phase must be 0..3");
+  *tile_threads = b->launch[phase].tile_threads;
+  *grid = b->launch[phase].grid;
+  *xcd = b->launch[phase].xcd;
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_autotune(lwfr_batch* b, const double* d_u_in, double* d_u_out, int32_t reps) {
+  lwfr_status st = batch_check(b, d_u_in, d_u_out);
+  if (st != LWFR_OK) return st;
+  if (reps < 1 || reps > 100) return fail(LWFR_E_INVALID_ARG, "reps must be in 1..100");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(LWFR_E_HIP, "autotune: hipEventCreate failed");
+  }
+  const bool timing = b->tm.on;
+  b->tm.on = false;
+  st = batch_step(b, d_u_in, d_u_out, nullptr);  // every phase's inputs in place
+  const int grids[5] = {0, 1024, 2048, 4096, 8192};
+  auto none = [] { return LWFR_OK; };
+  auto stages_first = [&] { return batch_phase_any(b, LWFR_PHASE_STAGES, d_u_in, d_u_out, nullptr); };
+  for (int ph = 0; ph < 4 && st == LWFR_OK; ++ph) {
+    BatchLaunch best = b->launch[ph];
+    float tbest = 1e30f;
+    for (int tt : {256, 128}) {
+      if (ph == LWFR_PHASE_FACES && tt != 256) continue;
+      for (int g : grids)
+        for (int x : {0, 1}) {
+          const BatchLaunch l{tt, g, x};
+          float t = 0.0f;
+          if (ph == LWFR_PHASE_UPDATE) st = time_phase(b, ph, l, d_u_in, d_u_out, reps, stages_first, e0, e1, t);
+          else st = time_phase(b, ph, l, d_u_in, d_u_out, reps, none, e0, e1, t);
+          if (st != LWFR_OK) break;
+          if (t < tbest) { tbest = t; best = l; }
+        }
+      if (st != LWFR_OK) break;
+    }
+    b->launch[ph] = best;
+    // the phase's outputs with the chosen shape, for the phases after it
+    if (st == LWFR_OK && ph != LWFR_PHASE_UPDATE) st = batch_phase_any(b, ph, d_u_in, d_u_out, nullptr);
+  }
+  if (st == LWFR_OK) st = batch_step(b, d_u_in, d_u_out, nullptr);
+  hipError_t err = hipStreamSynchronize(b->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->tm.on = timing;
+  if (st == LWFR_OK && err != hipSuccess) st = fail(LWFR_E_HIP, std::string("autotune: ") + hipGetErrorString(err));
+  return st;
+}
+
+lwfr_status lwfr_batch_graph_capture(lwfr_batch* b, double* d_u_a, double* d_u_b, int32_t nsteps,
+                                     double* d_dt_hist) {
+  lwfr_status st = batch_check(b, d_u_a, d_u_b);
+  if (st != LWFR_OK) return st;
+  if (nsteps < 1 || nsteps > 100000) return fail(LWFR_E_INVALID_ARG, "nsteps must be in 1..100000");
+  const size_t count = b->inst.size();
+  return capture(b->stream, b->tm, b->graph, nsteps, [&](int k) {
+    const double* in = (k & 1) ? d_u_b : d_u_a;
+    double* out = (k & 1) ? d_u_a : d_u_b;
+    return batch_step(b, in, out, d_dt_hist ? d_dt_hist + count * (size_t)k : nullptr);
+  });
+}
+
+lwfr_status lwfr_batch_graph_launch(lwfr_batch* b) {
+  if (!b) return fail(LWFR_E_INVALID_ARG, "null batch");
+  if (!b->graph) return fail(LWFR_E_STATE, "no captured graph");
+  hipError_t err = hipGraphLaunch(b->graph, b->stream);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(err));
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_batch_query(lwfr_batch* b, uint32_t* flags_or) {
+  if (!b) return fail(LWFR_E_INVALID_ARG, "null batch");
+  if (!b->bound) return fail(LWFR_E_STATE, "lwfr_batch_bind has not been called");
+  return lwfr_query(b->inst[0], flags_or);
+}
+
+lwfr_status lwfr_batch_timing_begin(lwfr_batch* b, int32_t max_launches) {
+  if (!b) return fail(LWFR_E_INVALID_ARG, "null batch");
+  if (!b->bound) return fail(LWFR_E_STATE, "lwfr_batch_bind has not been called");
+  return timing_begin(b->tm, max_launches);
+}
+
+lwfr_status lwfr_batch_timing_end(lwfr_batch* b, double* ms, uint32_t* launches) {
+  if (!b || !ms || !launches) return fail(LWFR_E_INVALID_ARG, "null argument");
+  return timing_end(b->tm, b->stream, ms, launches);
 }
 
 }  // extern "C"

@@ -70,10 +70,31 @@ _SIGS = {
                         ctypes.c_void_p],
     "lwfr_timing_begin": [ctypes.c_void_p, ctypes.c_int32],
     "lwfr_timing_end": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32)],
+    "lwfr_graph_capture": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
+    "lwfr_graph_launch": [ctypes.c_void_p],
     "lwfr_destroy": [ctypes.c_void_p],
+    "lwfr_batch_init": [ctypes.POINTER(lwfr_config), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
+    "lwfr_batch_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lwfr_batch_state_offsets": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
+    "lwfr_batch_problem": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)],
+    "lwfr_batch_bind": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "lwfr_batch_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lwfr_batch_set_launch": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "lwfr_batch_get_launch": [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+    "lwfr_batch_autotune": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32],
+    "lwfr_batch_graph_capture": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                 ctypes.c_void_p],
+    "lwfr_batch_graph_launch": [ctypes.c_void_p],
+    "lwfr_batch_query": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)],
+    "lwfr_batch_timing_begin": [ctypes.c_void_p, ctypes.c_int32],
+    "lwfr_batch_timing_end": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint32)],
+    "lwfr_batch_destroy": [ctypes.c_void_p],
 }
 TIMING_KERNELS = ("k_pre", "k_dt", "k_ch", "k_ch_fin", "k_stages", "k_faces", "k_update", "k_residual",
-                  "k_adj_update", "k_adj_faces", "k_adj_stages")
+                  "k_adj_update", "k_adj_faces", "k_adj_stages", "kb_pre", "kb_dt", "kb_stages", "kb_faces",
+                  "kb_update")
+LWFR_PHASE_PRE, LWFR_PHASE_STAGES, LWFR_PHASE_FACES, LWFR_PHASE_UPDATE = 0, 1, 2, 3
 
 
 def lib():
@@ -202,15 +223,35 @@ def lwfr_timing_begin(ctx, max_launches):
 
 def lwfr_timing_end(ctx):
     """{kernel name: (total ms, launches)} of the launches since lwfr_timing_begin."""
-    n = len(TIMING_KERNELS)
-    ms = (ctypes.c_double * n)()
-    cnt = (ctypes.c_uint32 * n)()
-    _check(lib().lwfr_timing_end(ctx, ms, cnt))
-    return {TIMING_KERNELS[k]: (ms[k], cnt[k]) for k in range(n)}
+    return _timing_dict(lib().lwfr_timing_end, ctx)
+
+
+def lwfr_graph_capture(ctx, u_a, u_b, nsteps, dt_ch_hist=None):
+    _check(lib().lwfr_graph_capture(ctx, _ptr(u_a), _ptr(u_b), int(nsteps), _ptr(dt_ch_hist)))
+
+
+def lwfr_graph_launch(ctx):
+    _check(lib().lwfr_graph_launch(ctx))
 
 
 def lwfr_destroy(ctx):
     _check(lib().lwfr_destroy(ctx))
+
+
+def _timing_dict(fn, handle):
+    n = len(TIMING_KERNELS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_uint32 * n)()
+    _check(fn(handle, ms, cnt))
+    return {TIMING_KERNELS[k]: (ms[k], cnt[k]) for k in range(n)}
+
+
+def _aligned(nbytes, device):
+    import torch
+
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off: off + nbytes]
 
 
 class Stepper:
@@ -264,6 +305,12 @@ class Stepper:
     def step_taped(self, u_in, u_out, dt, tape, dt_ch=None):
         lwfr_step_taped(self.ctx, u_in, u_out, dt, dt_ch, tape)
 
+    def graph_capture(self, u_a, u_b, nsteps, dt_ch_hist=None):
+        lwfr_graph_capture(self.ctx, u_a, u_b, nsteps, dt_ch_hist)
+
+    def graph_launch(self):
+        lwfr_graph_launch(self.ctx)
+
     def close(self):
         if self.ctx is not None:
             lwfr_destroy(self.ctx)
@@ -274,3 +321,99 @@ class Stepper:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many independent problems advanced together (lwfr_batch_*).
+
+    cfgs: a list of lwfr_config of one equation system.  The batch state is one
+    flat float64 device tensor; view(u, i) is problem i's (nvars, nelem, npts)
+    view of it."""
+
+    def __init__(self, cfgs, device="cuda:0", stream=None):
+        import torch
+
+        self.cfgs = list(cfgs)
+        arr = (lwfr_config * len(self.cfgs))(*self.cfgs)
+        self.handle = ctypes.c_void_p()
+        _check(lib().lwfr_batch_init(arr, len(self.cfgs), ctypes.byref(self.handle)))
+        self.device = torch.device(device)
+        n = ctypes.c_size_t()
+        _check(lib().lwfr_batch_workspace_bytes(self.handle, ctypes.byref(n)))
+        self.nbytes = n.value
+        self.ws = _aligned(self.nbytes, self.device)
+        offs = (ctypes.c_int64 * (len(self.cfgs) + 1))()
+        _check(lib().lwfr_batch_state_offsets(self.handle, offs))
+        self.offsets = list(offs)
+        self.size = self.offsets[-1]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib().lwfr_batch_bind(self.handle, ctypes.c_void_p(self.ws.data_ptr()), self.nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream)))
+        self.shapes = []
+        for c in self.cfgs:
+            dim = DIMS[c.equation]
+            ne = c.nelem[0] * (c.nelem[1] if dim == 2 else 1)
+            self.shapes.append((NVARS[c.equation], ne, (c.degree + 1) ** dim))
+
+    def __len__(self):
+        return len(self.cfgs)
+
+    def empty(self):
+        import torch
+
+        return torch.empty(self.size, dtype=torch.float64, device=self.device)
+
+    def view(self, u, i):
+        return u[self.offsets[i]: self.offsets[i + 1]].view(self.shapes[i])
+
+    def problem(self, i):
+        ctx = ctypes.c_void_p()
+        _check(lib().lwfr_batch_problem(self.handle, int(i), ctypes.byref(ctx)))
+        return ctx
+
+    def step(self, u_in, u_out, dt=None):
+        _check(lib().lwfr_batch_step(self.handle, _ptr(u_in), _ptr(u_out), _ptr(dt)))
+
+    def set_launch(self, phase, tile_threads, grid, xcd):
+        _check(lib().lwfr_batch_set_launch(self.handle, int(phase), int(tile_threads), int(grid), int(xcd)))
+
+    def get_launch(self, phase):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lwfr_batch_get_launch(self.handle, int(phase), ctypes.byref(a), ctypes.byref(b),
+                                           ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, u_in, u_out, reps=3):
+        _check(lib().lwfr_batch_autotune(self.handle, _ptr(u_in), _ptr(u_out), int(reps)))
+
+    def graph_capture(self, u_a, u_b, nsteps, dt_hist=None):
+        _check(lib().lwfr_batch_graph_capture(self.handle, _ptr(u_a), _ptr(u_b), int(nsteps), _ptr(dt_hist)))
+
+    def graph_launch(self):
+        _check(lib().lwfr_batch_graph_launch(self.handle))
+
+    def query(self):
+        f = ctypes.c_uint32()
+        st = lib().lwfr_batch_query(self.handle, ctypes.byref(f))
+        return st, f.value
+
+    def timing_begin(self, max_launches):
+        _check(lib().lwfr_batch_timing_begin(self.handle, int(max_launches)))
+
+    def timing_end(self):
+        return _timing_dict(lib().lwfr_batch_timing_end, self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            lwfr_destroy_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lwfr_destroy_batch(handle):
+    _check(lib().lwfr_batch_destroy(handle))

@@ -79,3 +79,41 @@ def test_reference_nodes_match_oracle(N):
 @pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_fourier_cfl_matches_oracle(N):
     assert abs(lwfr.lwfr_cfl_number(N) - oracle.cfl_number(N)) < 2e-6 * oracle.cfl_number(N)
+
+
+def test_batch_host_side():
+    """Batch set-up on the host: offsets, workspace size, validation (no GPU calls)."""
+    L = lwfr.lib()
+    specs = [(3, 1), (5, 2), (1, 4)]
+    cfgs = [lwfr.make_config(lwfr.LWFR_EQ_SW2D, N, (n, n)) for n, N in specs]
+    arr = (lwfr.lwfr_config * 3)(*cfgs)
+    h = ctypes.c_void_p()
+    assert L.lwfr_batch_init(arr, 3, ctypes.byref(h)) == lwfr.LWFR_OK
+    offs = (ctypes.c_int64 * 4)()
+    assert L.lwfr_batch_state_offsets(h, offs) == lwfr.LWFR_OK
+    sizes = [4 * n * n * (N + 1) ** 2 for n, N in specs]
+    assert list(offs) == [0, sizes[0], sizes[0] + sizes[1], sum(sizes)]
+    nb = ctypes.c_size_t()
+    assert L.lwfr_batch_workspace_bytes(h, ctypes.byref(nb)) == lwfr.LWFR_OK
+    single = sum(lwfr.lwfr_workspace_bytes(lwfr.lwfr_init(c)) for c in cfgs)
+    assert nb.value > single
+    for phase, tt, grid, xcd in [(4, 256, 0, 1), (2, 128, 0, 1), (0, 64, 0, 1), (1, 256, -1, 1), (3, 256, 0, 2)]:
+        assert L.lwfr_batch_set_launch(h, phase, tt, grid, xcd) == lwfr.LWFR_E_INVALID_ARG
+    assert L.lwfr_batch_set_launch(h, 1, 128, 4096, 0) == lwfr.LWFR_OK
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.lwfr_batch_get_launch(h, 1, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == lwfr.LWFR_OK
+    assert (a.value, b.value, c.value) == (128, 4096, 0)
+    # stepping before binding is a state error
+    assert L.lwfr_batch_step(h, ctypes.c_void_p(256), ctypes.c_void_p(1 << 30), None) == lwfr.LWFR_E_STATE
+    assert L.lwfr_batch_destroy(h) == lwfr.LWFR_OK
+    # mixed systems, unsupported system, adjoint flag
+    mixed = (lwfr.lwfr_config * 2)(cfgs[0], lwfr.make_config(lwfr.LWFR_EQ_SW1D, 2, 8))
+    assert L.lwfr_batch_init(mixed, 2, ctypes.byref(h)) == lwfr.LWFR_E_INVALID_ARG
+    mhd = (lwfr.lwfr_config * 1)(lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 2, (4, 4)))
+    assert L.lwfr_batch_init(mhd, 1, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
+    adj = (lwfr.lwfr_config * 1)(lwfr.make_config(lwfr.LWFR_EQ_SW2D, 2, (4, 4), flags=lwfr.LWFR_CFG_ADJOINT))
+    assert L.lwfr_batch_init(adj, 1, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
+    bad = (lwfr.lwfr_config * 2)(cfgs[0], lwfr.make_config(lwfr.LWFR_EQ_SW2D, 5, (4, 4)))
+    assert L.lwfr_batch_init(bad, 2, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
+    assert "problem 1" in lwfr.lwfr_last_error()
+    assert L.lwfr_batch_init(arr, 0, ctypes.byref(h)) == lwfr.LWFR_E_INVALID_ARG
