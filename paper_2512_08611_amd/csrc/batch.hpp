@@ -48,12 +48,26 @@ constexpr int batch_epb(int DIM) {
   return NT / ipow(N + 1, DIM);
 }
 
+// elements per tile of the batched stage phase (two lanes per point in 2-D)
+template <class Ph, int N, int NT>
+constexpr int batch_epb_stages() {
+  return NT / (stage_lanes<Ph>() * ipow(N + 1, Ph::DIM));
+}
+
 template <template <class, int, int> class Lds, class Ph, int NT>
 union LdsByDegree {
   Lds<Ph, 1, NT> n1;
   Lds<Ph, 2, NT> n2;
   Lds<Ph, 3, NT> n3;
   Lds<Ph, 4, NT> n4;
+};
+
+template <class Ph, int NT>
+union StageLdsByDegree {
+  StageLdsT<Ph, 1, NT> n1;
+  StageLdsT<Ph, 2, NT> n2;
+  StageLdsT<Ph, 3, NT> n3;
+  StageLdsT<Ph, 4, NT> n4;
 };
 
 template <class Ph, int NT>
@@ -103,13 +117,10 @@ __global__ void __launch_bounds__(256) kb_dt(const BatchArgs ba, const int* __re
 }
 
 // The batched kernels hold the registers of their largest degree; the hint
-// keeps the stage kernel at two waves per SIMD, as the single-problem stage
-// kernel of degree 4 (a few registers spill).
+// keeps the stage kernel at two waves per SIMD (a few registers spill).
 template <class Ph, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
-    kb_stages(const BatchArgs ba, const double* __restrict__ u_in, double* __restrict__ u_out) {
-  constexpr int DIM = Ph::DIM;
-  __shared__ LdsByDegree<StagesLds, Ph, NT> L;
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) kb_stages(const BatchArgs ba, const double* __restrict__ u_in, double* __restrict__ u_out) {
+  __shared__ StageLdsByDegree<Ph, NT> L;
   int t0, t1, step;
   tile_range(ba.ntiles, ba.xcd, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
@@ -118,10 +129,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
     const double* un = u_in + ba.uoff[inst];
     double* rv = u_out + ba.uoff[inst];
     switch (kp.N) {
-      case 1: stages_body<Ph, 1, batch_epb<1, NT>(DIM), NT>(kp, L.n1, un, rv, nullptr, blk); break;
-      case 2: stages_body<Ph, 2, batch_epb<2, NT>(DIM), NT>(kp, L.n2, un, rv, nullptr, blk); break;
-      case 3: stages_body<Ph, 3, batch_epb<3, NT>(DIM), NT>(kp, L.n3, un, rv, nullptr, blk); break;
-      default: stages_body<Ph, 4, batch_epb<4, NT>(DIM), NT>(kp, L.n4, un, rv, nullptr, blk); break;
+      case 1: stage_body<Ph, 1, batch_epb_stages<Ph, 1, NT>(), NT>(kp, L.n1, un, rv, nullptr, blk); break;
+      case 2: stage_body<Ph, 2, batch_epb_stages<Ph, 2, NT>(), NT>(kp, L.n2, un, rv, nullptr, blk); break;
+      case 3: stage_body<Ph, 3, batch_epb_stages<Ph, 3, NT>(), NT>(kp, L.n3, un, rv, nullptr, blk); break;
+      default: stage_body<Ph, 4, batch_epb_stages<Ph, 4, NT>(), NT>(kp, L.n4, un, rv, nullptr, blk); break;
     }
     __syncthreads();
   }

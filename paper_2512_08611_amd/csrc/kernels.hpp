@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "physics.hpp"
 #include "refel.hpp"
 
@@ -24,6 +26,10 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 #ifndef STAGES_WAVES_PER_EU
 #define STAGES_WAVES_PER_EU 1
+#endif
+// extra doubles after each variable's node row in the stage kernel's LDS
+#ifndef LWFR_STAGES_PAD
+#define LWFR_STAGES_PAD 0
 #endif
 
 // everything a kernel needs besides the state pointers, passed by value
@@ -112,12 +118,14 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
   const bool act = le < EPB && e < kp.E;
   const PhysParams pp{kp.g, kp.gamma, 0.0};
   const bool want_alpha = kp.blending >= 1 && kp.alpha_force < 0.0;
+  // lanes without an element read element 0 (unconditional loads pipeline;
+  // a load under a lane condition waits for its data before the next one)
+  const int es = act ? e : 0;
   double x[M];
 #pragma unroll
-  for (int v = 0; v < M; ++v) {
-    x[v] = act ? un[((size_t)v * kp.E + e) * P + p] : 1.0;
-    s_u[le][v][p] = x[v];
-  }
+  for (int v = 0; v < M; ++v) x[v] = un[((size_t)v * kp.E + es) * P + p];
+#pragma unroll
+  for (int v = 0; v < M; ++v) s_u[le][v][p] = x[v];
   if (want_alpha) s_q[le][p] = Ph::indicator(x, pp);
   __syncthreads();
   // element mean of each variable, summed over the nodes in order
@@ -216,12 +224,20 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams
   pre_body<Ph, N, EPB, NT>(kp, L, un, blockIdx.x, kp.part + blockIdx.x);
 }
 
-// k_dt: one block; Lambda and dt
-__global__ void __launch_bounds__(256) k_dt(const KParams kp, double* d_dt_ch, int has_ch) {
-  __shared__ double s_max[256];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < kp.nblk_pre; i += blockDim.x) m = fmax(m, kp.part[i]);
-  s_max[threadIdx.x] = m;
+// k_dt: one block of 1024 threads; Lambda and dt
+__global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, int has_ch) {
+  __shared__ double s_max[1024];
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  const int n = kp.nblk_pre, st = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * st < n; i += 4 * st) {
+    m0 = fmax(m0, kp.part[i]);
+    m1 = fmax(m1, kp.part[i + st]);
+    m2 = fmax(m2, kp.part[i + 2 * st]);
+    m3 = fmax(m3, kp.part[i + 3 * st]);
+  }
+  for (; i < n; i += st) m0 = fmax(m0, kp.part[i]);
+  s_max[threadIdx.x] = fmax(fmax(m0, m1), fmax(m2, m3));
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
@@ -263,11 +279,17 @@ __global__ void __launch_bounds__(256) k_ch(const KParams kp) {
   if (threadIdx.x == 0) kp.part2[blockIdx.x] = s_min[0];
 }
 
-__global__ void __launch_bounds__(256) k_ch_fin(const KParams kp, double* d_dt_ch) {
-  __shared__ double s_min[256];
-  double m = INFINITY;
-  for (int i = threadIdx.x; i < kp.nblk_ch; i += blockDim.x) m = fmin(m, kp.part2[i]);
-  s_min[threadIdx.x] = m;
+__global__ void __launch_bounds__(1024) k_ch_fin(const KParams kp, double* d_dt_ch) {
+  __shared__ double s_min[1024];
+  double m0 = INFINITY, m1 = INFINITY;
+  const int n = kp.nblk_ch, st = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + st < n; i += 2 * st) {
+    m0 = fmin(m0, kp.part2[i]);
+    m1 = fmin(m1, kp.part2[i + st]);
+  }
+  for (; i < n; i += st) m0 = fmin(m0, kp.part2[i]);
+  s_min[threadIdx.x] = fmin(m0, m1);
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + s]);
@@ -301,7 +323,7 @@ struct StagesLds {
   static constexpr int DIM = Ph::DIM, M = Ph::M, P = ipow(N + 1, DIM), EL = (NT + P - 1) / P;
   static constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
   static constexpr int NBUF = (DIM * M + DIM * NCD) > (DIM * M + M) ? (DIM * M + DIM * NCD) : (DIM * M + M);
-  double s_buf[EL][NBUF][P];
+  double s_buf[EL][NBUF][P + LWFR_STAGES_PAD];
 };
 
 template <class Ph, int N, int EPB, int NT>
@@ -324,7 +346,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
 
   double un[M];
 #pragma unroll
-  for (int v = 0; v < M; ++v) un[v] = act ? un_g[((size_t)v * kp.E + e) * P + p] : 1.0;
+  for (int v = 0; v < M; ++v) un[v] = un_g[((size_t)v * kp.E + (act ? e : 0)) * P + p];
   double Drow[DIM][n1];
 #pragma unroll
   for (int r = 0; r < n1; ++r) {
@@ -468,12 +490,251 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
   }
 }
 
+// ------------------------------------------------------------------------
+// Stage kernel of the 2-D systems with two lanes per solution point.  The lane
+// of direction d evaluates the d-flux f_d, its derivative D_d, the derivatives
+// of the non-conservative columns along d and B_d(u) D_d u, i.e. the d-part
+// L_d of the local operator; the two lanes of a point swap halves so that each
+// forms L = L_x + L_y for its half of the variables (direction 0 the first
+// ceil(M/2), direction 1 the rest) and keeps the running stage sums, U and R of
+// that half, and both rebuild the full stage state from their halves.  Same
+// arithmetic as the one-lane body, about half the registers per lane.
+//
+// Lane t of the workgroup takes direction (t >> 4) & 1 and point slot
+// 16 (t >> 5) + (t & 15): each group of 16 lanes (one LDS cycle of a 64-bit
+// access) reads along a single direction, which keeps the derivative reads
+// free of bank conflicts, and partners sit in neighbouring 16-lane rows, where
+// v_permlane16_swap exchanges them without LDS.
+__device__ inline unsigned int partner16(unsigned int x, bool odd_row) {
+  // rows 2k and 2k+1 of the wave exchange x
+  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  return odd_row ? r[0] : r[1];
+}
+__device__ inline double swap_pair(double x, bool odd_row) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned int lo = partner16((unsigned int)(b & 0xffffffffULL), odd_row);
+  const unsigned int hi = partner16((unsigned int)(b >> 32), odd_row);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// threads of a two-lane stage workgroup holding EPB elements of P points: whole
+// pairs of 16-lane rows
+constexpr int stages2_threads(int EPB, int P) { return (2 * EPB * P + 31) / 32 * 32; }
+
+template <class Ph, int N, int NT>
+struct Stages2Lds {
+  static constexpr int M = Ph::M, P = ipow(N + 1, 2), EL = (NT / 2 + P - 1) / P, NCD = Ph::NCD;
+  static constexpr int NBUF = (2 * M + 2 * NCD) > (3 * M) ? (2 * M + 2 * NCD) : (3 * M);
+  double s_buf[EL][NBUF][P + LWFR_STAGES_PAD];
+};
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N, NT>& L,
+                                             const double* __restrict__ un_g, double* __restrict__ rvol_g,
+                                             double* d_alpha_out, int blk) {
+  static_assert(Ph::DIM == 2 && Ph::NCD > 0, "two-lane stage body is for 2-D systems");
+  constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NFP = n1, NCD = Ph::NCD;
+  constexpr int H0 = (M + 1) / 2, H1 = M - H0;
+  using Tab = Tableau<N>;
+  constexpr int S = Tab::S;
+  auto& s_buf = L.s_buf;
+
+  const int tid = threadIdx.x;
+  const int d = (tid >> 4) & 1, np = ((tid >> 5) << 4) | (tid & 15);
+  const bool odd = d != 0;  // odd 16-lane row of its pair
+  const int le = np / P, p = np - le * P;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
+  const int i = p % n1, j = p / n1;
+  const int q = d ? i : j;            // line of the lane's direction through p
+  const int ii = d ? j : i;           // position along that line
+  const int sq = d ? 1 : n1, sr = d ? n1 : 1;  // node(q, r) = q*sq + r*sr
+  const int vo = d ? H0 : 0;          // first variable of the lane's half
+  const double dt = kp.scal[0];
+  const double idx = d ? kp.inv_dx[1] : kp.inv_dx[0];
+  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+
+  // u^n of the lane's half (lane 1 with H1 < H0 pads with its last variable)
+  double uo[H0];
+#pragma unroll
+  for (int k = 0; k < H0; ++k) {
+    const int v = vo + (k < (d ? H1 : H0) ? k : 0);
+    uo[k] = un_g[((size_t)v * kp.E + (act ? e : 0)) * P + p];
+  }
+  double Drow[n1];
+#pragma unroll
+  for (int r = 0; r < n1; ++r) Drow[r] = kp.D[ii][r];
+
+  double Fa[M], Ua[H0], Ra[H0], Sp[S][H0];
+#pragma unroll
+  for (int v = 0; v < M; ++v) Fa[v] = 0.0;
+#pragma unroll
+  for (int k = 0; k < H0; ++k) { Ua[k] = 0.0; Ra[k] = 0.0; }
+
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    // the lane's half of the stage state, then the full state
+    double uh[H0], u[M];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) uh[k] = first_nz<N>(st) >= 0 ? uo[k] - dt * Sp[st][k] : uo[k];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      const double other = swap_pair(uh[k], odd);
+      u[k] = d ? other : uh[k];
+      if (k < H1) u[H0 + k] = d ? uh[k] : other;
+    }
+    double f[M];
+    Ph::flux_rd(u, d, f, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v)
+      if (Ph::flux_nc_alias(v) < 0) s_buf[le][d * M + v][p] = f[v];
+#pragma unroll
+    for (int c = 0; c < NCD; ++c) {
+      const double x0 = u[Ph::nc_comp(0, c)], x1 = u[Ph::nc_comp(1, c)];
+      s_buf[le][2 * M + d * NCD + c][p] = d ? x1 : x0;
+    }
+    const double bs = Tab::b(st);
+    if (bs != 0.0) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) Fa[v] += bs * f[v];
+#pragma unroll
+      for (int k = 0; k < H0; ++k) Ua[k] += bs * uh[k];
+    }
+    __syncthreads();
+    // L_d = (D_d f_d + B_d(u) D_d u) / dx_d
+    double Ld[M];
+    {
+      double wc[NCD], nc[M];
+#pragma unroll
+      for (int c = 0; c < NCD; ++c) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][2 * M + d * NCD + c][q * sq + r * sr];
+        wc[c] = sacc;
+      }
+      Ph::ncprod_rd(u, wc, d, nc, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double sacc = 0.0;
+        if (Ph::flux_nc_alias(v) >= 0) {
+          sacc = pp.ch * wc[Ph::flux_nc_alias(v)];  // D_d (c_h w) = c_h D_d w
+        } else {
+#pragma unroll
+          for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][d * M + v][q * sq + r * sr];
+        }
+        Ld[v] = (sacc + nc[v]) * idx;
+      }
+    }
+    __syncthreads();
+    // L = L_x + L_y on the lane's half
+    double Lh[H0];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      const double send = d ? Ld[k] : (k < H1 ? Ld[H0 + k] : 0.0);
+      const double got = swap_pair(send, odd);
+      const double mine = d ? (k < H1 ? Ld[H0 + k] : 0.0) : Ld[k];
+      Lh[k] = d ? got + mine : mine + got;
+    }
+    if (bs != 0.0) {
+#pragma unroll
+      for (int k = 0; k < H0; ++k) Ra[k] += bs * Lh[k];
+    }
+#pragma unroll
+    for (int t = st + 1; t < S; ++t) {
+      const double a = Tab::a(t, st);
+      if (a != 0.0) {
+#pragma unroll
+        for (int k = 0; k < H0; ++k) Sp[t][k] = first_nz<N>(t) == st ? a * Lh[k] : Sp[t][k] + a * Lh[k];
+      }
+    }
+  }
+
+  // time-averaged flux (lane's direction) and solution (lane's half) to LDS
+#pragma unroll
+  for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = Fa[v];
+#pragma unroll
+  for (int k = 0; k < H0; ++k)
+    if (k < (d ? H1 : H0)) s_buf[le][2 * M + vo + k][p] = Ua[k];
+  __syncthreads();
+
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < H0; ++k)
+      if (k < (d ? H1 : H0)) rvol_g[((size_t)(vo + k) * kp.E + e) * P + p] = Ra[k];
+    // face traces: 4*NFP face points per element over the element's 2P lanes
+    constexpr int NFT = 4 * NFP;
+    const int tl = 2 * p + d;
+    for (int t = tl; t < NFT; t += 2 * P) {
+      const int dd = t / (2 * NFP);
+      const int rem = t - dd * 2 * NFP;
+      const int side = rem / NFP;
+      const int qq = rem - side * NFP;
+      const double* V = side ? kp.VR : kp.VL;
+      const size_t nf = (size_t)kp.E * NFP;
+      const size_t fo = (size_t)e * NFP + qq;
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double tf = 0.0, tu = 0.0, tn = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+          const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
+          tf += V[r] * s_buf[le][dd * M + v][nd];
+          tu += V[r] * s_buf[le][2 * M + v][nd];
+          tn += V[r] * un_g[((size_t)v * kp.E + e) * P + nd];
+        }
+        const size_t o = ((size_t)(dd * 2 + side) * M + v) * nf + fo;
+        kp.Ftr[o] = tf;
+        kp.Utr[o] = tu;
+        kp.untr[o] = tn;
+      }
+    }
+    // blending coefficient of the element (smoothed over face neighbours)
+    if (p == 0 && d == 0) {
+      double a;
+      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
+      else if (kp.blending == 0) a = 0.0;
+      else {
+        a = kp.alpha_raw[e];
+#pragma unroll
+        for (int dn = 0; dn < 2; ++dn)
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[nbr_elem(kp, e, dn, sd)]);
+      }
+      kp.alpha[e] = a;
+      if (d_alpha_out) d_alpha_out[e] = a;
+    }
+  }
+}
+
+// lanes per solution point of the stage kernel: two for the 2-D systems with
+// many variables (register bound with one lane), one otherwise (the 2-D
+// shallow water system already runs at high occupancy with one lane)
+template <class Ph>
+constexpr int stage_lanes() {
+  return Ph::DIM == 2 && Ph::M >= 8 ? 2 : 1;
+}
+template <class Ph, int N, int NT>
+using StageLdsT = typename std::conditional<stage_lanes<Ph>() == 2, Stages2Lds<Ph, N, NT>, StagesLds<Ph, N, NT>>::type;
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void stage_body(const KParams& kp, StageLdsT<Ph, N, NT>& L, const double* __restrict__ un_g,
+                                           double* __restrict__ rvol_g, double* d_alpha_out, int blk) {
+  if constexpr (stage_lanes<Ph>() == 2) stages2_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
+  else stages_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
+}
+
+// threads of a stage workgroup of EPB elements
 template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
+constexpr int stage_threads() {
+  return stage_lanes<Ph>() == 2 ? stages2_threads(EPB, ipow(N + 1, Ph::DIM)) : EPB * ipow(N + 1, Ph::DIM);
+}
+
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
     k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
-  constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
-  __shared__ StagesLds<Ph, N, NT> L;
-  stages_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
+  constexpr int NT = stage_threads<Ph, N, EPB>();
+  __shared__ StageLdsT<Ph, N, NT> L;
+  stage_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -662,30 +923,30 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
   const size_t nf = (size_t)kp.E * NFP;
 
-  double un[M];
+  // lanes without an element read element 0 (unconditional loads pipeline)
+  const int es = act ? e : 0;
+  double un[M], R[M];
 #pragma unroll
-  for (int v = 0; v < M; ++v) {
-    un[v] = act ? un_g[((size_t)v * kp.E + e) * P + p] : 1.0;
-    s_u[le][v][p] = un[v];
-  }
+  for (int v = 0; v < M; ++v) un[v] = un_g[((size_t)v * kp.E + es) * P + p];
+#pragma unroll
+  for (int v = 0; v < M; ++v) R[v] = io[((size_t)v * kp.E + es) * P + p];
+#pragma unroll
+  for (int v = 0; v < M; ++v) s_u[le][v][p] = un[v];
   int eL[DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) eL[d] = act ? nbr_elem(kp, e, d, 0) : 0;
+  for (int d = 0; d < DIM; ++d) eL[d] = nbr_elem(kp, es, d, 0);
   uint32_t fl = 0;
   // high order update
   double uH[M];
   {
-    double R[M];
-#pragma unroll
-    for (int v = 0; v < M; ++v) R[v] = act ? io[((size_t)v * kp.E + e) * P + p] : 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
-      const size_t fR = (size_t)e * NFP + q, fL = (size_t)eL[d] * NFP + q;
+      const size_t fR = (size_t)es * NFP + q, fL = (size_t)eL[d] * NFP + q;
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        const double dm = act ? kp.Dm[((size_t)d * M + v) * nf + fR] : 0.0;
-        const double dp = act ? kp.Dp[((size_t)d * M + v) * nf + fL] : 0.0;
+        const double dm = kp.Dm[((size_t)d * M + v) * nf + fR];
+        const double dp = kp.Dp[((size_t)d * M + v) * nf + fL];
         R[v] += (dm * kp.gR[ii] + dp * kp.gL[ii]) * kp.inv_dx[d];
       }
     }
@@ -736,9 +997,9 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
           s_left[le][v][pn] = fc + bR[v];
         }
       } else {
-        const size_t fR = (size_t)e * NFP + q;
+        const size_t fR = (size_t)es * NFP + q;
 #pragma unroll
-        for (int v = 0; v < M; ++v) right[v] = act ? kp.Fm[((size_t)d * M + v) * nf + fR] : 0.0;
+        for (int v = 0; v < M; ++v) right[v] = kp.Fm[((size_t)d * M + v) * nf + fR];
       }
       __syncthreads();
       double left[M];
@@ -748,7 +1009,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
       } else {
         const size_t fL = (size_t)eL[d] * NFP + q;
 #pragma unroll
-        for (int v = 0; v < M; ++v) left[v] = act ? kp.Fp[((size_t)d * M + v) * nf + fL] : 0.0;
+        for (int v = 0; v < M; ++v) left[v] = kp.Fp[((size_t)d * M + v) * nf + fL];
       }
 #pragma unroll
       for (int v = 0; v < M; ++v) RL[v] += (right[v] - left[v]) * kp.inv_wdx[d][ii];
@@ -757,30 +1018,52 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     double uL[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) uL[v] = un[v] - dt * RL[v];
-    const double al = act ? kp.alpha[e] : 0.0;
+    const double al = kp.alpha[es];
 #pragma unroll
     for (int v = 0; v < M; ++v) us[v] = (1.0 - al) * uH[v] + al * uL[v];
-    // Algorithm 2
+    // Algorithm 2.  Element minima: every point stores its value, one thread
+    // per element reduces, every point reads the result.
+    static_assert(2 * Ph::K <= P && Ph::K <= M, "reduction slots");
     double Theta = 1.0;
+    double Pa[Ph::K > 0 ? Ph::K : 1];
 #pragma unroll
     for (int k = 0; k < Ph::K; ++k) {
-      const double Pa = Ph::constraint(k, uL, pp);
-      s_red[le][p] = Pa;
-      __syncthreads();
-      double Pmin = s_red[le][0];
+      Pa[k] = Ph::constraint(k, uL, pp);
+      s_f[le][k][p] = Pa[k];
+    }
+    __syncthreads();
+    if (p == 0) {
 #pragma unroll
-      for (int r = 1; r < P; ++r) Pmin = fmin(Pmin, s_red[le][r]);
-      __syncthreads();
-      if (Pmin <= 0.0) fl |= 2u;
-      if (kp.blending == 2) {
+      for (int k = 0; k < Ph::K; ++k) {
+        double m = s_f[le][k][0];
+#pragma unroll
+        for (int r = 1; r < P; ++r) m = fmin(m, s_f[le][k][r]);
+        s_red[le][k] = m;
+      }
+    }
+    __syncthreads();
+    double Pmin[Ph::K > 0 ? Ph::K : 1];
+#pragma unroll
+    for (int k = 0; k < Ph::K; ++k) {
+      Pmin[k] = s_red[le][k];
+      if (Pmin[k] <= 0.0) fl |= 2u;
+    }
+    if (kp.blending == 2) {
+#pragma unroll
+      for (int k = 0; k < Ph::K; ++k) {
         bool guard = false;
-        const double th_p = theta_limit(0.1 * Pmin, Pa, Ph::constraint(k, us, pp), guard);
-        s_red[le][p] = th_p;
+        const double th_p = theta_limit(0.1 * Pmin[k], Pa[k], Ph::constraint(k, us, pp), guard);
+        __syncthreads();  // every point has read the previous minimum
+        s_left[le][0][p] = th_p;
         __syncthreads();
-        double th = s_red[le][0];
+        if (p == 0) {
+          double m = s_left[le][0][0];
 #pragma unroll
-        for (int r = 1; r < P; ++r) th = fmin(th, s_red[le][r]);
+          for (int r = 1; r < P; ++r) m = fmin(m, s_left[le][0][r]);
+          s_red[le][Ph::K + k] = m;
+        }
         __syncthreads();
+        const double th = s_red[le][Ph::K + k];
         if (th < 1.0) {
 #pragma unroll
           for (int v = 0; v < M; ++v) us[v] = th * us[v] + (1.0 - th) * uL[v];
@@ -813,8 +1096,11 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
         for (int q = 0; q < NFP; ++q) {
           const size_t fu = (size_t)d * nf + (size_t)e * NFP + q;
           const size_t fd = (size_t)d * nf + (size_t)eL[d] * NFP + q;
-          if (kp.theta_face[fu] < 1.0 || kp.theta_face[fd] < 1.0) f |= 4u;
-          if (kp.guard_face[fu] || kp.guard_face[fd]) f |= 16u;
+          // both faces loaded unconditionally (no short-circuit between the loads)
+          const double tu = kp.theta_face[fu], td = kp.theta_face[fd];
+          const uint32_t gu = kp.guard_face[fu], gd = kp.guard_face[fd];
+          f |= ((tu < 1.0) | (td < 1.0)) ? 4u : 0u;
+          f |= (gu | gd) ? 16u : 0u;
         }
     }
     if (d_flags) d_flags[e] = f;

@@ -86,6 +86,16 @@ template <int N>
 constexpr int epb_for(int DIM, int M) {
   return LWFR_EPB_OVERRIDE > 0 ? LWFR_EPB_OVERRIDE : (DIM == 2 && N == 4 && M >= 9) ? 5 : 256 / ipow(N + 1, DIM);
 }
+// Elements per workgroup of the stage kernel (stage_lanes lanes per point):
+// about 256 threads.
+#ifndef LWFR_EPB_STAGES_OVERRIDE
+#define LWFR_EPB_STAGES_OVERRIDE 0
+#endif
+template <class Ph, int N>
+constexpr int epb_stages() {
+  return LWFR_EPB_STAGES_OVERRIDE > 0 ? LWFR_EPB_STAGES_OVERRIDE
+         : (256 / (stage_lanes<Ph>() * ipow(N + 1, Ph::DIM)) > 0 ? 256 / (stage_lanes<Ph>() * ipow(N + 1, Ph::DIM)) : 1);
+}
 inline int epb_runtime(int N, int DIM, int M) {
   switch (N) {
     case 1: return epb_for<1>(DIM, M);
@@ -150,14 +160,15 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   hipStream_t s = c->stream;
   const bool has_ch = std::is_same<Ph, MHD2D>::value && kp.ch_in < 0.0;
   LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N, EPB>), dim3(c->nblk_pre), dim3(EPB * P), 0, s, kp, u_in);
-  LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(256), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
+  LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(1024), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
   if (has_ch) {
     LWFR_LAUNCH(KID_CH, "k_ch", k_ch, dim3(c->nblk_ch), dim3(256), 0, s, kp);
-    LWFR_LAUNCH(KID_CHFIN, "k_ch_fin", k_ch_fin, dim3(1), dim3(256), 0, s, kp, d_dt_ch);
+    LWFR_LAUNCH(KID_CHFIN, "k_ch_fin", k_ch_fin, dim3(1), dim3(1024), 0, s, kp, d_dt_ch);
   }
   const int nblk_el = (E + EPB - 1) / EPB;
-  LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
-              d_alpha);
+  constexpr int EPBS = epb_stages<Ph, N>();
+  LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPBS>), dim3((E + EPBS - 1) / EPBS),
+              dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
   const int nfp_total = DIM * E * NFP;
   LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
   LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
@@ -284,14 +295,18 @@ lwfr_status timing_end(Timing& tm, hipStream_t s, double* ms, uint32_t* launches
 }
 
 // Captures nsteps calls of step(k) on stream s into an executable graph
-// (replacing *exec).  Timing is suspended during the capture.
+// (replacing *exec).  Timing is suspended during the capture (events recorded
+// inside a graph cannot be timed).
 template <class F>
 lwfr_status capture(hipStream_t s, Timing& tm, hipGraphExec_t& exec, int nsteps, F&& step) {
   if (!s) return fail(LWFR_E_STATE, "graph capture needs a non-default stream");
   const bool timing = tm.on;
   tm.on = false;
   hipError_t err = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-  if (err != hipSuccess) { tm.on = timing; return fail(LWFR_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(err)); }
+  if (err != hipSuccess) {
+    tm.on = timing;
+    return fail(LWFR_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(err));
+  }
   lwfr_status st = LWFR_OK;
   for (int k = 0; k < nsteps && st == LWFR_OK; ++k) st = step(k);
   hipGraph_t g = nullptr;
@@ -371,6 +386,7 @@ struct lwfr_batch {
   int equation = 0;
   std::vector<long long> uoff;  // [ninst+1] state offsets (doubles)
   BatchTable tab[2];            // per-point phases with 256 and 128 threads per tile
+  BatchTable stab[2];           // stage phase (stage_lanes lanes per point), 256 and 128 threads
   BatchTable ftab;              // face phase
   size_t off_kps = 0, off_uoff = 0, off_part = 0, off_flag = 0, hdr_bytes = 0, ws_bytes = 0;
   std::vector<size_t> off_inst;
@@ -387,7 +403,8 @@ namespace {
 
 const BatchTable& table_for(const lwfr_batch* b, int phase) {
   if (phase == LWFR_PHASE_FACES) return b->ftab;
-  return b->launch[phase].tile_threads == 128 ? b->tab[1] : b->tab[0];
+  const int v = b->launch[phase].tile_threads == 128 ? 1 : 0;
+  return phase == LWFR_PHASE_STAGES ? b->stab[v] : b->tab[v];
 }
 
 BatchArgs batch_args(const lwfr_batch* b, const BatchTable& t, const BatchLaunch& l) {
@@ -840,13 +857,14 @@ lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch**
   }
   // tile tables
   const int tt[2] = {256, 128};
-  for (int v = 0; v < 2; ++v) {
-    BatchTable& t = b->tab[v];
-    t.tile_threads = tt[v];
+  for (int v = 0; v < 4; ++v) {
+    BatchTable& t = v < 2 ? b->tab[v] : b->stab[v - 2];
+    t.tile_threads = tt[v & 1];
     t.tile_begin.assign(count + 1, 0);
     for (int i = 0; i < count; ++i) {
       const lwfr_ctx* c = b->inst[i];
-      const int epb = tt[v] / c->P;
+      const int lanes = v < 2 ? 1 : (c->DIM == 2 && c->M >= 8 ? 2 : 1);  // stage_lanes
+      const int epb = tt[v & 1] / (lanes * c->P);
       const int nb = (c->E + epb - 1) / epb;
       for (int k = 0; k < nb; ++k) { t.tinst.push_back(i); t.tblk.push_back(k); }
       t.tile_begin[i + 1] = (int)t.tinst.size();
@@ -871,7 +889,7 @@ lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch**
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   b->off_kps = take(count * sizeof(KParams));
   b->off_uoff = take(count * sizeof(long long));
-  for (BatchTable* t : {&b->tab[0], &b->tab[1], &b->ftab}) {
+  for (BatchTable* t : {&b->tab[0], &b->tab[1], &b->stab[0], &b->stab[1], &b->ftab}) {
     t->off_tinst = take(t->ntiles * sizeof(int));
     t->off_tblk = take(t->ntiles * sizeof(int));
     t->off_tb = take((count + 1) * sizeof(int));
@@ -931,7 +949,7 @@ lwfr_status lwfr_batch_bind(lwfr_batch* b, void* d_ws, size_t bytes, void* strea
     const long long o = b->uoff[i];
     std::memcpy(h + b->off_uoff + i * sizeof(long long), &o, sizeof(long long));
   }
-  for (const BatchTable* t : {&b->tab[0], &b->tab[1], &b->ftab}) {
+  for (const BatchTable* t : {&b->tab[0], &b->tab[1], &b->stab[0], &b->stab[1], &b->ftab}) {
     std::memcpy(h + t->off_tinst, t->tinst.data(), t->ntiles * sizeof(int));
     std::memcpy(h + t->off_tblk, t->tblk.data(), t->ntiles * sizeof(int));
     std::memcpy(h + t->off_tb, t->tile_begin.data(), (count + 1) * sizeof(int));

@@ -72,6 +72,7 @@ struct SW1D {
 
 struct SW2D {
   static constexpr int M = 4, DIM = 2, K = 1, NCD = 1;
+  __host__ __device__ static constexpr int flux_nc_alias(int) { return -1; }
   __host__ __device__ static constexpr int nc_comp(int, int) { return 3; }
   template <int d>
   __device__ static void flux(const double* u, double* f, const PhysParams& pp) {
@@ -91,6 +92,25 @@ struct SW2D {
   template <int d>
   __device__ static double sigma(const double* u, const PhysParams& pp) {
     return fabs(u[1 + d] / u[0]) + sqrt(pp.g * u[0]);
+  }
+  // flux and B_d(u) w with the direction d a run-time value (selects, no
+  // branches: lanes of one wave may take different directions); wc holds the
+  // d-derivative of the non-conservative column (b)
+  __device__ static void flux_rd(const double* u, int d, double* f, const PhysParams& pp) {
+    const double hu = d ? u[2] : u[1];
+    const double vel = hu / u[0];
+    const double ph = 0.5 * pp.g * u[0] * u[0];
+    f[0] = hu;
+    f[1] = d ? u[1] * vel : u[1] * vel + ph;
+    f[2] = d ? u[2] * vel + ph : u[2] * vel;
+    f[3] = 0.0;
+  }
+  __device__ static void ncprod_rd(const double* u, const double* wc, int d, double* o, const PhysParams& pp) {
+    const double t = pp.g * u[0] * wc[0];
+    o[0] = 0.0;
+    o[1] = d ? 0.0 : t;
+    o[2] = d ? t : 0.0;
+    o[3] = 0.0;
   }
   __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
   __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
@@ -133,6 +153,9 @@ struct SW2D {
 struct MHD2D {
   static constexpr int M = 9, DIM = 2, K = 2, NCD = 2;
   __host__ __device__ static constexpr int nc_comp(int d, int i) { return i == 0 ? 5 + d : 8; }
+  // flux components equal to c_h times a non-conservative column in every
+  // direction (f_d[8] = c_h B_d): index of that column, else -1
+  __host__ __device__ static constexpr int flux_nc_alias(int v) { return v == 8 ? 0 : -1; }
   __device__ static double pressure(const double* u, const PhysParams& pp) {
     const double ir = 1.0 / u[0];
     const double mm = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
@@ -170,6 +193,49 @@ struct MHD2D {
     const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
     const double vd = d == 0 ? v1 : v2;
     const double dB = w[5 + d], dpsi = w[8];
+    const double vB = v1 * u[5] + v2 * u[6] + v3 * u[7];
+    o[0] = 0.0;
+    o[1] = dB * u[5];
+    o[2] = dB * u[6];
+    o[3] = dB * u[7];
+    o[4] = dB * vB + dpsi * vd * u[8];
+    o[5] = dB * v1;
+    o[6] = dB * v2;
+    o[7] = dB * v3;
+    o[8] = dpsi * vd;
+  }
+  // flux and B_d(u) w with the direction d a run-time value (selects, no
+  // branches); wc = (d-derivative of B_d, d-derivative of psi)
+  __device__ static void flux_rd(const double* u, int d, double* f, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+    const double B1 = u[5], B2 = u[6], B3 = u[7], psi = u[8];
+    const double bb = B1 * B1 + B2 * B2 + B3 * B3;
+    const double vv = v1 * v1 + v2 * v2 + v3 * v3;
+    const double p = (pp.gamma - 1.0) * (u[4] - 0.5 * u[0] * vv - 0.5 * bb - 0.5 * psi * psi);
+    const double vB = v1 * B1 + v2 * B2 + v3 * B3;
+    const double vd = d ? v2 : v1;
+    const double Bd = d ? B2 : B1;
+    const double md = d ? u[2] : u[1];
+    const double pt = p + 0.5 * bb;
+    const double f1 = md * v1 - Bd * B1, f2 = md * v2 - Bd * B2;
+    f[0] = md;
+    f[1] = d ? f1 : f1 + pt;
+    f[2] = d ? f2 + pt : f2;
+    f[3] = md * v3 - Bd * B3;
+    f[4] = vd * (0.5 * u[0] * vv + pp.gamma / (pp.gamma - 1.0) * p + bb) - Bd * vB + pp.ch * psi * Bd;
+    const double cp = pp.ch * psi;
+    const double f5 = vd * B1 - Bd * v1, f6 = vd * B2 - Bd * v2;
+    f[5] = d ? f5 : cp;
+    f[6] = d ? cp : f6;
+    f[7] = vd * B3 - Bd * v3;
+    f[8] = pp.ch * Bd;
+  }
+  __device__ static void ncprod_rd(const double* u, const double* wc, int d, double* o, const PhysParams&) {
+    const double ir = 1.0 / u[0];
+    const double v1 = u[1] * ir, v2 = u[2] * ir, v3 = u[3] * ir;
+    const double vd = d ? v2 : v1;
+    const double dB = wc[0], dpsi = wc[1];
     const double vB = v1 * u[5] + v2 * u[6] + v3 * u[7];
     o[0] = 0.0;
     o[1] = dB * u[5];
