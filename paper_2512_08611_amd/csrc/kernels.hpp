@@ -446,9 +446,11 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
   if (act) {
 #pragma unroll
     for (int v = 0; v < M; ++v) rvol_g[((size_t)v * kp.E + e) * P + p] = Ra[v];
-    // face traces: 2*DIM*NFP face points per element, strided over the element's threads
+    // face traces: (variable, face point) pairs of the element, variable
+    // slowest, over the element's threads
     constexpr int NFT = 2 * DIM * NFP;
-    for (int t = p; t < NFT; t += P) {
+    for (int w = p; w < NFT * M; w += P) {
+      const int v = w / NFT, t = w - v * NFT;
       const int d = t / (2 * NFP);
       const int rem = t - d * 2 * NFP;
       const int side = rem / NFP;
@@ -456,8 +458,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
       const double* V = side ? kp.VR : kp.VL;
       const size_t nf = (size_t)kp.E * NFP;
       const size_t fo = (size_t)e * NFP + q;
-#pragma unroll
-      for (int v = 0; v < M; ++v) {
+      {
         double tf = 0.0, tu = 0.0, tn = 0.0;
 #pragma unroll
         for (int r = 0; r < n1; ++r) {
@@ -661,10 +662,12 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
     for (int k = 0; k < H0; ++k)
       if (k < (d ? H1 : H0)) rvol_g[((size_t)(vo + k) * kp.E + e) * P + p] = Ra[k];
-    // face traces: 4*NFP face points per element over the element's 2P lanes
+    // face traces: (variable, face point) pairs of the element, variable
+    // slowest, over the element's 2P lanes
     constexpr int NFT = 4 * NFP;
     const int tl = 2 * p + d;
-    for (int t = tl; t < NFT; t += 2 * P) {
+    for (int w = tl; w < NFT * M; w += 2 * P) {
+      const int v = w / NFT, t = w - v * NFT;
       const int dd = t / (2 * NFP);
       const int rem = t - dd * 2 * NFP;
       const int side = rem / NFP;
@@ -672,8 +675,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
       const double* V = side ? kp.VR : kp.VL;
       const size_t nf = (size_t)kp.E * NFP;
       const size_t fo = (size_t)e * NFP + qq;
-#pragma unroll
-      for (int v = 0; v < M; ++v) {
+      {
         double tf = 0.0, tu = 0.0, tn = 0.0;
 #pragma unroll
         for (int r = 0; r < n1; ++r) {
@@ -741,21 +743,29 @@ __global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((
 // lower order fluxes f^{num,-}, f^{num,+}(uL, uR) of eq. combined.num.flux
 template <class Ph, int d>
 __device__ inline void low_flux(const double* uL, const double* uR, double* fm, double* fp, const PhysParams& pp) {
+  // few live arrays: the central part is formed in fc, then the two
+  // non-conservative parts are added one after the other
   constexpr int M = Ph::M;
-  double fL[M], fR[M], avg[M], bL[M], bR[M];
+  double fc[M], t[M];
   const double sl = Ph::template sigma<d>(uL, pp), sr = Ph::template sigma<d>(uR, pp);
   const double lam = sl >= sr ? sl : sr;
-  Ph::template flux<d>(uL, fL, pp);
-  Ph::template flux<d>(uR, fR, pp);
+  Ph::template flux<d>(uL, fc, pp);
+  Ph::template flux<d>(uR, t, pp);
 #pragma unroll
-  for (int v = 0; v < M; ++v) avg[v] = 0.5 * (uL[v] + uR[v]);
-  Ph::template ncprod<d>(uL, avg, bL, pp);
-  Ph::template ncprod<d>(uR, avg, bR, pp);
+  for (int v = 0; v < M; ++v) fc[v] = 0.5 * (fc[v] + t[v]) - 0.5 * lam * (uR[v] - uL[v]);
 #pragma unroll
-  for (int v = 0; v < M; ++v) {
-    const double fc = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
-    if (fm) fm[v] = fc + bL[v];
-    if (fp) fp[v] = fc + bR[v];
+  for (int v = 0; v < M; ++v) t[v] = 0.5 * (uL[v] + uR[v]);  // average state
+  if (fm) {
+    double b[M];
+    Ph::template ncprod<d>(uL, t, b, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) fm[v] = fc[v] + b[v];
+  }
+  if (fp) {
+    double b[M];
+    Ph::template ncprod<d>(uR, t, b, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) fp[v] = fc[v] + b[v];
   }
 }
 
@@ -767,7 +777,11 @@ __device__ inline bool admissible(const double* x, const PhysParams& pp) {
   return ok;
 }
 
-// one face point of direction d between element e (minus side) and en (plus side)
+// one face point of direction d between element e (minus side) and en (plus
+// side).  Written so that few values are live at once: the traces die once
+// F^num, U^num and the two correction offsets C^- = F_tr^- + B(u^{n,-}) U^-,
+// C^+ = F_tr^+ + B(u^{n,+}) U^+ are formed, and the candidate states of
+// Algorithm 1 are rebuilt for each constraint.
 template <class Ph, int N, int d>
 __device__ inline void face_point(const KParams& kp, const double* __restrict__ un_g, int e, int q, double dt,
                                   const PhysParams& pp) {
@@ -775,95 +789,114 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
   const int en = nbr_elem(kp, e, d, 1);
   const size_t nf = (size_t)kp.E * NFP;
   const size_t fiL = (size_t)e * NFP + q, fiR = (size_t)en * NFP + q;
-  double a[M], b[M], FL[M], FR[M], UL[M], UR[M], sL[M], sR[M];
+  // trace index of side (0 left face, 1 right face); u^n of point r along the line
+  auto tr = [&](int side, int v, size_t fi) { return ((size_t)(d * 2 + side) * M + v) * nf + fi; };
+  auto node = [&](int v, int el, int r) { return un_g[((size_t)v * kp.E + el) * P + node_at<n1>(d, q, r)]; };
+  double sL[M], sR[M];
 #pragma unroll
   for (int v = 0; v < M; ++v) {
-    const size_t oL = ((size_t)(d * 2 + 1) * M + v) * nf + fiL;
-    const size_t oR = ((size_t)(d * 2 + 0) * M + v) * nf + fiR;
-    a[v] = kp.untr[oL]; b[v] = kp.untr[oR];
-    FL[v] = kp.Ftr[oL]; FR[v] = kp.Ftr[oR];
-    UL[v] = kp.Utr[oL]; UR[v] = kp.Utr[oR];
-    sL[v] = un_g[((size_t)v * kp.E + e) * P + node_at<n1>(d, q, N)];
-    sR[v] = un_g[((size_t)v * kp.E + en) * P + node_at<n1>(d, q, 0)];
+    sL[v] = node(v, e, N);
+    sR[v] = node(v, en, 0);
   }
-  // wave speed from the face values of u^n; an inadmissible face value uses
-  // its neighbouring solution point instead
-  const double sa = admissible<Ph>(a, pp) ? Ph::template sigma<d>(a, pp) : Ph::template sigma<d>(sL, pp);
-  const double sb = admissible<Ph>(b, pp) ? Ph::template sigma<d>(b, pp) : Ph::template sigma<d>(sR, pp);
-  const double lam = sa >= sb ? sa : sb;
-  double Fnum[M], Unum[M], Ba[M], Bb[M], Fm[M], Fp[M];
+  double Fm[M], Fp[M], Cm[M], Cp[M];
+  {
+    double a[M], b[M], UL[M], UR[M];
 #pragma unroll
-  for (int v = 0; v < M; ++v) {
-    Fnum[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (UR[v] - UL[v]);
-    Unum[v] = 0.5 * (UL[v] + UR[v]);
+    for (int v = 0; v < M; ++v) {
+      a[v] = kp.untr[tr(1, v, fiL)];
+      b[v] = kp.untr[tr(0, v, fiR)];
+      UL[v] = kp.Utr[tr(1, v, fiL)];
+      UR[v] = kp.Utr[tr(0, v, fiR)];
+      Cm[v] = kp.Ftr[tr(1, v, fiL)];
+      Cp[v] = kp.Ftr[tr(0, v, fiR)];
+    }
+    // wave speed from the face values of u^n; an inadmissible face value uses
+    // its neighbouring solution point instead
+    const double sa = admissible<Ph>(a, pp) ? Ph::template sigma<d>(a, pp) : Ph::template sigma<d>(sL, pp);
+    const double sb = admissible<Ph>(b, pp) ? Ph::template sigma<d>(b, pp) : Ph::template sigma<d>(sR, pp);
+    const double lam = sa >= sb ? sa : sb;
+    double Unum[M], t[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      Fm[v] = 0.5 * (Cm[v] + Cp[v]) - 0.5 * lam * (UR[v] - UL[v]);  // F^num
+      Fp[v] = Fm[v];
+      Unum[v] = 0.5 * (UL[v] + UR[v]);
+    }
+    Ph::template ncprod<d>(a, Unum, t, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) Fm[v] += t[v];
+    Ph::template ncprod<d>(b, Unum, t, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) Fp[v] += t[v];
+    Ph::template ncprod<d>(a, UL, t, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) Cm[v] += t[v];
+    Ph::template ncprod<d>(b, UR, t, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) Cp[v] += t[v];
   }
-  Ph::template ncprod<d>(a, Unum, Ba, pp);
-  Ph::template ncprod<d>(b, Unum, Bb, pp);
   const double af = kp.blending == 0 ? 0.0 : 0.5 * (kp.alpha[e] + kp.alpha[en]);
   double Theta = 1.0;
   bool guard = false;
-  if (af == 0.0 && kp.blending != 2) {
-#pragma unroll
-    for (int v = 0; v < M; ++v) { Fm[v] = Fnum[v] + Ba[v]; Fp[v] = Fnum[v] + Bb[v]; }
-  } else {
+  if (!(af == 0.0 && kp.blending != 2)) {
     double fLOm[M], fLOp[M];
     low_flux<Ph, d>(sL, sR, fLOm, fLOp, pp);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      Fm[v] = (1.0 - af) * (Fnum[v] + Ba[v]) + af * fLOm[v];
-      Fp[v] = (1.0 - af) * (Fnum[v] + Bb[v]) + af * fLOp[v];
+      Fm[v] = (1.0 - af) * Fm[v] + af * fLOm[v];
+      Fp[v] = (1.0 - af) * Fp[v] + af * fLOp[v];
     }
     if (kp.blending == 2 && N >= 1) {
       // Algorithm 1 with DIM*dt in the candidate updates of the two subcells
       // next to the face
-      double sLi[M], sRi[M], finL[M], finR[M];
+      double finL[M], finR[M];
+      {
+        double sLi[M], sRi[M];
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        sLi[v] = un_g[((size_t)v * kp.E + e) * P + node_at<n1>(d, q, N - 1)];
-        sRi[v] = un_g[((size_t)v * kp.E + en) * P + node_at<n1>(d, q, 1)];
+        for (int v = 0; v < M; ++v) {
+          sLi[v] = node(v, e, N - 1);
+          sRi[v] = node(v, en, 1);
+        }
+        low_flux<Ph, d>(sLi, sL, nullptr, finL, pp);
+        low_flux<Ph, d>(sR, sRi, finR, nullptr, pp);
       }
-      low_flux<Ph, d>(sLi, sL, nullptr, finL, pp);
-      low_flux<Ph, d>(sR, sRi, finR, nullptr, pp);
       const double cN = DIM * dt * kp.inv_wdx[d][N], c0 = DIM * dt * kp.inv_wdx[d][0];
-      double uNlo[M], u0lo[M], uN[M], u0[M];
-#pragma unroll
-      for (int v = 0; v < M; ++v) {
-        uNlo[v] = sL[v] - cN * (fLOm[v] - finL[v]);
-        u0lo[v] = sR[v] - c0 * (finR[v] - fLOp[v]);
-        uN[v] = sL[v] - cN * (Fm[v] - finL[v]);
-        u0[v] = sR[v] - c0 * (finR[v] - Fp[v]);
-      }
 #pragma unroll
       for (int k = 0; k < Ph::K; ++k) {
-        const double PN = Ph::constraint(k, uNlo, pp), P0 = Ph::constraint(k, u0lo, pp);
-        const double th0 = theta_limit(0.1 * P0, P0, Ph::constraint(k, u0, pp), guard);
-        const double thN = theta_limit(0.1 * PN, PN, Ph::constraint(k, uN, pp), guard);
+        double x[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = sL[v] - cN * (fLOm[v] - finL[v]);
+        const double PN = Ph::constraint(k, x, pp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = sR[v] - c0 * (finR[v] - fLOp[v]);
+        const double P0 = Ph::constraint(k, x, pp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = sR[v] - c0 * (finR[v] - Fp[v]);
+        const double th0 = theta_limit(0.1 * P0, P0, Ph::constraint(k, x, pp), guard);
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = sL[v] - cN * (Fm[v] - finL[v]);
+        const double thN = theta_limit(0.1 * PN, PN, Ph::constraint(k, x, pp), guard);
         const double th = th0 <= thN ? th0 : thN;
         if (th < 1.0) {
 #pragma unroll
           for (int v = 0; v < M; ++v) {
             Fm[v] = th * Fm[v] + (1.0 - th) * fLOm[v];
             Fp[v] = th * Fp[v] + (1.0 - th) * fLOp[v];
-            uN[v] = sL[v] - cN * (Fm[v] - finL[v]);
-            u0[v] = sR[v] - c0 * (finR[v] - Fp[v]);
           }
         }
         Theta *= th;
       }
     }
   }
-  // outputs: F^± and the correction differences F^± - F_tr^± - B(u^{n,±}) U^±
-  double nca[M], ncb[M];
-  Ph::template ncprod<d>(a, UL, nca, pp);
-  Ph::template ncprod<d>(b, UR, ncb, pp);
+  // outputs: F^± and the correction differences F^± - (F_tr^± + B(u^{n,±}) U^±)
   const size_t fo = (size_t)d * nf + fiL;
 #pragma unroll
   for (int v = 0; v < M; ++v) {
     const size_t o = ((size_t)d * M + v) * nf + fiL;
     kp.Fm[o] = Fm[v];
     kp.Fp[o] = Fp[v];
-    kp.Dm[o] = Fm[v] - FL[v] - nca[v];
-    kp.Dp[o] = Fp[v] - FR[v] - ncb[v];
+    kp.Dm[o] = Fm[v] - Cm[v];
+    kp.Dp[o] = Fp[v] - Cp[v];
   }
   kp.theta_face[fo] = Theta;
   kp.guard_face[fo] = guard ? 1u : 0u;
@@ -883,8 +916,14 @@ __device__ __forceinline__ void faces_body(const KParams& kp, const double* __re
   else if constexpr (DIM == 2) face_point<Ph, N, 1>(kp, un_g, e, q, dt, pp);
 }
 
+#ifndef FACES_WAVES_PER_EU
+#define FACES_WAVES_PER_EU 1
+#endif
+// at least FACES_WAVES_PER_EU waves per SIMD: the scheduler otherwise hoists
+// every load of the 9-variable systems and runs at one wave per SIMD
 template <class Ph, int N>
-__global__ void __launch_bounds__(256) k_faces(const KParams kp, const double* __restrict__ un_g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES_WAVES_PER_EU)))
+    k_faces(const KParams kp, const double* __restrict__ un_g) {
   faces_body<Ph, N>(kp, un_g, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
