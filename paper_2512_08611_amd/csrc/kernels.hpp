@@ -501,31 +501,36 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
 // that half, and both rebuild the full stage state from their halves.  Same
 // arithmetic as the one-lane body, about half the registers per lane.
 //
-// Lane t of the workgroup takes direction (t >> 4) & 1 and point slot
-// 16 (t >> 5) + (t & 15): each group of 16 lanes (one LDS cycle of a 64-bit
-// access) reads along a single direction, which keeps the derivative reads
-// free of bank conflicts, and partners sit in neighbouring 16-lane rows, where
-// v_permlane16_swap exchanges them without LDS.
-__device__ inline unsigned int partner16(unsigned int x, bool odd_row) {
-  // rows 2k and 2k+1 of the wave exchange x
-  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-  return odd_row ? r[0] : r[1];
-}
-__device__ inline double swap_pair(double x, bool odd_row) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const unsigned int lo = partner16((unsigned int)(b & 0xffffffffULL), odd_row);
-  const unsigned int hi = partner16((unsigned int)(b >> 32), odd_row);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+// Lane t of the workgroup takes direction (t >> 5) & 1 and point slot
+// 32 (t >> 6) + (t & 31): each half-wave reads along a single direction, which
+// keeps the derivative reads free of LDS bank conflicts, and partners sit in
+// the two halves of one wave, where v_permlane32_swap exchanges them without
+// LDS.
+// v_permlane32_swap exchanges the upper half-wave of its first operand with
+// the lower half-wave of its second.  Each lane passes (a, b); afterwards the
+// lane holds (a of the lower-half lane, b of the upper-half lane) of its pair:
+// with a the value for the first half of the variables and b for the second,
+// every lane ends with the first-half value from direction 0 and the
+// second-half value from direction 1, without selects.
+__device__ inline void cross_pair(double& a, double& b) {
+  const unsigned long long ba = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned int)(ba & 0xffffffffULL),
+                                                   (unsigned int)(bb & 0xffffffffULL), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned int)(ba >> 32), (unsigned int)(bb >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
 }
 
 // threads of a two-lane stage workgroup holding EPB elements of P points: whole
-// pairs of 16-lane rows
-constexpr int stages2_threads(int EPB, int P) { return (2 * EPB * P + 31) / 32 * 32; }
+// waves
+constexpr int stages2_threads(int EPB, int P) { return (2 * EPB * P + 63) / 64 * 64; }
 
 template <class Ph, int N, int NT>
 struct Stages2Lds {
   static constexpr int M = Ph::M, P = ipow(N + 1, 2), EL = (NT / 2 + P - 1) / P, NCD = Ph::NCD;
-  static constexpr int NBUF = (2 * M + 2 * NCD) > (3 * M) ? (2 * M + 2 * NCD) : (3 * M);
+  // stages: f_x, f_y, the non-conservative columns; end: F_x, F_y, U, u^n
+  static constexpr int NBUF = (2 * M + 2 * NCD) > (4 * M) ? (2 * M + 2 * NCD) : (4 * M);
   double s_buf[EL][NBUF][P + LWFR_STAGES_PAD];
 };
 
@@ -541,8 +546,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
   auto& s_buf = L.s_buf;
 
   const int tid = threadIdx.x;
-  const int d = (tid >> 4) & 1, np = ((tid >> 5) << 4) | (tid & 15);
-  const bool odd = d != 0;  // odd 16-lane row of its pair
+  const int d = (tid >> 5) & 1, np = ((tid >> 6) << 5) | (tid & 31);
   const int le = np / P, p = np - le * P;
   const int e = blk * EPB + le;
   const bool act = le < EPB && e < kp.E;
@@ -580,9 +584,11 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     for (int k = 0; k < H0; ++k) uh[k] = first_nz<N>(st) >= 0 ? uo[k] - dt * Sp[st][k] : uo[k];
 #pragma unroll
     for (int k = 0; k < H0; ++k) {
-      const double other = swap_pair(uh[k], odd);
-      u[k] = d ? other : uh[k];
-      if (k < H1) u[H0 + k] = d ? uh[k] : other;
+      // direction 0 holds the first half, direction 1 the second
+      double a = uh[k], b = uh[k];
+      cross_pair(a, b);
+      u[k] = a;
+      if (k < H1) u[H0 + k] = b;
     }
     double f[M];
     Ph::flux_rd(u, d, f, pp);
@@ -631,10 +637,11 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     double Lh[H0];
 #pragma unroll
     for (int k = 0; k < H0; ++k) {
-      const double send = d ? Ld[k] : (k < H1 ? Ld[H0 + k] : 0.0);
-      const double got = swap_pair(send, odd);
-      const double mine = d ? (k < H1 ? Ld[H0 + k] : 0.0) : Ld[k];
-      Lh[k] = d ? got + mine : mine + got;
+      // (L_d of variable k, L_d of variable H0 + k) from both directions:
+      // afterwards a = L_x and b = L_y of the lane's own variable
+      double a = Ld[k], b = k < H1 ? Ld[H0 + k] : 0.0;
+      cross_pair(a, b);
+      Lh[k] = a + b;
     }
     if (bs != 0.0) {
 #pragma unroll
@@ -650,12 +657,15 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     }
   }
 
-  // time-averaged flux (lane's direction) and solution (lane's half) to LDS
+  // time-averaged flux (lane's direction), solution and u^n (lane's half) to LDS
 #pragma unroll
   for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = Fa[v];
 #pragma unroll
   for (int k = 0; k < H0; ++k)
-    if (k < (d ? H1 : H0)) s_buf[le][2 * M + vo + k][p] = Ua[k];
+    if (k < (d ? H1 : H0)) {
+      s_buf[le][2 * M + vo + k][p] = Ua[k];
+      s_buf[le][3 * M + vo + k][p] = uo[k];
+    }
   __syncthreads();
 
   if (act) {
@@ -682,7 +692,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
           const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
           tf += V[r] * s_buf[le][dd * M + v][nd];
           tu += V[r] * s_buf[le][2 * M + v][nd];
-          tn += V[r] * un_g[((size_t)v * kp.E + e) * P + nd];
+          tn += V[r] * s_buf[le][3 * M + v][nd];
         }
         const size_t o = ((size_t)(dd * 2 + side) * M + v) * nf + fo;
         kp.Ftr[o] = tf;
