@@ -229,6 +229,14 @@ def main():
     avg_ms = per_kernel["k_stages"]["ms_per_launch"]
     flops = STAGE_LOOP_FLOPS_PER_DOF.get(("GLMMHD2D", N))
     achieved = flops * dofs / (avg_ms * 1e-3) / 1e12 if flops else None
+    # HBM bytes per launch of the stage kernel from the committed counter summary
+    # of this workload, only while it was taken on the current kernel sources
+    from paper_2512_08611_amd import counters
+
+    traffic, traffic_us = (None, None)
+    if (n, N) == (256, 4):
+        traffic, traffic_us = counters.read_traffic(os.path.join(ROOT, "profiles", "counters_mhd256_n4.md"),
+                                                    f"k_stages<MHD2D, {N},")
     roofline = {
         "kernel": "k_stages",
         "bound": "alu",
@@ -236,7 +244,9 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS if achieved else None,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a device copy)",
+        "traffic_profile_mean_us": traffic_us,
         "algorithmic_flops_per_launch": flops * dofs if flops else None,
         "dominant_kernel_by_time": dom,
     }

@@ -1,0 +1,138 @@
+"""Summaries of rocprofv3 runs of bench.py: kernel durations and HBM bytes.
+
+A summary (a short markdown file under profiles/) records, per kernel of one
+workload: the mean duration from a --kernel-trace --stats run, and the HBM
+bytes per launch from two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+dispatch).  Each counter is scaled by what it reads for a plain device copy of
+known size in the same run (the copy bench.py --copy-calibration issues), so
+bytes = FETCH_SIZE * 1024 * copied/FETCH_SIZE(copy) and likewise for writes.
+
+The summary carries a digest of the kernel sources (csrc/*, include/lwfr.h);
+bench.py reports the measured traffic only while the digest matches the
+current sources, and null otherwise.
+
+  python -m paper_2512_08611_amd.counters --stats KT_STATS.csv --fetch FETCH.csv \\
+      --write WRITE.csv --copy-bytes 268435456 --match MHD2D --out profiles/NAME.md \\
+      --command "..." [--command "..."]
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(_HERE)
+
+
+def sources_digest(root=ROOT):
+    """sha256 over the kernel sources and the C ABI header, in name order."""
+    files = sorted(glob.glob(os.path.join(root, "paper_2512_08611_amd", "csrc", "*")))
+    files.append(os.path.join(root, "include", "lwfr.h"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _short(name):
+    """'void lwfr::k_stages<lwfr::MHD2D, 4, 5>(...)' -> 'k_stages<MHD2D, 4, 5>'."""
+    n = name.split("(")[0].replace("void ", "").replace("lwfr::", "")
+    return n.strip()
+
+
+def _counter_means(path, counter):
+    vals = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        vals.setdefault(_short(r["Kernel_Name"]), []).append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return vals
+
+
+def _copy_factor(vals, copy_bytes):
+    """bytes per counter KiB from the largest device copy in the run."""
+    copies = [v for k, lst in vals.items() if "copyBuffer" in k for v in lst]
+    if not copies:
+        raise ValueError("no device copy in the counter run (run bench.py with --copy-calibration)")
+    grid, kib = max(copies)
+    return copy_bytes / kib
+
+
+def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match):
+    """{kernel: {mean_us, calls, fetch_bytes, write_bytes}} for kernels whose name contains `match`,
+    and the two calibration factors."""
+    out = {}
+    for r in csv.DictReader(open(stats_csv)):
+        k = _short(r["Name"])
+        if match in k:
+            out[k] = {"mean_us": float(r["AverageNs"]) / 1e3, "calls": int(r["Calls"])}
+    fv = _counter_means(fetch_csv, "FETCH_SIZE")
+    wv = _counter_means(write_csv, "WRITE_SIZE")
+    ff = _copy_factor(fv, copy_bytes)
+    fw = _copy_factor(wv, copy_bytes)
+    for k in out:
+        f = [v for _, v in fv.get(k, [])]
+        w = [v for _, v in wv.get(k, [])]
+        out[k]["fetch_bytes"] = ff * sum(f) / len(f) if f else None
+        out[k]["write_bytes"] = fw * sum(w) / len(w) if w else None
+    return out, ff, fw
+
+
+def write_md(path, title, summary, ff, fw, commands, digest):
+    lines = [f"# {title}", "", "Commands (from the repository root R on the GPU box; the counter passes are separate runs):", ""]
+    lines += ["```"] + list(commands) + ["```", ""]
+    lines += [f"Calibration (256 MiB device copy in the same runs): FETCH_SIZE x {ff / 1024:.3f} KiB, "
+              f"WRITE_SIZE x {fw / 1024:.3f} KiB per counted KiB.", ""]
+    lines += ["| kernel | calls | mean (us) | HBM read (MB/launch) | HBM write (MB/launch) | GB/s |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(summary.items(), key=lambda kv: -kv[1]["mean_us"] * kv[1]["calls"]):
+        rd = v["fetch_bytes"] or 0.0
+        wr = v["write_bytes"] or 0.0
+        bw = (rd + wr) / (v["mean_us"] * 1e-6) / 1e9 if v["mean_us"] else 0.0
+        lines.append(f"| `{k}` | {v['calls']} | {v['mean_us']:.1f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {bw:.0f} |")
+    lines += ["", f"kernel sources sha256: {digest}", ""]
+    for k, v in sorted(summary.items()):
+        if v["fetch_bytes"] is not None and v["write_bytes"] is not None:
+            lines.append(f"traffic_bytes {k} {v['fetch_bytes'] + v['write_bytes']:.0f} mean_us {v['mean_us']:.3f}")
+    open(path, "w").write("\n".join(lines) + "\n")
+
+
+def read_traffic(path, kernel_prefix, digest=None):
+    """(bytes per launch, mean us) of the first kernel whose name starts with kernel_prefix in the
+    summary at path, or (None, None) if missing or if the summary's source digest differs."""
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != (digest or sources_digest()):
+        return None, None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes "):
+            parts = line.split()
+            # traffic_bytes <name with spaces> <bytes> mean_us <us>
+            name = " ".join(parts[1:-3])
+            if name.startswith(kernel_prefix):
+                return float(parts[-3]), float(parts[-1])
+    return None, None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--stats", required=True, help="rocprofv3 --stats kernel_stats.csv")
+    ap.add_argument("--fetch", required=True, help="counter_collection.csv of the FETCH_SIZE run")
+    ap.add_argument("--write", required=True, help="counter_collection.csv of the WRITE_SIZE run")
+    ap.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
+    ap.add_argument("--match", default="MHD2D")
+    ap.add_argument("--title", default="Kernel durations and HBM traffic")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    s, ff, fw = summarize(a.stats, a.fetch, a.write, a.copy_bytes, a.match)
+    write_md(a.out, a.title, s, ff, fw, a.command, sources_digest())
+
+
+if __name__ == "__main__":
+    main()

@@ -529,9 +529,13 @@ constexpr int stages2_threads(int EPB, int P) { return (2 * EPB * P + 63) / 64 *
 template <class Ph, int N, int NT>
 struct Stages2Lds {
   static constexpr int M = Ph::M, P = ipow(N + 1, 2), EL = (NT / 2 + P - 1) / P, NCD = Ph::NCD;
-  // stages: f_x, f_y, the non-conservative columns; end: F_x, F_y, U, u^n
+  // stages: f_x, f_y, the non-conservative columns; end: F_x, F_y, U, u^n.
+  // Field f of element slot le at s_buf[le][f * P + point]; the slot stride ES
+  // is padded to ES = P (mod 32) so that the point slots of a half-wave, which
+  // run over into the next element, stay consecutive in bank order
   static constexpr int NBUF = (2 * M + 2 * NCD) > (4 * M) ? (2 * M + 2 * NCD) : (4 * M);
-  double s_buf[EL][NBUF][P + LWFR_STAGES_PAD];
+  static constexpr int ES = NBUF * P + (((P - NBUF * P) % 32) + 32) % 32;
+  double s_buf[EL][ES];
 };
 
 template <class Ph, int N, int EPB, int NT>
@@ -594,11 +598,11 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     Ph::flux_rd(u, d, f, pp);
 #pragma unroll
     for (int v = 0; v < M; ++v)
-      if (Ph::flux_nc_alias(v) < 0) s_buf[le][d * M + v][p] = f[v];
+      if (Ph::flux_nc_alias(v) < 0) s_buf[le][(d * M + v) * P + (p)] = f[v];
 #pragma unroll
     for (int c = 0; c < NCD; ++c) {
       const double x0 = u[Ph::nc_comp(0, c)], x1 = u[Ph::nc_comp(1, c)];
-      s_buf[le][2 * M + d * NCD + c][p] = d ? x1 : x0;
+      s_buf[le][(2 * M + d * NCD + c) * P + (p)] = d ? x1 : x0;
     }
     const double bs = Tab::b(st);
     if (bs != 0.0) {
@@ -616,7 +620,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
       for (int c = 0; c < NCD; ++c) {
         double sacc = 0.0;
 #pragma unroll
-        for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][2 * M + d * NCD + c][q * sq + r * sr];
+        for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][(2 * M + d * NCD + c) * P + (q * sq + r * sr)];
         wc[c] = sacc;
       }
       Ph::ncprod_rd(u, wc, d, nc, pp);
@@ -627,7 +631,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
           sacc = pp.ch * wc[Ph::flux_nc_alias(v)];  // D_d (c_h w) = c_h D_d w
         } else {
 #pragma unroll
-          for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][d * M + v][q * sq + r * sr];
+          for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][(d * M + v) * P + (q * sq + r * sr)];
         }
         Ld[v] = (sacc + nc[v]) * idx;
       }
@@ -659,12 +663,12 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
 
   // time-averaged flux (lane's direction), solution and u^n (lane's half) to LDS
 #pragma unroll
-  for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = Fa[v];
+  for (int v = 0; v < M; ++v) s_buf[le][(d * M + v) * P + (p)] = Fa[v];
 #pragma unroll
   for (int k = 0; k < H0; ++k)
     if (k < (d ? H1 : H0)) {
-      s_buf[le][2 * M + vo + k][p] = Ua[k];
-      s_buf[le][3 * M + vo + k][p] = uo[k];
+      s_buf[le][(2 * M + vo + k) * P + (p)] = Ua[k];
+      s_buf[le][(3 * M + vo + k) * P + (p)] = uo[k];
     }
   __syncthreads();
 
@@ -690,9 +694,9 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
         for (int r = 0; r < n1; ++r) {
           const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
-          tf += V[r] * s_buf[le][dd * M + v][nd];
-          tu += V[r] * s_buf[le][2 * M + v][nd];
-          tn += V[r] * s_buf[le][3 * M + v][nd];
+          tf += V[r] * s_buf[le][(dd * M + v) * P + (nd)];
+          tu += V[r] * s_buf[le][(2 * M + v) * P + (nd)];
+          tn += V[r] * s_buf[le][(3 * M + v) * P + (nd)];
         }
         const size_t o = ((size_t)(dd * 2 + side) * M + v) * nf + fo;
         kp.Ftr[o] = tf;

@@ -31,3 +31,20 @@ def test_multi_gpu_request_exits_with_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_counter_summary_is_tied_to_the_kernel_sources(tmp_path):
+    """bench.py reports measured HBM traffic only from a summary taken on the current kernels."""
+    from paper_2512_08611_amd import counters
+
+    digest = counters.sources_digest()
+    text = ("kernel sources sha256: " + digest + "\n"
+            "traffic_bytes k_stages<MHD2D, 4, 5> 575303840 mean_us 326.444\n"
+            "traffic_bytes k_faces<MHD2D, 4> 1103491788 mean_us 191.364\n")
+    p = tmp_path / "s.md"
+    p.write_text(text)
+    assert counters.read_traffic(str(p), "k_stages<MHD2D, 4,") == (575303840.0, 326.444)
+    assert counters.read_traffic(str(p), "k_faces<MHD2D, 4>") == (1103491788.0, 191.364)
+    assert counters.read_traffic(str(p), "k_update") == (None, None)
+    assert counters.read_traffic(str(p), "k_stages", digest="0" * 64) == (None, None)
+    assert counters.read_traffic(str(tmp_path / "missing.md"), "k_stages") == (None, None)
