@@ -42,6 +42,7 @@ class OraCfg(ctypes.Structure):
         ("cs", ctypes.c_double), ("cfl", ctypes.c_double),
         ("blending", ctypes.c_int32),
         ("alpha_max", ctypes.c_double), ("alpha_min", ctypes.c_double), ("alpha_force", ctypes.c_double),
+        ("gll", ctypes.c_int32),
     ]
 
 
@@ -59,14 +60,17 @@ def _p(a, ctype=ctypes.c_double):
 
 
 def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81, cs=0.9,
-             cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0):
+             cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0, gll=False):
+    """gll: Gauss-Lobatto-Legendre solution points with the g_2 correction (App. B)
+    instead of Gauss-Legendre points with the Radau correction."""
     c = OraCfg()
     c.eq, c.N, c.nx, c.ny = eq, N, nx, (ny if DIMS[eq] == 2 else 1)
     c.lo[0], c.lo[1] = lo
     c.hi[0], c.hi[1] = hi
     c.gamma, c.gravity, c.cs = gamma, gravity, cs
-    c.cfl = cfl_number(N) if cfl is None else cfl
+    c.cfl = cfl_number(N, gll) if cfl is None else cfl
     c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
+    c.gll = 1 if gll else 0
     return c
 
 
@@ -80,12 +84,12 @@ def nfp(c):
     return 1 if DIMS[c.eq] == 1 else c.N + 1
 
 
-def refel(N):
+def refel(N, gll=False):
     n1 = N + 1
     out = {k: np.zeros(n1) for k in ("xi", "w", "VL", "VR", "gLp", "gRp")}
     D = np.zeros((n1, n1))
     Leg = np.zeros((n1, n1))
-    rc = lib().ora_refel(N, _p(out["xi"]), _p(out["w"]), _p(D), _p(out["VL"]), _p(out["VR"]),
+    rc = lib().ora_refel(N, 1 if gll else 0, _p(out["xi"]), _p(out["w"]), _p(D), _p(out["VL"]), _p(out["VR"]),
                          _p(out["gLp"]), _p(out["gRp"]), _p(Leg))
     assert rc == 0
     out["D"], out["Leg"] = D, Leg

@@ -16,6 +16,7 @@ struct ora_cfg {
   double cs, cfl;
   int32_t blending;
   double alpha_max, alpha_min, alpha_force;
+  int32_t gll;
 };
 
 static Config to_cfg(const ora_cfg* c) {
@@ -25,6 +26,7 @@ static Config to_cfg(const ora_cfg* c) {
   k.gamma = c->gamma; k.gravity = c->gravity; k.cs = c->cs; k.cfl = c->cfl;
   k.blending = c->blending; k.alpha_max = c->alpha_max; k.alpha_min = c->alpha_min;
   k.alpha_force = c->alpha_force;
+  k.gll = c->gll;
   return k;
 }
 
@@ -33,6 +35,7 @@ template <class Fn>
 static int dispatch(const ora_cfg* c, Fn fn) {
   Config k = to_cfg(c);
   if (k.N < 0 || k.N > 4 || k.nx < 1 || k.ny < 1) return 1;
+  if (k.gll && k.N < 1) return 1;
   switch (k.eq) {
     case EQ_SW1D: { SW1D ph{k.gravity}; Scheme<SW1D> s(ph, k); fn(s); return 0; }
     case EQ_SW2D: { SW2D ph{k.gravity}; Scheme<SW2D> s(ph, k); fn(s); return 0; }
@@ -45,10 +48,10 @@ static int dispatch(const ora_cfg* c, Fn fn) {
 
 extern "C" {
 
-int ora_refel(int N, double* xi, double* w, double* D, double* VL, double* VR, double* gLp, double* gRp,
+int ora_refel(int N, int gll, double* xi, double* w, double* D, double* VL, double* VR, double* gLp, double* gRp,
               double* Leg) {
-  if (N < 0 || N > 8) return 1;
-  RefElem r(N);
+  if (N < 0 || N > 8 || (gll && N < 1)) return 1;
+  RefElem r(N, gll != 0);
   int n1 = N + 1;
   std::memcpy(xi, r.xi.data(), n1 * sizeof(double));
   std::memcpy(w, r.w.data(), n1 * sizeof(double));

@@ -42,8 +42,9 @@ def max_growth(N, nu, re, ntheta=721):
 
 
 @functools.lru_cache(maxsize=None)
-def cfl_number(N):
-    """Largest nu with rho(G) <= 1 + tol for degree N (bisection to 1e-10 in nu).
+def cfl_number(N, gll=False):
+    """Largest nu with rho(G) <= 1 + tol for degree N (bisection to 1e-10 in nu);
+    gll: Gauss-Lobatto-Legendre points with the g_2 correction.
 
     tol = 1e-12 for N <= 3.  For N = 4 the order-5 Taylor weights leave nearly
     undamped modes a weak growth of order (nu theta)^6 (about 5e-6 per step
@@ -54,7 +55,7 @@ def cfl_number(N):
     tol = 1e-12 if N <= 3 else 1e-5
     from . import refel
 
-    re = refel(N)
+    re = refel(N, gll)
     lo, hi = 0.0, 1.5
     while hi - lo > 1e-10:
         mid = 0.5 * (lo + hi)

@@ -42,6 +42,7 @@ struct Config {
   int blending;    // 0: pure high order; 1: indicator blend; 2: blend + Alg. 1 + Alg. 2
   double alpha_max, alpha_min;
   double alpha_force;  // >= 0: every alpha_e is set to this value (tests, residual modes)
+  int gll = 0;         // 1: Gauss-Lobatto-Legendre solution points with g_2 correction (App. B)
 };
 
 enum : uint32_t {
@@ -72,7 +73,7 @@ struct Scheme {
   double dx[2];
 
   Scheme(const Phys& p, const Config& c)
-      : ph(p), cfg(c), re(c.N), tb(c.N), N(c.N), n1(c.N + 1) {
+      : ph(p), cfg(c), re(c.N, c.gll != 0), tb(c.N), N(c.N), n1(c.N + 1) {
     P = DIM == 1 ? n1 : n1 * n1;
     nfp = DIM == 1 ? 1 : n1;
     nx = c.nx; ny = DIM == 1 ? 1 : c.ny;
