@@ -167,6 +167,40 @@ def batched(torch, lwfr, workloads, np, steps=50, count=64):
     }
 
 
+def variant_timing(torch, lwfr, workloads, np, n, N, flags, steps, name):
+    """ms per step of the default workload with other lwfr_config.flags (e.g. GLL points)."""
+    dev = torch.device("cuda:0")
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), cfl_safety=0.9, blending=2, flags=flags)
+    st = lwfr.Stepper(cfg, dev)
+    ua = torch.tensor(workloads.mhd_smooth(np.array(st.xi), n, n, seed=0), dtype=torch.float64, device=dev)
+    ub = torch.empty_like(ua)
+    for _ in range(3):
+        st.step(ua, ub)
+        ua, ub = ub, ua
+    lwfr.lwfr_timing_begin(st.ctx, 8 * steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step(ua, ub)
+        ua, ub = ub, ua
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = lwfr.lwfr_timing_end(st.ctx)
+    status, flags_or = st.query()
+    dofs = n * n * (N + 1) ** 2
+    return {
+        "variant": name,
+        "workload": f"GLM-MHD {n}x{n}, N={N}, same data and settings as the main line",
+        "value": dofs * steps / wall,
+        "unit": "DOF-updates/s",
+        "ms_per_step": wall / steps * 1e3,
+        "cfl_number": lwfr.lwfr_cfl_number(N, flags),
+        "kernels_ms_per_launch": {k: ms / c for k, (ms, c) in kern.items() if c},
+        "step_status": int(status),
+        "flags_or": int(flags_or),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -282,6 +316,8 @@ def main():
         out["adjoint_over_forward"] = adjoint_over_forward(torch, lwfr, workloads, np)
     if not args.no_batch:
         out["batched"] = batched(torch, lwfr, workloads, np)
+    out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_GLL, K,
+                                   "Gauss-Lobatto-Legendre points with the g_2 correction")
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

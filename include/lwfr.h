@@ -91,6 +91,12 @@ typedef struct {
 
 /* lwfr_config.flags: reserve the workspace of lwfr_adjoint_step */
 #define LWFR_CFG_ADJOINT 1u
+/* lwfr_config.flags: Gauss-Lobatto-Legendre solution points with the g_2
+ * correction functions (App. B, the variant after eq. fr.form.non.cons: GLL
+ * points on [0,1], g_R'(xi_p) = delta_pN/w_p, g_L'(xi_p) = -delta_p0/w_p) in
+ * place of Gauss-Legendre points with the Radau correction.  Subcell widths
+ * are the GLL weights; cfl_number = 0 takes the Fourier limit of this scheme. */
+#define LWFR_CFG_GLL 2u
 
 /* Validates cfg and builds the reference element, tableau and launch shapes on
  * the host.  No device work.  *out receives a context owned by the caller
@@ -110,6 +116,9 @@ lwfr_status lwfr_reference_nodes(const lwfr_ctx* ctx, double* xi, double* w);
 
 /* The library's Fourier (von Neumann) CFL(N) of the linearised scheme. */
 lwfr_status lwfr_cfl_number(int32_t degree, double* cfl);
+/* As lwfr_cfl_number for the scheme that lwfr_config.flags cfg_flags select
+ * (LWFR_CFG_GLL). */
+lwfr_status lwfr_cfl_number_for(int32_t degree, uint32_t cfg_flags, double* cfl);
 
 /* Attaches caller-owned device workspace and a HIP stream (hipStream_t passed as
  * void*; NULL = default stream).  The workspace must stay valid until the next

@@ -512,6 +512,13 @@ lwfr_status lwfr_cfl_number(int32_t degree, double* cfl) {
   return LWFR_OK;
 }
 
+lwfr_status lwfr_cfl_number_for(int32_t degree, uint32_t cfg_flags, double* cfl) {
+  if (!cfl) return fail(LWFR_E_INVALID_ARG, "cfl is null");
+  if (degree < 1 || degree > 4) return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
+  *cfl = fourier_cfl(degree, (cfg_flags & LWFR_CFG_GLL) != 0);
+  return LWFR_OK;
+}
+
 lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   if (!cfg || !out) return fail(LWFR_E_INVALID_ARG, "null argument");
   *out = nullptr;
@@ -546,8 +553,9 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     c->nblk_pre = (c->E + epb - 1) / epb;  // k_pre: 256/P elements per block
     c->nblk_ch = (c->E + 255) / 256;       // k_ch: one thread per element
   }
-  c->rd = make_refdata(c->N);
-  c->cfl = cfg->cfl_number > 0.0 ? cfg->cfl_number : fourier_cfl(c->N);
+  const bool gll = (cfg->flags & LWFR_CFG_GLL) != 0;
+  c->rd = make_refdata(c->N, gll);
+  c->cfl = cfg->cfl_number > 0.0 ? cfg->cfl_number : fourier_cfl(c->N, gll);
 
   KParams& kp = c->kp;
   std::memset(&kp, 0, sizeof(kp));

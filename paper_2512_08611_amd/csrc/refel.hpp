@@ -2,10 +2,13 @@
 //
 // Solution points: Gauss-Legendre nodes on [0,1] (paper §2 eq. soln.points),
 // found by Newton's method on P_{N+1} from Chebyshev starting points; weights
-// 1/((1-z^2) P'_{N+1}(z)^2) mapped to [0,1].  Lagrange data use the barycentric
-// form: D_ij = (l_j/l_i)/(x_i - x_j), D_ii = -sum_{j!=i} D_ij (eq. diff.matrix);
-// the Radau correction slopes use App. B eq. correction.identities,
-// g_R'(xi_p) = l_p(1)/w_p and g_L'(xi_p) = -l_p(0)/w_p.
+// 1/((1-z^2) P'_{N+1}(z)^2) mapped to [0,1].  Or, for the variant of App. B,
+// Gauss-Lobatto-Legendre nodes: the ends and the roots of P_N' (Newton, P_N''
+// from Legendre's equation), weights 1/(N(N+1) P_N(z)^2) on [0,1].  Lagrange
+// data use the barycentric form: D_ij = (l_j/l_i)/(x_i - x_j),
+// D_ii = -sum_{j!=i} D_ij (eq. diff.matrix); the correction slopes use App. B
+// eq. correction.identities, g_R'(xi_p) = l_p(1)/w_p and g_L'(xi_p) = -l_p(0)/w_p
+// (Radau correction with GL points, g_2 with GLL points).
 #pragma once
 #include <cmath>
 #include <complex>
@@ -37,13 +40,33 @@ inline void legendre_pair(int n, double z, double& P, double& dP) {
   dP = n * (z * p - pm1) / (z * z - 1.0);
 }
 
-inline RefData make_refdata(int N) {
+inline RefData make_refdata(int N, bool gll = false) {
   RefData r{};
   r.N = N;
   r.n1 = N + 1;
   const int n = N + 1;
   const double pi = 3.141592653589793238462643;
-  for (int i = 0; i < n; ++i) {
+  if (gll && N >= 1) {
+    for (int i = 0; i < n; ++i) {
+      double z = i == 0 ? -1.0 : i == N ? 1.0 : -std::cos(pi * i / N);
+      double P, dP;
+      if (i > 0 && i < N) {
+        for (int it = 0; it < 60; ++it) {
+          legendre_pair(N, z, P, dP);
+          const double d2P = (2.0 * z * dP - N * (N + 1.0) * P) / (1.0 - z * z);
+          const double dz = dP / d2P;
+          z -= dz;
+          if (std::fabs(dz) < 1e-17) break;
+        }
+        legendre_pair(N, z, P, dP);
+      } else {
+        P = (i == 0 && N % 2 == 1) ? -1.0 : 1.0;  // P_N(+-1) = (+-1)^N
+      }
+      r.xi[i] = 0.5 * (z + 1.0);
+      r.w[i] = 1.0 / (N * (N + 1.0) * P * P);
+    }
+  }
+  for (int i = 0; i < n && !(gll && N >= 1); ++i) {
     // ascending nodes: start from -cos(pi (2i+1)/(2n))
     double z = -std::cos(pi * (2.0 * i + 1.0) / (2.0 * n));
     double P, dP;
@@ -77,9 +100,17 @@ inline RefData make_refdata(int N) {
   }
   for (int end = 0; end < 2; ++end) {
     const double x = end;
+    double* V = end ? r.VR : r.VL;
+    int at = -1;  // an end that is itself a node (GLL): l_j(x) = delta
+    for (int j = 0; j < n; ++j)
+      if (x == r.xi[j]) at = j;
+    if (at >= 0) {
+      for (int j = 0; j < n; ++j) V[j] = j == at ? 1.0 : 0.0;
+      continue;
+    }
     double den = 0.0, num[kMaxN1];
     for (int j = 0; j < n; ++j) { num[j] = lam[j] / (x - r.xi[j]); den += num[j]; }
-    for (int j = 0; j < n; ++j) (end ? r.VR : r.VL)[j] = num[j] / den;
+    for (int j = 0; j < n; ++j) V[j] = num[j] / den;
   }
   for (int p = 0; p < n; ++p) {
     r.gR[p] = r.VR[p] / r.w[p];
@@ -192,8 +223,8 @@ inline double max_growth(const RefData& r, double nu) {
 }
 }  // namespace detail
 
-inline double fourier_cfl(int N) {
-  const RefData r = make_refdata(N);
+inline double fourier_cfl(int N, bool gll = false) {
+  const RefData r = make_refdata(N, gll);
   // degree 4: order-5 Taylor weights give nearly undamped modes a weak growth
   // (about 5e-6 per step below the limit); the limit is the sharp loss of
   // stability of the high-frequency modes

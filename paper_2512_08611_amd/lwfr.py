@@ -17,6 +17,7 @@ LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
 LWFR_E_INADMISSIBLE, LWFR_E_NONFINITE, LWFR_E_WORKSPACE, LWFR_E_STATE = 4, 5, 6, 7
 LWFR_EQ_SW1D, LWFR_EQ_SW2D, LWFR_EQ_GLMMHD2D, LWFR_EQ_LINADV1D, LWFR_EQ_VARADV1D = 1, 2, 3, 4, 5
 LWFR_CFG_ADJOINT = 1
+LWFR_CFG_GLL = 2
 LWFR_FLAG_ALG2, LWFR_FLAG_LOW_INADM, LWFR_FLAG_ALG1, LWFR_FLAG_NONFINITE, LWFR_FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
 
 NVARS = {1: 3, 2: 4, 3: 9, 4: 1, 5: 2}
@@ -56,6 +57,7 @@ _SIGS = {
     "lwfr_state_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "lwfr_reference_nodes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "lwfr_cfl_number": [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "lwfr_cfl_number_for": [ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)],
     "lwfr_bind": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "lwfr_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p],
@@ -168,9 +170,10 @@ def lwfr_reference_nodes(ctx, n1):
     return list(xi), list(w)
 
 
-def lwfr_cfl_number(degree):
+def lwfr_cfl_number(degree, flags=0):
+    """Fourier CFL(N) of the scheme that the config flags select (LWFR_CFG_GLL)."""
     c = ctypes.c_double()
-    _check(lib().lwfr_cfl_number(degree, ctypes.byref(c)))
+    _check(lib().lwfr_cfl_number_for(degree, int(flags), ctypes.byref(c)))
     return c.value
 
 

@@ -81,6 +81,20 @@ def test_fourier_cfl_matches_oracle(N):
     assert abs(lwfr.lwfr_cfl_number(N) - oracle.cfl_number(N)) < 2e-6 * oracle.cfl_number(N)
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+def test_gll_reference_data_and_cfl_match_oracle(N):
+    """GLL points: the library's nodes, weights and Fourier limit (host code) against the
+    oracle's independent construction."""
+    ctx = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_SW1D, N, 4, flags=lwfr.LWFR_CFG_GLL))
+    xi, w = lwfr.lwfr_reference_nodes(ctx, N + 1)
+    re_ = oracle.refel(N, gll=True)
+    np.testing.assert_allclose(xi, re_["xi"], atol=2e-16)
+    np.testing.assert_allclose(w, re_["w"], atol=2e-16)
+    lwfr.lwfr_destroy(ctx)
+    c = oracle.cfl_number(N, gll=True)
+    assert abs(lwfr.lwfr_cfl_number(N, lwfr.LWFR_CFG_GLL) - c) < 2e-6 * c
+
+
 def test_batch_host_side():
     """Batch set-up on the host: offsets, workspace size, validation (no GPU calls)."""
     L = lwfr.lib()

@@ -176,3 +176,30 @@ def test_adjoint_requires_flag():
     with pytest.raises(lwfr.LwfrError) as ei:
         st.adjoint_step(u, 1e-3, u, torch.empty_like(u))
     assert ei.value.status == lwfr.LWFR_E_STATE
+
+
+@pytest.mark.parametrize("eq,N,nx,ny", [(oracle.EQ_SW1D, 3, 13, 1), (oracle.EQ_MHD2D, 3, 5, 4), (oracle.EQ_MHD2D, 4, 4, 4)])
+def test_dot_product_gll(eq, N, nx, ny):
+    """The adjoint with GLL points and the g_2 correction against the oracle's forward mode.
+
+    Nodal interpolation at GLL points gives both sides of a face the same point,
+    so the two face states would be equal and the max of their wave speeds an
+    exact tie (both one-sided derivatives valid); a 1e-2 relative jitter per
+    point separates them."""
+    cfg = lwfr.make_config(eq, N, (nx, ny), cfl_number=0.1, blending=2,
+                           flags=lwfr.LWFR_CFG_ADJOINT | lwfr.LWFR_CFG_GLL)
+    st = lwfr.Stepper(cfg, DEV)
+    oc = oracle.make_cfg(eq, N, nx, ny, cfl=0.1, blending=2, gll=True)
+    xi = oracle.refel(N, gll=True)["xi"]
+    u = W.sw1d_wave(xi, nx, 2) if eq == oracle.EQ_SW1D else W.mhd_smooth(xi, nx, ny, 2, amp=0.05)
+    rng = np.random.default_rng(11)
+    u = u * (1 + 1e-2 * rng.uniform(-1, 1, u.shape)) + 1e-3 * rng.uniform(-1, 1, u.shape)
+    dt, ch = oracle.dt_ch(oc, u)
+    scale = np.abs(u).mean(axis=(1, 2), keepdims=True) + 1e-3
+    for _ in range(3):
+        v = rng.normal(size=u.shape) * scale
+        lam = rng.normal(size=u.shape)
+        _, Jv = oracle.jvp(oc, u, v, dt, ch)
+        mu = gpu_adjoint(st, u, dt, lam)
+        a, b = float(np.sum(lam * Jv)), float(np.sum(mu * v))
+        assert abs(a - b) <= 1e-11 * float(np.sum(np.abs(lam * Jv)))
