@@ -201,6 +201,35 @@ def variant_timing(torch, lwfr, workloads, np, n, N, flags, steps, name):
     }
 
 
+def rotor_run(torch, lwfr, workloads, np, n=256, N=4, tend=0.15, gamma=1.4):
+    """The MHD rotor (eq. rotor.ic) to t = 0.15 with N = 4 on n x n elements, dt from the
+    CFL rule on the device each step, blending with Algorithms 1 and 2."""
+    dev = torch.device("cuda:0")
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), gamma=gamma, blending=2)
+    st = lwfr.Stepper(cfg, dev)
+    ua = torch.tensor(workloads.mhd_rotor(np.array(st.xi), n, gamma), dtype=torch.float64, device=dev)
+    ub = torch.empty_like(ua)
+    hist = torch.zeros((20000, 2), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t, k = 0.0, 0
+    while t < tend and k < hist.shape[0]:
+        # dt read back every 64 steps only: the device computes each step's dt
+        st.step(ua, ub, 0.0, hist[k])
+        ua, ub = ub, ua
+        k += 1
+        if k % 64 == 0:
+            t = float(hist[:k, 0].sum())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t = float(hist[:k, 0].sum())
+    status, flags = st.query()
+    dofs = n * n * (N + 1) ** 2
+    return {"workload": f"MHD rotor (eq. rotor.ic, gamma {gamma}) {n}x{n}, N={N}, to t >= {tend}",
+            "steps": k, "t_end": t, "ms_per_step": wall / k * 1e3, "value": dofs * k / wall,
+            "unit": "DOF-updates/s", "step_status": int(status), "flags_or": int(flags)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -316,6 +345,7 @@ def main():
         out["adjoint_over_forward"] = adjoint_over_forward(torch, lwfr, workloads, np)
     if not args.no_batch:
         out["batched"] = batched(torch, lwfr, workloads, np)
+    out["rotor"] = rotor_run(torch, lwfr, workloads, np)
     out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_GLL, K,
                                    "Gauss-Lobatto-Legendre points with the g_2 correction")
     if args.copy_calibration:

@@ -147,6 +147,25 @@ def mhd_blocky(xi, nx, ny=None, seed=0, nblocks=16, gamma=GAMMA_MHD):
     return _mhd_cons(rho_b[k], z, z, z, p_b[k], B_b[0][k], B_b[1][k], B_b[2][k], z, gamma)
 
 
+def mhd_rotor(xi, n, gamma=1.4):
+    """MHD rotor (paper §5.5, eq. rotor.ic) on [0,1]^2: a dense disc (rho = 10,
+    r <= 0.1) spinning at angular speed 20 inside a medium at rest, linear taper
+    over 0.1 < r <= 0.115, p = 1, B = (5/sqrt(4 pi), 0, 0), psi = 0.  The paper
+    does not state gamma for this test; 1.4 is the value of the cited setup
+    (Balsara & Spicer)."""
+    x, y = coords_2d(xi, n, n)
+    r = np.sqrt((x - 0.5) ** 2 + (y - 0.5) ** 2)
+    r0, r1 = 0.1, 0.115
+    f = np.clip((r1 - r) / (r1 - r0), 0.0, 1.0)
+    inside = r <= r0
+    fr = np.where(inside, 1.0, f)
+    rho = 1.0 + 9.0 * fr
+    v1 = -20.0 * fr * (y - 0.5)
+    v2 = 20.0 * fr * (x - 0.5)
+    z = np.zeros_like(x)
+    return _mhd_cons(rho, v1, v2, z, z + 1.0, z + 5.0 / math.sqrt(4 * math.pi), z, z, z, gamma)
+
+
 def alfven(xi, nx, t=0.0, gamma=GAMMA_MHD):
     """Circularly polarised Alfven wave on [0, sqrt 2]^2 (paper §5.5, exact solution at time t):
     rho = 1, p = 0.1, v_perp = 0.1 sin(2 pi (x_perp + t)), v = (-v_perp sin a, v_perp cos a,
