@@ -43,6 +43,8 @@ class OraCfg(ctypes.Structure):
         ("blending", ctypes.c_int32),
         ("alpha_max", ctypes.c_double), ("alpha_min", ctypes.c_double), ("alpha_force", ctypes.c_double),
         ("gll", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 4),
+        ("ghost", ctypes.c_void_p),
     ]
 
 
@@ -59,10 +61,16 @@ def _p(a, ctype=ctypes.c_double):
     return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
 
 
+BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_DIRICHLET = 0, 1, 2, 3
+
+
 def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81, cs=0.9,
-             cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0, gll=False):
+             cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0, gll=False,
+             bc=(0, 0, 0, 0)):
     """gll: Gauss-Lobatto-Legendre solution points with the g_2 correction (App. B)
-    instead of Gauss-Legendre points with the Radau correction."""
+    instead of Gauss-Legendre points with the Radau correction.
+    bc: boundary kinds of the sides (x lo, x hi, y lo, y hi), BC_* (periodic by
+    default); BC_DIRICHLET data go with each call (`ghost=` of step)."""
     c = OraCfg()
     c.eq, c.N, c.nx, c.ny = eq, N, nx, (ny if DIMS[eq] == 2 else 1)
     c.lo[0], c.lo[1] = lo
@@ -71,6 +79,9 @@ def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gra
     c.cfl = cfl_number(N, gll) if cfl is None else cfl
     c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
     c.gll = 1 if gll else 0
+    for i in range(4):
+        c.bc[i] = bc[i]
+    c.ghost = None
     return c
 
 
@@ -141,10 +152,13 @@ def alpha(c, u):
     return araw, al, tie
 
 
-def step(c, u, dt=0.0, ch=-1.0, alpha_in=None):
+def step(c, u, dt=0.0, ch=-1.0, alpha_in=None, ghost=None):
     """One step.  dt > 0 is used as given, otherwise eq. time.step.2d; ch >= 0 overrides c_h;
-    alpha_in replaces the indicator's blending coefficients."""
+    alpha_in replaces the indicator's blending coefficients; ghost holds the data of
+    BC_DIRICHLET sides (layout of Config::ghost in oracle/scheme.hpp)."""
     u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    gbuf = None if ghost is None else np.ascontiguousarray(ghost, dtype=np.float64)
+    c.ghost = None if gbuf is None else gbuf.ctypes.data
     E = c.nx * c.ny
     d = DIMS[c.eq]
     out = {
@@ -160,9 +174,21 @@ def step(c, u, dt=0.0, ch=-1.0, alpha_in=None):
     rc = lib().ora_step(ctypes.byref(c), _p(u), _p(out["u"]), ctypes.c_double(dt), ctypes.c_double(ch), _p(ain),
                         _p(out["dt_ch"]), _p(out["alpha"]), _p(out["flags"], ctypes.c_uint32),
                         _p(out["tie"], ctypes.c_uint8), _p(out["theta_face"]), _p(out["theta_elem"]))
-    assert rc == 0
+    c.ghost = None
+    assert rc == 0, rc
     out["dt"], out["ch"] = float(out["dt_ch"][0]), float(out["dt_ch"][1])
     return out
+
+
+def ghost_size(c):
+    """Doubles of the BC_DIRICHLET data of configuration c: for each side b = 2 d + s
+    (x lo, x hi[, y lo, y hi]) a block [quantity 3][variable M][face point along the side]."""
+    M = NVARS[c.eq]
+    tot = 0
+    for d in range(DIMS[c.eq]):
+        lines = c.ny if d == 0 else c.nx
+        tot += 2 * 3 * M * lines * nfp(c)
+    return tot
 
 
 def residual(c, u, dt, mode, ch=-1.0):

@@ -17,6 +17,8 @@ struct ora_cfg {
   int32_t blending;
   double alpha_max, alpha_min, alpha_force;
   int32_t gll;
+  int32_t bc[4];        // sides (x lo, x hi, y lo, y hi): 0 periodic, 1 outflow, 2 wall, 3 Dirichlet
+  const double* ghost;  // Dirichlet data (see Config::ghost)
 };
 
 static Config to_cfg(const ora_cfg* c) {
@@ -27,15 +29,26 @@ static Config to_cfg(const ora_cfg* c) {
   k.blending = c->blending; k.alpha_max = c->alpha_max; k.alpha_min = c->alpha_min;
   k.alpha_force = c->alpha_force;
   k.gll = c->gll;
+  for (int i = 0; i < 4; ++i) k.bc[i / 2][i % 2] = c->bc[i];
+  k.ghost = c->ghost;
   return k;
 }
 
-// Calls fn(scheme) with the scheme of the configured equation system.
+// Calls fn(scheme) with the scheme of the configured equation system.  Calls
+// that take a step (steps_ = true) need the data of every Dirichlet side.
 template <class Fn>
-static int dispatch(const ora_cfg* c, Fn fn) {
+static int dispatch(const ora_cfg* c, Fn fn, bool steps_ = true) {
   Config k = to_cfg(c);
   if (k.N < 0 || k.N > 4 || k.nx < 1 || k.ny < 1) return 1;
   if (k.gll && k.N < 1) return 1;
+  for (int d = 0; d < 2; ++d) {
+    if ((k.bc[d][0] == BC_PERIODIC) != (k.bc[d][1] == BC_PERIODIC)) return 3;
+    for (int sd = 0; sd < 2; ++sd) {
+      if (k.bc[d][sd] < 0 || k.bc[d][sd] > BC_DIRICHLET) return 3;
+      if (k.bc[d][sd] == BC_WALL && k.eq != EQ_SW1D && k.eq != EQ_SW2D) return 3;
+      if (k.bc[d][sd] == BC_DIRICHLET && steps_ && !k.ghost) return 3;
+    }
+  }
   switch (k.eq) {
     case EQ_SW1D: { SW1D ph{k.gravity}; Scheme<SW1D> s(ph, k); fn(s); return 0; }
     case EQ_SW2D: { SW2D ph{k.gravity}; Scheme<SW2D> s(ph, k); fn(s); return 0; }
@@ -117,7 +130,7 @@ int ora_ncols(int eq, int d, int* cols) {
 }
 
 int ora_dt_ch(const ora_cfg* c, const double* u, double* dt_ch) {
-  return dispatch(c, [&](auto& s) { s.dt_ch(u, dt_ch[0], dt_ch[1]); });
+  return dispatch(c, [&](auto& s) { s.dt_ch(u, dt_ch[0], dt_ch[1]); }, false);
 }
 
 int ora_alpha(const ora_cfg* c, const double* u, double* araw, double* alpha, uint8_t* tie) {
@@ -128,7 +141,7 @@ int ora_alpha(const ora_cfg* c, const double* u, double* araw, double* alpha, ui
     std::memcpy(araw, a.data(), a.size() * sizeof(double));
     std::memcpy(alpha, b.data(), b.size() * sizeof(double));
     if (tie) std::memcpy(tie, t.data(), t.size());
-  });
+  }, false);
 }
 
 // One step.  dt_in > 0: use it (c_h is still computed from u unless ch_in >= 0);

@@ -43,7 +43,19 @@ struct Config {
   double alpha_max, alpha_min;
   double alpha_force;  // >= 0: every alpha_e is set to this value (tests, residual modes)
   int gll = 0;         // 1: Gauss-Lobatto-Legendre solution points with g_2 correction (App. B)
+  // boundary condition of side (d, s): BC_PERIODIC, BC_OUTFLOW (the ghost copies
+  // the inside face), BC_WALL (mirror with the normal momentum reversed; shallow
+  // water only), BC_DIRICHLET (ghost face data given in `ghost`).  A direction is
+  // periodic on both sides or on neither.
+  int bc[2][2] = {{0, 0}, {0, 0}};
+  // BC_DIRICHLET data: for boundary b = 2 d + s, block b of 3*M*NB_d values,
+  // [quantity][v][j] with quantity 0 = u^n at the face (also the outside subcell
+  // state), 1 = U (time average), 2 = F_d (time-averaged d-flux), j = position
+  // along the boundary (line index * nfp + q); NB_d = lines * nfp.
+  const double* ghost = nullptr;
 };
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_WALL = 2, BC_DIRICHLET = 3 };
 
 enum : uint32_t {
   FLAG_ALG2 = 1u,          // Algorithm 2 limited the element (theta < 1)
@@ -91,6 +103,16 @@ struct Scheme {
     else ey = side ? (ey + 1) % ny : (ey + ny - 1) % ny;
     return ex + nx * ey;
   }
+  // element e lies on the non-periodic side (d, side) of the domain
+  bool on_boundary(int e, int d, int side) const {
+    if (cfg.bc[d][side] == BC_PERIODIC) return false;
+    int ex = e % nx, ey = e / nx;
+    int c = d == 0 ? ex : ey, n = d == 0 ? nx : ny;
+    return side ? c == n - 1 : c == 0;
+  }
+  // position along boundary (d, side) of face point q of element e
+  int bpos(int e, int d, int q) const { return (d == 0 ? e / nx : e % nx) * nfp + q; }
+  int blines(int d) const { return d == 0 ? ny : nx; }
   // node with position r along direction d on line q
   int node(int d, int q, int r) const { return d == 0 ? r + n1 * q : q + n1 * r; }
   int pos(int d, int p) const { return d == 0 ? p % n1 : p / n1; }
@@ -195,7 +217,8 @@ struct Scheme {
     for (int e = 0; e < E; ++e) {
       double a = araw[e];
       for (int d = 0; d < DIM; ++d)
-        for (int sd = 0; sd < 2; ++sd) a = std::max(a, 0.5 * araw[nbr(e, d, sd)]);
+        for (int sd = 0; sd < 2; ++sd)
+          if (!on_boundary(e, d, sd)) a = std::max(a, 0.5 * araw[nbr(e, d, sd)]);
       alpha[e] = a;
     }
   }
@@ -355,101 +378,189 @@ struct Scheme {
     std::vector<T> Fm, Fp;        // [d][v][e][q]: face d between e and nbr(e,d,1)
     std::vector<double> theta;    // [d][e][q] product of Alg. 1 thetas
     std::vector<uint8_t> guard;   // [d][e][q]
+    // left boundary faces of non-periodic directions: F^+ for the element e on
+    // that side, [d][v][e][q] (entries of other elements unused)
+    std::vector<T> FpLeft;
+    std::vector<double> thetaLeft;
+    std::vector<uint8_t> guardLeft;
   };
+
+  // the data of one side of a face: face values of u^n, F_d and U, and u^n at the
+  // point next to the face (s) and after it (si)
+  template <class T>
+  struct Side {
+    T a[M], F[M], U[M], s[M], si[M];
+  };
+
+  // side data of element e at its right (fs = 1) or left (fs = 0) face
+  template <class T>
+  void elem_side(const T* un, const Local<T>& L, int d, int e, int q, int fs, Side<T>& S) const {
+    for (int v = 0; v < M; ++v) {
+      S.a[v] = L.untr[tidx(d, fs, v, e, q)];
+      S.F[v] = L.Ftr[tidx(d, fs, v, e, q)];
+      S.U[v] = L.Utr[tidx(d, fs, v, e, q)];
+      S.s[v] = un[idx(v, e, node(d, q, fs ? N : 0))];
+      S.si[v] = un[idx(v, e, node(d, q, fs ? (N > 0 ? N - 1 : 0) : (N > 0 ? 1 : 0)))];
+    }
+  }
+
+  // ghost side of boundary (d, side) outside the inside data `in` of element e
+  template <class T>
+  void ghost_side(int d, int side, int e, int q, const Side<T>& in, Side<T>& g) const {
+    const int kind = cfg.bc[d][side];
+    if (kind == BC_OUTFLOW) { g = in; return; }
+    if (kind == BC_WALL) {
+      // mirror image: the normal momentum changes sign; every component of the
+      // d-flux of the mirror state is the negative of the d-flux except the
+      // normal momentum flux (f_d(P u) = -P f_d(u)), and so are its time averages
+      const int mn = 1 + d;
+      for (int v = 0; v < M; ++v) {
+        const double sgn = v == mn ? -1.0 : 1.0;
+        g.a[v] = T(sgn) * in.a[v];
+        g.U[v] = T(sgn) * in.U[v];
+        g.s[v] = T(sgn) * in.s[v];
+        g.si[v] = T(sgn) * in.si[v];
+        g.F[v] = T(-sgn) * in.F[v];
+      }
+      return;
+    }
+    // Dirichlet data
+    size_t off = 0;
+    for (int b = 0; b < 2 * d + side; ++b) off += (size_t)3 * M * blines(b / 2) * nfp;
+    const size_t NB = (size_t)blines(d) * nfp, j = bpos(e, d, q);
+    for (int v = 0; v < M; ++v) {
+      g.a[v] = T(cfg.ghost[off + (0 * M + v) * NB + j]);
+      g.U[v] = T(cfg.ghost[off + (1 * M + v) * NB + j]);
+      g.F[v] = T(cfg.ghost[off + (2 * M + v) * NB + j]);
+      g.s[v] = g.a[v];
+      g.si[v] = g.a[v];
+    }
+  }
 
   template <class T>
   void faces(const T* un, const Local<T>& L, const std::vector<double>& alpha, double dt, double ch,
              Faces<T>& Fc) const {
     Fc.Fm.assign((size_t)DIM * M * E * nfp, T(0.0));
     Fc.Fp.assign(Fc.Fm.size(), T(0.0));
+    Fc.FpLeft.assign(Fc.Fm.size(), T(0.0));
     Fc.theta.assign((size_t)DIM * E * nfp, 1.0);
     Fc.guard.assign((size_t)DIM * E * nfp, 0);
-    T a[M], b[M], FL[M], FR[M], UL[M], UR[M], Fnum[M], Unum[M], Ba[M], Bb[M];
-    T sL[M], sR[M], sLi[M], sRi[M], fLOm[M], fLOp[M], Fm[M], Fp[M], tmp[M], finL[M], finR[M];
-    T uN[M], u0[M], uNlo[M], u0lo[M];
+    Fc.thetaLeft.assign((size_t)DIM * E * nfp, 1.0);
+    Fc.guardLeft.assign((size_t)DIM * E * nfp, 0);
+    Side<T> mi, pl;
+    T Fm[M], Fp[M];
     for (int d = 0; d < DIM; ++d)
       for (int e = 0; e < E; ++e) {
         int en = nbr(e, d, 1);
         for (int q = 0; q < nfp; ++q) {
-          for (int v = 0; v < M; ++v) {
-            a[v] = L.untr[tidx(d, 1, v, e, q)];
-            b[v] = L.untr[tidx(d, 0, v, en, q)];
-            FL[v] = L.Ftr[tidx(d, 1, v, e, q)];
-            FR[v] = L.Ftr[tidx(d, 0, v, en, q)];
-            UL[v] = L.Utr[tidx(d, 1, v, e, q)];
-            UR[v] = L.Utr[tidx(d, 0, v, en, q)];
-          }
-          for (int v = 0; v < M; ++v) {
-            sL[v] = un[idx(v, e, node(d, q, N))];
-            sR[v] = un[idx(v, en, node(d, q, 0))];
-          }
-          // high order time-averaged fluxes (eqs. numflux.cons, good.numflux.non.cons);
-          // lambda from the face values of u^n (eq. rusanov.wave.speed); a face value
-          // that is not admissible (an undershoot of the polynomial next to a jump)
-          // gives its wave speed at the adjacent solution point instead.
-          T sa = admissible(a) ? ph.sigma(d, a, ch) : ph.sigma(d, sL, ch);
-          T sb = admissible(b) ? ph.sigma(d, b, ch) : ph.sigma(d, sR, ch);
-          T lam = tmax(sa, sb);
-          for (int v = 0; v < M; ++v) {
-            Fnum[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * lam * (UR[v] - UL[v]);
-            Unum[v] = T(0.5) * (UL[v] + UR[v]);
-          }
-          ph.ncprod(d, a, Unum, Ba);
-          ph.ncprod(d, b, Unum, Bb);
-          // lower order flux at the face from the neighbouring subcell values
-          lof(d, sL, sR, ch, fLOm, fLOp);
-          // blend with alpha_{e+1/2} = (alpha_e + alpha_{e+1})/2 (eq. Fblend)
-          double af = 0.5 * (alpha[e] + alpha[en]);
-          for (int v = 0; v < M; ++v) {
-            Fm[v] = T(1.0 - af) * (Fnum[v] + Ba[v]) + T(af) * fLOm[v];
-            Fp[v] = T(1.0 - af) * (Fnum[v] + Bb[v]) + T(af) * fLOp[v];
-          }
-          // Algorithm 1: limit F^± so that the neighbouring subcell updates stay
-          // admissible; in DIM dimensions the candidate uses DIM*dt (the subcell
-          // update is the mean of DIM one-directional updates with DIM*dt).
           size_t fi = ((size_t)d * E + e) * nfp + q;
-          if (cfg.blending == 2 && N >= 1) {
+          if (!on_boundary(e, d, 1)) {
+            // interior (or periodic) face between e and en
+            elem_side(un, L, d, e, q, 1, mi);
+            elem_side(un, L, d, en, q, 0, pl);
+            double th = 1.0;
+            uint8_t gd = 0;
+            face(d, mi, pl, 0.5 * (alpha[e] + alpha[en]), true, true, dt, ch, Fm, Fp, th, gd);
             for (int v = 0; v < M; ++v) {
-              sLi[v] = un[idx(v, e, node(d, q, N - 1))];
-              sRi[v] = un[idx(v, en, node(d, q, 1))];
+              Fc.Fm[fidx(d, v, e, q)] = Fm[v];
+              Fc.Fp[fidx(d, v, e, q)] = Fp[v];
             }
-            lof(d, sLi, sL, ch, tmp, finL);  // f^{e,+}_{N-1/2}
-            lof(d, sR, sRi, ch, finR, tmp);  // f^{e+1,-}_{1/2}
-            T cN = T(DIM * dt / (re.w[N] * dx[d])), c0 = T(DIM * dt / (re.w[0] * dx[d]));
-            auto cand = [&]() {
-              for (int v = 0; v < M; ++v) {
-                uN[v] = sL[v] - cN * (Fm[v] - finL[v]);
-                u0[v] = sR[v] - c0 * (finR[v] - Fp[v]);
-              }
-            };
-            for (int v = 0; v < M; ++v) {
-              uNlo[v] = sL[v] - cN * (fLOm[v] - finL[v]);
-              u0lo[v] = sR[v] - c0 * (finR[v] - fLOp[v]);
-            }
-            cand();
-            double Theta = 1.0;
-            bool guard = false;
-            for (int k = 0; k < K; ++k) {
-              double PN = val(ph.constraint(k, uNlo)), P0 = val(ph.constraint(k, u0lo));
-              double th0 = theta_concave(0.1 * P0, P0, val(ph.constraint(k, u0)), guard);
-              double thN = theta_concave(0.1 * PN, PN, val(ph.constraint(k, uN)), guard);
-              double th = std::min(th0, thN);
-              for (int v = 0; v < M; ++v) {
-                Fm[v] = T(th) * Fm[v] + T(1.0 - th) * fLOm[v];
-                Fp[v] = T(th) * Fp[v] + T(1.0 - th) * fLOp[v];
-              }
-              cand();
-              Theta *= th;
-            }
-            Fc.theta[fi] = Theta;
-            Fc.guard[fi] = guard ? 1 : 0;
+            Fc.theta[fi] = th;
+            Fc.guard[fi] = gd;
+            continue;
           }
-          for (int v = 0; v < M; ++v) {
-            Fc.Fm[fidx(d, v, e, q)] = Fm[v];
-            Fc.Fp[fidx(d, v, e, q)] = Fp[v];
+          // right boundary face of e: ghost outside; the ghost carries alpha_e
+          {
+            elem_side(un, L, d, e, q, 1, mi);
+            ghost_side(d, 1, e, q, mi, pl);
+            double th = 1.0;
+            uint8_t gd = 0;
+            face(d, mi, pl, alpha[e], true, false, dt, ch, Fm, Fp, th, gd);
+            for (int v = 0; v < M; ++v) Fc.Fm[fidx(d, v, e, q)] = Fm[v];
+            Fc.theta[fi] = th;
+            Fc.guard[fi] = gd;
+          }
+          // left boundary face of the element on the opposite side of the line
+          {
+            const int el = en;  // nbr wraps to the first element of the line
+            elem_side(un, L, d, el, q, 0, pl);
+            ghost_side(d, 0, el, q, pl, mi);
+            double th = 1.0;
+            uint8_t gd = 0;
+            face(d, mi, pl, alpha[el], false, true, dt, ch, Fm, Fp, th, gd);
+            const size_t fl = ((size_t)d * E + el) * nfp + q;
+            for (int v = 0; v < M; ++v) Fc.FpLeft[fidx(d, v, el, q)] = Fp[v];
+            Fc.thetaLeft[fl] = th;
+            Fc.guardLeft[fl] = gd;
           }
         }
       }
+  }
+
+  // One face in direction d from its minus side mi and plus side pl: the
+  // blended fluxes F^- (for the minus element) and F^+ (for the plus element).
+  // Algorithm 1 limits with the candidates of the sides marked `limit_*` (a
+  // ghost side has no subcell of the mesh to keep admissible).
+  template <class T>
+  void face(int d, const Side<T>& mi, const Side<T>& pl, double af, bool limit_minus, bool limit_plus, double dt,
+            double ch, T* Fm, T* Fp, double& Theta, uint8_t& guard_out) const {
+    T Fnum[M], Unum[M], Ba[M], Bb[M], fLOm[M], fLOp[M], tmp[M], finL[M], finR[M];
+    T uN[M], u0[M], uNlo[M], u0lo[M];
+    // high order time-averaged fluxes (eqs. numflux.cons, good.numflux.non.cons);
+    // lambda from the face values of u^n (eq. rusanov.wave.speed); a face value
+    // that is not admissible (an undershoot of the polynomial next to a jump)
+    // gives its wave speed at the adjacent solution point instead.
+    T sa = admissible(mi.a) ? ph.sigma(d, mi.a, ch) : ph.sigma(d, mi.s, ch);
+    T sb = admissible(pl.a) ? ph.sigma(d, pl.a, ch) : ph.sigma(d, pl.s, ch);
+    T lam = tmax(sa, sb);
+    for (int v = 0; v < M; ++v) {
+      Fnum[v] = T(0.5) * (mi.F[v] + pl.F[v]) - T(0.5) * lam * (pl.U[v] - mi.U[v]);
+      Unum[v] = T(0.5) * (mi.U[v] + pl.U[v]);
+    }
+    ph.ncprod(d, mi.a, Unum, Ba);
+    ph.ncprod(d, pl.a, Unum, Bb);
+    // lower order flux at the face from the neighbouring subcell values
+    lof(d, mi.s, pl.s, ch, fLOm, fLOp);
+    // blend with alpha_{e+1/2} (eq. Fblend)
+    for (int v = 0; v < M; ++v) {
+      Fm[v] = T(1.0 - af) * (Fnum[v] + Ba[v]) + T(af) * fLOm[v];
+      Fp[v] = T(1.0 - af) * (Fnum[v] + Bb[v]) + T(af) * fLOp[v];
+    }
+    Theta = 1.0;
+    guard_out = 0;
+    // Algorithm 1: limit F^± so that the neighbouring subcell updates stay
+    // admissible; in DIM dimensions the candidate uses DIM*dt (the subcell
+    // update is the mean of DIM one-directional updates with DIM*dt).
+    if (cfg.blending == 2 && N >= 1) {
+      lof(d, mi.si, mi.s, ch, tmp, finL);  // f^{e,+}_{N-1/2}
+      lof(d, pl.s, pl.si, ch, finR, tmp);  // f^{e+1,-}_{1/2}
+      T cN = T(DIM * dt / (re.w[N] * dx[d])), c0 = T(DIM * dt / (re.w[0] * dx[d]));
+      auto cand = [&]() {
+        for (int v = 0; v < M; ++v) {
+          uN[v] = mi.s[v] - cN * (Fm[v] - finL[v]);
+          u0[v] = pl.s[v] - c0 * (finR[v] - Fp[v]);
+        }
+      };
+      for (int v = 0; v < M; ++v) {
+        uNlo[v] = mi.s[v] - cN * (fLOm[v] - finL[v]);
+        u0lo[v] = pl.s[v] - c0 * (finR[v] - fLOp[v]);
+      }
+      cand();
+      bool guard = false;
+      for (int k = 0; k < K; ++k) {
+        double PN = val(ph.constraint(k, uNlo)), P0 = val(ph.constraint(k, u0lo));
+        double th0 = limit_plus ? theta_concave(0.1 * P0, P0, val(ph.constraint(k, u0)), guard) : 1.0;
+        double thN = limit_minus ? theta_concave(0.1 * PN, PN, val(ph.constraint(k, uN)), guard) : 1.0;
+        double th = std::min(th0, thN);
+        for (int v = 0; v < M; ++v) {
+          Fm[v] = T(th) * Fm[v] + T(1.0 - th) * fLOm[v];
+          Fp[v] = T(th) * Fp[v] + T(1.0 - th) * fLOp[v];
+        }
+        cand();
+        Theta *= th;
+      }
+      guard_out = guard ? 1 : 0;
+    }
   }
 
   // ------------------------------------------------ 5. element update -----
@@ -464,8 +575,11 @@ struct Scheme {
       for (int d = 0; d < DIM; ++d)
         for (int q = 0; q < nfp; ++q) {
           size_t iu = ((size_t)d * E + e) * nfp + q, il = ((size_t)d * E + nbr(e, d, 0)) * nfp + q;
-          if (Fc.theta[iu] < 1.0 || Fc.theta[il] < 1.0) fl |= FLAG_ALG1;
-          if (Fc.guard[iu] || Fc.guard[il]) fl |= FLAG_ALG1_GUARD;
+          const bool lb = on_boundary(e, d, 0);
+          const double thl = lb ? Fc.thetaLeft[iu] : Fc.theta[il];
+          const uint8_t gl = lb ? Fc.guardLeft[iu] : Fc.guard[il];
+          if (Fc.theta[iu] < 1.0 || thl < 1.0) fl |= FLAG_ALG1;
+          if (Fc.guard[iu] || gl) fl |= FLAG_ALG1_GUARD;
         }
       // high order update (eq. crkfr.non.cons.final), corrections along each line
       for (int p = 0; p < P; ++p)
@@ -477,8 +591,9 @@ struct Scheme {
             for (int r = 0; r < n1; ++r)
               dF = dF + T(re.D[i * n1 + r]) * L.F[(size_t)d * M * E * P + idx(v, e, node(d, q, r))];
             int el = nbr(e, d, 0);
+            const T Fleft = on_boundary(e, d, 0) ? Fc.FpLeft[fidx(d, v, e, q)] : Fc.Fp[fidx(d, v, el, q)];
             T cR = Fc.Fm[fidx(d, v, e, q)] - L.Ftr[tidx(d, 1, v, e, q)] - L.Fnc[tidx(d, 1, v, e, q)];
-            T cL = Fc.Fp[fidx(d, v, el, q)] - L.Ftr[tidx(d, 0, v, e, q)] - L.Fnc[tidx(d, 0, v, e, q)];
+            T cL = Fleft - L.Ftr[tidx(d, 0, v, e, q)] - L.Fnc[tidx(d, 0, v, e, q)];
             R = R + (dF + cR * T(re.gRp[i]) + cL * T(re.gLp[i])) / T(dx[d]);
           }
           uH[(size_t)v * P + p] = un[idx(v, e, p)] - T(dt) * R;
@@ -505,6 +620,8 @@ struct Scheme {
               for (int v = 0; v < M; ++v) { x0[v] = un[idx(v, e, node(d, q, i - 1))]; x1[v] = un[idx(v, e, p)]; }
               lof(d, x0, x1, ch, tmp, fp);
               for (int v = 0; v < M; ++v) left[v] = fp[v];
+            } else if (on_boundary(e, d, 0)) {
+              for (int v = 0; v < M; ++v) left[v] = Fc.FpLeft[fidx(d, v, e, q)];
             } else {
               for (int v = 0; v < M; ++v) left[v] = Fc.Fp[fidx(d, v, el, q)];
             }
