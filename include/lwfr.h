@@ -6,8 +6,9 @@
  *
  * Problem (paper §3 eq. flux.and.non.cons, 2-D form in §5 above eq.
  * time.step.2d):   u_t + sum_d [ f_d(u)_{x_d} + B_d(u) u_{x_d} ] = 0
- * on a uniform periodic Cartesian mesh of tensor-product elements with the
- * N+1 Gauss-Legendre solution points per direction (§2 eq. soln.points).
+ * on a uniform Cartesian mesh of tensor-product elements with the N+1
+ * Gauss-Legendre solution points per direction (§2 eq. soln.points),
+ * periodic or with the side kinds of lwfr_config.bc.
  *
  * Conventions shared by every call
  *  - All floating point data are IEEE FP64.
@@ -36,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LWFR_ABI_VERSION 1u
+#define LWFR_ABI_VERSION 2u
 
 typedef struct lwfr_ctx lwfr_ctx;
 
@@ -65,6 +66,21 @@ typedef enum {
   LWFR_BLEND_ADMISSIBLE = 2  /* blend + Algorithm 1 (face fluxes) + Algorithm 2 (element blend) */
 } lwfr_blending;
 
+/* Kinds of the sides of the domain (lwfr_config.bc).  The paper leaves the
+ * boundary conditions to the problem (§2 after eq. con.law.source) and its
+ * tests use periodic sides, reflective walls, inflow and outflow boundaries
+ * (§5.2, shock diffraction).  A non-periodic side takes a ghost state at each
+ * boundary face point and the face flux of the interior faces from it; the
+ * face blends with the inside element's alpha_e, Algorithm 1 keeps only the
+ * inside subcell admissible, and the smoothing of alpha_e skips the missing
+ * neighbour. */
+typedef enum {
+  LWFR_BC_PERIODIC = 0,   /* both sides of the direction; the default */
+  LWFR_BC_OUTFLOW = 1,    /* ghost = the inside face data */
+  LWFR_BC_WALL = 2,       /* mirror image: normal momentum reversed (shallow water only) */
+  LWFR_BC_DIRICHLET = 3   /* ghost face data given by lwfr_set_boundary_data */
+} lwfr_boundary;
+
 /* Per-element flag bits written to d_flags. */
 #define LWFR_FLAG_ALG2 1u          /* Algorithm 2 limited the element */
 #define LWFR_FLAG_LOW_INADM 2u     /* the lower order update is not admissible in the element */
@@ -77,7 +93,7 @@ typedef struct {
   int32_t equation;      /* lwfr_equation */
   int32_t degree;        /* N, 1..4 */
   int32_t nelem[2];      /* elements per direction; nelem[1] ignored in 1-D */
-  double lo[2], hi[2];   /* domain box; periodic in every direction */
+  double lo[2], hi[2];   /* domain box */
   double gamma;          /* GLM-MHD ratio of specific heats (5/3) */
   double gravity;        /* shallow water g (9.81) */
   double cfl_safety;     /* C_s of eq. time.step.2d (the paper's default 0.9) */
@@ -87,6 +103,8 @@ typedef struct {
   double alpha_min;      /* indicator clip threshold (1e-3) */
   double alpha_force;    /* >= 0: every alpha_e is this value; < 0: smoothness indicator */
   uint32_t flags;        /* LWFR_CFG_* bits */
+  int32_t bc[4];         /* lwfr_boundary of the sides x lo, x hi, y lo, y hi (y ignored in
+                            1-D); a direction is periodic on both sides or on neither */
 } lwfr_config;
 
 /* lwfr_config.flags: reserve the workspace of lwfr_adjoint_step */
@@ -101,7 +119,9 @@ typedef struct {
 /* Validates cfg and builds the reference element, tableau and launch shapes on
  * the host.  No device work.  *out receives a context owned by the caller
  * until lwfr_destroy.  Errors: LWFR_E_INVALID_ARG (bad value, null pointer,
- * ABI mismatch), LWFR_E_UNSUPPORTED (degree outside 1..4). */
+ * ABI mismatch, a direction periodic on one side only, a wall for a system
+ * other than shallow water), LWFR_E_UNSUPPORTED (degree outside 1..4;
+ * LWFR_CFG_ADJOINT with a non-periodic side). */
 lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out);
 
 /* Device workspace bytes the context needs (traces, face fluxes, indicator,
@@ -120,6 +140,22 @@ lwfr_status lwfr_cfl_number(int32_t degree, double* cfl);
  * (LWFR_CFG_GLL). */
 lwfr_status lwfr_cfl_number_for(int32_t degree, uint32_t cfg_flags, double* cfl);
 
+/* Doubles of the Dirichlet data of the context: for each side b = 2 d + s
+ * (x lo, x hi[, y lo, y hi]; every side has its block, used or not) a block
+ * [quantity 3][variable M][position along the side], quantity 0 = u^n at the
+ * boundary face point (also the outside subcell state of the lower order
+ * flux), 1 = U (the time average of the solution over the step), 2 = F_d (the
+ * time-averaged flux normal to the side); positions: line index (the other
+ * direction's element index) * nfp + q, nfp = N+1 in 2-D, 1 in 1-D. */
+lwfr_status lwfr_boundary_data_size(const lwfr_ctx* ctx, size_t* ndouble);
+
+/* Device pointer to the Dirichlet data (lwfr_boundary_data_size doubles) read
+ * by every following step until replaced; the caller keeps it valid and
+ * fills it for each step before enqueuing it (U and F_d depend on dt, so steps
+ * of a context with a Dirichlet side need dt > 0).  Errors:
+ * LWFR_E_INVALID_ARG (null), LWFR_E_STATE (the context has no Dirichlet side). */
+lwfr_status lwfr_set_boundary_data(lwfr_ctx* ctx, const double* d_ghost);
+
 /* Attaches caller-owned device workspace and a HIP stream (hipStream_t passed as
  * void*; NULL = default stream).  The workspace must stay valid until the next
  * bind or lwfr_destroy.  Errors: LWFR_E_WORKSPACE. */
@@ -133,7 +169,9 @@ lwfr_status lwfr_bind(lwfr_ctx* ctx, void* d_workspace, size_t bytes, void* stre
  *   d_dt_ch  nullable; receives {dt, c_h} (c_h = GLM cleaning speed, 0 otherwise)
  *   d_alpha  nullable; receives the blending coefficient alpha_e of each element
  *   d_flags  nullable; receives LWFR_FLAG_* bits of each element
- * Asynchronous on the bound stream; LWFR_E_STATE if not bound. */
+ * Asynchronous on the bound stream; LWFR_E_STATE if not bound, or if the
+ * context has a Dirichlet side without data; LWFR_E_INVALID_ARG for dt <= 0
+ * with a Dirichlet side. */
 lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
                       double* d_alpha, uint32_t* d_flags);
 
@@ -182,11 +220,12 @@ lwfr_status lwfr_query(lwfr_ctx* ctx, uint32_t* flags_or);
  * kernel id (0 per-element means/indicator, 1 time step, 2 GLM speed candidates,
  * 3 GLM speed, 4 element stages, 5 faces, 6 update, 7 residual, 8 update adjoint,
  * 9 face adjoint, 10 stage adjoint; batches: 11 means/indicator, 12 time steps,
- * 13 element stages, 14 faces, 15 update), the summed milliseconds ms[k] and the
+ * 13 element stages, 14 faces, 15 update; 16 boundary faces of non-periodic
+ * sides, single problems and batches), the summed milliseconds ms[k] and the
  * number of timed launches launches[k]; both arrays hold LWFR_TIMING_KERNELS
  * entries.  Events are created on the host by the library and released by
  * lwfr_destroy.  Launches inside a graph capture are not timed. */
-#define LWFR_TIMING_KERNELS 16
+#define LWFR_TIMING_KERNELS 17
 lwfr_status lwfr_timing_begin(lwfr_ctx* ctx, int32_t max_launches);
 lwfr_status lwfr_timing_end(lwfr_ctx* ctx, double* ms, uint32_t* launches);
 
@@ -198,7 +237,9 @@ lwfr_status lwfr_timing_end(lwfr_ctx* ctx, double* ms, uint32_t* launches);
  * The graph holds kernel launches only (no memory set or copy nodes).  Needs a
  * bound non-default stream (else LWFR_E_STATE).  Nothing runs until
  * lwfr_graph_launch, which enqueues the whole sequence on the bound stream;
- * the pointers are baked into the graph and must stay valid. */
+ * the pointers are baked into the graph and must stay valid.
+ * LWFR_E_UNSUPPORTED for a context with a Dirichlet side (dt is not known
+ * when the graph is built). */
 lwfr_status lwfr_graph_capture(lwfr_ctx* ctx, double* d_u_a, double* d_u_b, int32_t nsteps, double* d_dt_ch_hist);
 lwfr_status lwfr_graph_launch(lwfr_ctx* ctx);
 
@@ -226,7 +267,8 @@ enum {
 
 /* cfgs[0..count) as for lwfr_init (same equation for all, no
  * LWFR_CFG_ADJOINT).  Errors: those of lwfr_init (message names the problem),
- * LWFR_E_UNSUPPORTED for another equation system. */
+ * LWFR_E_UNSUPPORTED for another equation system or a Dirichlet side (the
+ * per-problem time steps are computed on the device). */
 lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch** out);
 lwfr_status lwfr_batch_workspace_bytes(const lwfr_batch* batch, size_t* bytes);
 lwfr_status lwfr_batch_state_offsets(const lwfr_batch* batch, int64_t* offsets);

@@ -6,6 +6,7 @@
 //   k_ch       GLM cleaning speed candidates per element, k_ch_fin the minimum
 //   k_stages   element-local stages, time averages F, U, B^loc, volume residual and face traces
 //   k_faces    interface fluxes, blend of eq. Fblend and Algorithm 1, one thread per face point
+//   k_bfaces   the two half faces of each boundary face point of a non-periodic direction
 //   k_update   correction update, subcell FV update, blend and Algorithm 2
 //   k_residual R = (u^n - u^{n+1})/dt
 //
@@ -65,6 +66,11 @@ struct KParams {
   uint32_t* guard_face;       // [d][E*nfp]
   uint32_t* flag_or;          // [1] OR of every element flag since the last query
   double* theta_elem;         // [E] product of Algorithm 2 thetas
+  // boundaries: kind of side (d, s), 0 periodic, 1 outflow, 2 wall, 3 Dirichlet
+  int bc[2][2];
+  const double* ghost;        // Dirichlet face data, per side 2d+s: [3][M][lines_d*nfp]
+  double* theta_left;         // [ny*nfp + nx*nfp] Algorithm 1 theta of the left boundary half faces
+  uint32_t* guard_left;
 };
 
 __device__ inline int nbr_elem(const KParams& kp, int e, int d, int side) {
@@ -72,6 +78,18 @@ __device__ inline int nbr_elem(const KParams& kp, int e, int d, int side) {
   if (d == 0) ex = side ? (ex + 1 == kp.nx ? 0 : ex + 1) : (ex == 0 ? kp.nx - 1 : ex - 1);
   else ey = side ? (ey + 1 == kp.ny ? 0 : ey + 1) : (ey == 0 ? kp.ny - 1 : ey - 1);
   return ex + kp.nx * ey;
+}
+
+// element e lies on the non-periodic side (d, side) of the mesh
+__device__ inline bool on_boundary(const KParams& kp, int e, int d, int side) {
+  if (kp.bc[d][side] == 0) return false;
+  const int c = d == 0 ? e % kp.nx : e / kp.nx, n = d == 0 ? kp.nx : kp.ny;
+  return side ? c == n - 1 : c == 0;
+}
+// neighbour whose raw alpha enters the smoothing of element e: across a
+// non-periodic side there is none, and e itself stands in (no effect on the max)
+__device__ inline int alpha_nbr(const KParams& kp, int e, int d, int side) {
+  return on_boundary(kp, e, d, side) ? e : nbr_elem(kp, e, d, side);
 }
 
 template <int n1>
@@ -483,7 +501,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
 #pragma unroll
-          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[nbr_elem(kp, e, d, sd)]);
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, d, sd)]);
       }
       kp.alpha[e] = a;
       if (d_alpha_out) d_alpha_out[e] = a;
@@ -714,7 +732,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
         for (int dn = 0; dn < 2; ++dn)
 #pragma unroll
-          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[nbr_elem(kp, e, dn, sd)]);
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, dn, sd)]);
       }
       kp.alpha[e] = a;
       if (d_alpha_out) d_alpha_out[e] = a;
@@ -942,6 +960,216 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES_
 }
 
 // ------------------------------------------------------------------------
+// Non-periodic directions.  A boundary face point is two half faces: the right
+// side of the last element of a line (ghost state on the plus side) and the
+// left side of the first element (ghost on the minus side).  k_faces treats
+// the wrap-around face of the line as periodic; k_bfaces runs after it and
+// overwrites that face's slot (the slot of the last element): F^-, D^-, theta
+// and guard from the right half face, F^+ and D^+ from the left half face
+// (k_update reads F^+ of an element's left face at the slot of its left
+// neighbour, which wraps to the last element), and the left half face's theta
+// and guard go to theta_left / guard_left.
+
+// face data of one side: u^n, time-averaged U and F_d at the face, u^n at the
+// solution point next to the face (s) and the one after it (si)
+template <int M>
+struct HalfSide {
+  double a[M], U[M], F[M], s[M], si[M];
+};
+
+// ghost state outside `in` at side (d, side): outflow copies it; a wall is its
+// mirror image (normal momentum reversed; f_d(P u) = -P f_d(u), so every flux
+// component but the normal momentum one changes sign); Dirichlet reads u^n, U
+// and F_d at boundary position j from kp.ghost.
+template <class Ph, int NFP>
+__device__ inline void ghost_state(const KParams& kp, int d, int side, int j, const HalfSide<Ph::M>& in,
+                                   HalfSide<Ph::M>& g) {
+  constexpr int M = Ph::M;
+  const int kind = kp.bc[d][side];
+  if (kind == 3) {
+    const size_t nb0 = (size_t)kp.ny * NFP, nb1 = (size_t)kp.nx * NFP;
+    const size_t nb = d == 0 ? nb0 : nb1;
+    const size_t off = d == 0 ? (size_t)side * 3 * M * nb0 : 2 * 3 * M * nb0 + (size_t)side * 3 * M * nb1;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      g.a[v] = kp.ghost[off + (size_t)v * nb + j];
+      g.U[v] = kp.ghost[off + (size_t)(M + v) * nb + j];
+      g.F[v] = kp.ghost[off + (size_t)(2 * M + v) * nb + j];
+      g.s[v] = g.a[v];
+      g.si[v] = g.a[v];
+    }
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const double sg = (kind == 2 && v == 1 + d) ? -1.0 : 1.0;
+    const double sf = kind == 2 ? -sg : 1.0;
+    g.a[v] = sg * in.a[v];
+    g.U[v] = sg * in.U[v];
+    g.s[v] = sg * in.s[v];
+    g.si[v] = sg * in.si[v];
+    g.F[v] = sf * in.F[v];
+  }
+}
+
+// blended, limited fluxes F^- and F^+ of one face from its two sides; Algorithm
+// 1 keeps only the subcells of the sides marked lim_m / lim_p admissible (a
+// ghost side has no subcell of the mesh)
+template <class Ph, int d>
+__device__ inline void half_face_flux(const KParams& kp, const HalfSide<Ph::M>& mi, const HalfSide<Ph::M>& pl,
+                                      double af, bool lim_m, bool lim_p, double dt, int N, const PhysParams& pp,
+                                      double* Fm, double* Fp, double& Theta, bool& guard) {
+  constexpr int M = Ph::M, DIM = Ph::DIM;
+  const double sa = admissible<Ph>(mi.a, pp) ? Ph::template sigma<d>(mi.a, pp) : Ph::template sigma<d>(mi.s, pp);
+  const double sb = admissible<Ph>(pl.a, pp) ? Ph::template sigma<d>(pl.a, pp) : Ph::template sigma<d>(pl.s, pp);
+  const double lam = sa >= sb ? sa : sb;
+  double Unum[M], t[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    Fm[v] = 0.5 * (mi.F[v] + pl.F[v]) - 0.5 * lam * (pl.U[v] - mi.U[v]);
+    Fp[v] = Fm[v];
+    Unum[v] = 0.5 * (mi.U[v] + pl.U[v]);
+  }
+  Ph::template ncprod<d>(mi.a, Unum, t, pp);
+#pragma unroll
+  for (int v = 0; v < M; ++v) Fm[v] += t[v];
+  Ph::template ncprod<d>(pl.a, Unum, t, pp);
+#pragma unroll
+  for (int v = 0; v < M; ++v) Fp[v] += t[v];
+  double fLOm[M], fLOp[M];
+  low_flux<Ph, d>(mi.s, pl.s, fLOm, fLOp, pp);
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    Fm[v] = (1.0 - af) * Fm[v] + af * fLOm[v];
+    Fp[v] = (1.0 - af) * Fp[v] + af * fLOp[v];
+  }
+  Theta = 1.0;
+  guard = false;
+  if (kp.blending != 2) return;
+  double finL[M], finR[M];
+  low_flux<Ph, d>(mi.si, mi.s, nullptr, finL, pp);
+  low_flux<Ph, d>(pl.s, pl.si, finR, nullptr, pp);
+  const double cN = DIM * dt * kp.inv_wdx[d][N], c0 = DIM * dt * kp.inv_wdx[d][0];
+#pragma unroll
+  for (int k = 0; k < Ph::K; ++k) {
+    double x[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) x[v] = mi.s[v] - cN * (fLOm[v] - finL[v]);
+    const double PN = Ph::constraint(k, x, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) x[v] = pl.s[v] - c0 * (finR[v] - fLOp[v]);
+    const double P0 = Ph::constraint(k, x, pp);
+    double th0 = 1.0, thN = 1.0;
+    if (lim_p) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) x[v] = pl.s[v] - c0 * (finR[v] - Fp[v]);
+      th0 = theta_limit(0.1 * P0, P0, Ph::constraint(k, x, pp), guard);
+    }
+    if (lim_m) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) x[v] = mi.s[v] - cN * (Fm[v] - finL[v]);
+      thN = theta_limit(0.1 * PN, PN, Ph::constraint(k, x, pp), guard);
+    }
+    const double th = th0 <= thN ? th0 : thN;
+    if (th < 1.0) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        Fm[v] = th * Fm[v] + (1.0 - th) * fLOm[v];
+        Fp[v] = th * Fp[v] + (1.0 - th) * fLOp[v];
+      }
+    }
+    Theta *= th;
+  }
+}
+
+// one half face of direction d: half 0 is the right boundary of the last
+// element of line `line`, half 1 the left boundary of its first element
+template <class Ph, int N, int d>
+__device__ inline void bface_point(const KParams& kp, const double* __restrict__ un_g, int half, int line, int q) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  const int eN = d == 0 ? (kp.nx - 1) + kp.nx * line : line + kp.nx * (kp.ny - 1);
+  const int e0 = d == 0 ? kp.nx * line : line;
+  const int j = line * NFP + q;
+  const size_t nf = (size_t)kp.E * NFP;
+  const double dt = kp.scal[0];
+  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const int ei = half == 0 ? eN : e0;  // the inside element
+  const int fs = half == 0 ? 1 : 0;    // its face: right (1) or left (0)
+  HalfSide<M> in, gh;
+  const size_t fi = (size_t)ei * NFP + q;
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const size_t o = ((size_t)(d * 2 + fs) * M + v) * nf + fi;
+    in.a[v] = kp.untr[o];
+    in.U[v] = kp.Utr[o];
+    in.F[v] = kp.Ftr[o];
+    in.s[v] = un_g[((size_t)v * kp.E + ei) * P + node_at<n1>(d, q, fs ? N : 0)];
+    in.si[v] = un_g[((size_t)v * kp.E + ei) * P + node_at<n1>(d, q, fs ? N - 1 : 1)];
+  }
+  ghost_state<Ph, NFP>(kp, d, fs, j, in, gh);
+  const double af = kp.blending == 0 ? 0.0 : kp.alpha[ei];
+  double Fm[M], Fp[M], Theta;
+  bool guard;
+  if (half == 0) half_face_flux<Ph, d>(kp, in, gh, af, true, false, dt, N, pp, Fm, Fp, Theta, guard);
+  else half_face_flux<Ph, d>(kp, gh, in, af, false, true, dt, N, pp, Fm, Fp, Theta, guard);
+  // correction offset of the inside side: F_tr + B(u^n) U at its face
+  double C[M];
+  Ph::template ncprod<d>(in.a, in.U, C, pp);
+  const size_t slot = (size_t)eN * NFP + q;
+  if (half == 0) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const size_t o = ((size_t)d * M + v) * nf + slot;
+      kp.Fm[o] = Fm[v];
+      kp.Dm[o] = Fm[v] - (in.F[v] + C[v]);
+    }
+    kp.theta_face[(size_t)d * nf + slot] = Theta;
+    kp.guard_face[(size_t)d * nf + slot] = guard ? 1u : 0u;
+  } else {
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const size_t o = ((size_t)d * M + v) * nf + slot;
+      kp.Fp[o] = Fp[v];
+      kp.Dp[o] = Fp[v] - (in.F[v] + C[v]);
+    }
+    const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + j;
+    kp.theta_left[bl] = Theta;
+    kp.guard_left[bl] = guard ? 1u : 0u;
+  }
+}
+
+// thread gid enumerates, per non-periodic direction d, the 2 * lines_d * nfp
+// pairs (half, position along the side)
+template <class Ph, int N>
+__device__ inline void bfaces_body(const KParams& kp, const double* __restrict__ un_g, int gid) {
+  constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
+  int d = 0;
+  const int cnt0 = kp.bc[0][0] != 0 ? 2 * kp.ny * NFP : 0;
+  if (gid >= cnt0) {
+    if (DIM == 1 || kp.bc[1][0] == 0) return;
+    gid -= cnt0;
+    d = 1;
+    if (gid >= 2 * kp.nx * NFP) return;
+  }
+  const int lines = d == 0 ? kp.ny : kp.nx;
+  const int half = gid / (lines * NFP);
+  const int j = gid - half * lines * NFP;
+  const int line = j / NFP, q = j - line * NFP;
+  if (d == 0) bface_point<Ph, N, 0>(kp, un_g, half, line, q);
+  else if constexpr (DIM == 2) bface_point<Ph, N, 1>(kp, un_g, half, line, q);
+}
+
+template <class Ph, int N>
+__global__ void __launch_bounds__(64) k_bfaces(const KParams kp, const double* __restrict__ un_g) {
+  bfaces_body<Ph, N>(kp, un_g, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// number of k_bfaces threads of a mesh with side kinds bc
+inline int bface_threads(int DIM, int nx, int ny, int NFP, const int bc[2][2]) {
+  return (bc[0][0] != 0 ? 2 * ny * NFP : 0) + (DIM == 2 && bc[1][0] != 0 ? 2 * nx * NFP : 0);
+}
+
+// ------------------------------------------------------------------------
 // k_update: one thread per solution point.  High order update (eq.
 // crkfr.non.cons.final), subcell FV update (eq. low.order.update), blend
 // (eq. blended.scheme) and Algorithm 2.  io holds R_vol on entry and u^{n+1}
@@ -1150,8 +1378,15 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
           const size_t fu = (size_t)d * nf + (size_t)e * NFP + q;
           const size_t fd = (size_t)d * nf + (size_t)eL[d] * NFP + q;
           // both faces loaded unconditionally (no short-circuit between the loads)
-          const double tu = kp.theta_face[fu], td = kp.theta_face[fd];
-          const uint32_t gu = kp.guard_face[fu], gd = kp.guard_face[fd];
+          const double tu = kp.theta_face[fu];
+          double td = kp.theta_face[fd];
+          const uint32_t gu = kp.guard_face[fu];
+          uint32_t gd = kp.guard_face[fd];
+          if (on_boundary(kp, e, d, 0)) {  // the left face is a boundary half face
+            const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + (size_t)(d == 0 ? e / kp.nx : e % kp.nx) * NFP + q;
+            td = kp.theta_left[bl];
+            gd = kp.guard_left[bl];
+          }
           f |= ((tu < 1.0) | (td < 1.0)) ? 4u : 0u;
           f |= (gu | gd) ? 16u : 0u;
         }

@@ -44,7 +44,10 @@ struct lwfr_ctx {
   KParams kp;
   // workspace carving (byte offsets)
   size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr, off_untr,
-      off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_flag, ws_bytes;
+      off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, ws_bytes;
+  // non-periodic sides: k_bfaces threads (0: periodic mesh); Dirichlet sides
+  int bface_threads = 0;
+  bool dirichlet = false;
   // adjoint workspace (only with LWFR_CFG_ADJOINT)
   bool adjoint = false;
   size_t off_uscr, off_grvol, off_gun, off_gFm, off_gFp, off_gDm, off_gDp, off_gFtr, off_gUtr, off_guntr, off_gsL,
@@ -116,7 +119,7 @@ inline int epb_runtime(int N, int DIM, int M) {
 enum {
   KID_PRE = 0, KID_DT, KID_CH, KID_CHFIN, KID_STAGES, KID_FACES, KID_UPDATE, KID_RESIDUAL,
   KID_ADJ_UPDATE, KID_ADJ_FACES, KID_ADJ_STAGES, KID_B_PRE, KID_B_DT, KID_B_STAGES, KID_B_FACES, KID_B_UPDATE,
-  KID_COUNT
+  KID_BFACES, KID_COUNT
 };
 static_assert(KID_COUNT == LWFR_TIMING_KERNELS, "kernel ids and LWFR_TIMING_KERNELS disagree");
 
@@ -171,6 +174,9 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
               dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
   const int nfp_total = DIM * E * NFP;
   LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
+  if (c->bface_threads > 0)
+    LWFR_LAUNCH(KID_BFACES, "k_bfaces", (k_bfaces<Ph, N>), dim3((c->bface_threads + 63) / 64), dim3(64), 0, s, kp,
+                u_in);
   LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
               d_flags);
   return LWFR_OK;
@@ -255,6 +261,14 @@ KParams with_tape(const lwfr_ctx* c, KParams kp, void* tape) {
   kp.untr = reinterpret_cast<double*>(t + c->tp_untr);
   kp.Utr = reinterpret_cast<double*>(t + c->tp_Utr);
   return kp;
+}
+
+// a step of a context with a Dirichlet side needs its data and a given dt
+lwfr_status dirichlet_ready(const lwfr_ctx* c, double dt) {
+  if (!c->dirichlet) return LWFR_OK;
+  if (!c->kp.ghost) return fail(LWFR_E_STATE, "Dirichlet side without data (lwfr_set_boundary_data)");
+  if (!(dt > 0.0)) return fail(LWFR_E_INVALID_ARG, "a context with a Dirichlet side needs dt > 0");
+  return LWFR_OK;
 }
 
 bool ranges_overlap(const void* a, const void* b, size_t bytes) {
@@ -342,6 +356,8 @@ void carve(lwfr_ctx* c, char* b) {
   kp.Dp = reinterpret_cast<double*>(b + c->off_Dp);
   kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
   kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
+  kp.theta_left = reinterpret_cast<double*>(b + c->off_thl);
+  kp.guard_left = reinterpret_cast<uint32_t*>(b + c->off_gul);
   kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
   if (c->adjoint) {
     AdjParams& ap = c->ap;
@@ -427,6 +443,22 @@ dim3 batch_grid(const BatchLaunch& l, int ntiles) {
   return dim3((unsigned)g);
 }
 
+// k_bfaces of one problem of a batch (its own KParams and workspace)
+template <class Ph>
+lwfr_status launch_bfaces(lwfr_ctx* pc, Timing& tm, hipStream_t s, const double* u) {
+  const dim3 g((pc->bface_threads + 63) / 64), blk(64);
+  TimedLaunch tl(tm, s, KID_BFACES);
+  switch (pc->N) {
+    case 1: hipLaunchKernelGGL((k_bfaces<Ph, 1>), g, blk, 0, s, pc->kp, u); break;
+    case 2: hipLaunchKernelGGL((k_bfaces<Ph, 2>), g, blk, 0, s, pc->kp, u); break;
+    case 3: hipLaunchKernelGGL((k_bfaces<Ph, 3>), g, blk, 0, s, pc->kp, u); break;
+    default: hipLaunchKernelGGL((k_bfaces<Ph, 4>), g, blk, 0, s, pc->kp, u); break;
+  }
+  tl.close();
+  LWFR_CHECK_LAUNCH("k_bfaces");
+  return LWFR_OK;
+}
+
 template <class Ph>
 lwfr_status batch_phase(lwfr_batch* c, int phase, const double* u_in, double* u_out, double* d_dt) {
   const BatchLaunch& l = c->launch[phase];
@@ -450,6 +482,13 @@ lwfr_status batch_phase(lwfr_batch* c, int phase, const double* u_in, double* u_
       break;
     case LWFR_PHASE_FACES:
       LWFR_LAUNCH(KID_B_FACES, "kb_faces", (kb_faces<Ph>), g, dim3(256), 0, s, ba, u_in);
+      // boundary half faces of the problems with non-periodic sides, one launch each
+      for (size_t i = 0; i < c->inst.size(); ++i) {
+        lwfr_ctx* pc = c->inst[i];
+        if (pc->bface_threads == 0) continue;
+        const lwfr_status st = launch_bfaces<Ph>(pc, c->tm, s, u_in + c->uoff[i]);
+        if (st != LWFR_OK) return st;
+      }
       break;
     default:
       if (big) LWFR_LAUNCH(KID_B_UPDATE, "kb_update", (kb_update<Ph, 256>), g, dim3(256), 0, s, ba, u_in, u_out);
@@ -540,6 +579,22 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   if (cfg->equation == LWFR_EQ_GLMMHD2D && !(cfg->gamma > 1.0)) return fail(LWFR_E_INVALID_ARG, "gamma > 1");
   if ((cfg->equation == LWFR_EQ_SW1D || cfg->equation == LWFR_EQ_SW2D) && !(cfg->gravity > 0.0))
     return fail(LWFR_E_INVALID_ARG, "gravity > 0");
+  bool nonperiodic = false, dirichlet = false;
+  for (int d = 0; d < info.DIM; ++d) {
+    const int32_t* k = cfg->bc + 2 * d;
+    for (int sd = 0; sd < 2; ++sd) {
+      if (k[sd] < LWFR_BC_PERIODIC || k[sd] > LWFR_BC_DIRICHLET)
+        return fail(LWFR_E_INVALID_ARG, "bc must be a lwfr_boundary value");
+      if (k[sd] == LWFR_BC_WALL && cfg->equation != LWFR_EQ_SW1D && cfg->equation != LWFR_EQ_SW2D)
+        return fail(LWFR_E_INVALID_ARG, "wall sides are defined for the shallow water systems");
+      nonperiodic = nonperiodic || k[sd] != LWFR_BC_PERIODIC;
+      dirichlet = dirichlet || k[sd] == LWFR_BC_DIRICHLET;
+    }
+    if ((k[0] == LWFR_BC_PERIODIC) != (k[1] == LWFR_BC_PERIODIC))
+      return fail(LWFR_E_INVALID_ARG, "a direction is periodic on both sides or on neither");
+  }
+  if (nonperiodic && (cfg->flags & LWFR_CFG_ADJOINT))
+    return fail(LWFR_E_UNSUPPORTED, "the adjoint step needs a periodic mesh");
 
   lwfr_ctx* c = new lwfr_ctx();
   c->cfg = *cfg;
@@ -578,6 +633,12 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   kp.ind_s = std::log(9999.0);
   kp.cs_cfl = cfg->cfl_safety * c->cfl;
   kp.ch_in = -1.0;
+  for (int d = 0; d < 2; ++d)
+    for (int sd = 0; sd < 2; ++sd) kp.bc[d][sd] = d < info.DIM ? cfg->bc[2 * d + sd] : 0;
+  kp.ghost = nullptr;
+  c->bface_threads = bface_threads(info.DIM, kp.nx, kp.ny, c->NFP, kp.bc);
+  c->dirichlet = dirichlet;
+  (void)nonperiodic;
 
   // workspace carving
   const size_t nfpt = (size_t)c->DIM * c->E * c->NFP;  // face points over all directions
@@ -599,6 +660,11 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_Dp = take(nfpt * c->M * sizeof(double));
   c->off_thf = take(nfpt * sizeof(double));
   c->off_guard = take(nfpt * sizeof(uint32_t));
+  {
+    const size_t nbl = ((size_t)ny + (info.DIM == 2 ? cfg->nelem[0] : 0)) * c->NFP;  // left boundary face points
+    c->off_thl = take(nbl * sizeof(double));
+    c->off_gul = take(nbl * sizeof(uint32_t));
+  }
   c->off_flag = take(sizeof(uint32_t));
   c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
   if (c->adjoint) {
@@ -650,6 +716,20 @@ lwfr_status lwfr_reference_nodes(const lwfr_ctx* c, double* xi, double* w) {
   return LWFR_OK;
 }
 
+lwfr_status lwfr_boundary_data_size(const lwfr_ctx* c, size_t* n) {
+  if (!c || !n) return fail(LWFR_E_INVALID_ARG, "null argument");
+  const size_t nb0 = (size_t)c->kp.ny * c->NFP, nb1 = c->DIM == 2 ? (size_t)c->kp.nx * c->NFP : 0;
+  *n = 2 * 3 * (size_t)c->M * (nb0 + nb1);
+  return LWFR_OK;
+}
+
+lwfr_status lwfr_set_boundary_data(lwfr_ctx* c, const double* d_ghost) {
+  if (!c || !d_ghost) return fail(LWFR_E_INVALID_ARG, "null argument");
+  if (!c->dirichlet) return fail(LWFR_E_STATE, "the context has no Dirichlet side");
+  c->kp.ghost = d_ghost;
+  return LWFR_OK;
+}
+
 lwfr_status lwfr_bind(lwfr_ctx* c, void* d_ws, size_t bytes, void* stream) {
   if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
   if (!d_ws) return fail(LWFR_E_WORKSPACE, "workspace is null");
@@ -673,6 +753,7 @@ lwfr_status lwfr_step(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double
   const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
   if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
   if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
+  if (lwfr_status st = dirichlet_ready(c, dt); st != LWFR_OK) return st;
   KParams kp = c->kp;
   kp.dt_in = dt > 0.0 ? dt : 0.0;
   kp.ch_in = -1.0;
@@ -688,6 +769,7 @@ lwfr_status lwfr_step_fixed(lwfr_ctx* c, const double* d_u_in, double* d_u_out, 
   if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt must be positive and finite");
   if (!(ch >= 0.0) || !std::isfinite(ch)) return fail(LWFR_E_INVALID_ARG, "ch must be >= 0 and finite");
+  if (lwfr_status st = dirichlet_ready(c, dt); st != LWFR_OK) return st;
   KParams kp = c->kp;
   kp.dt_in = dt;
   kp.ch_in = ch;
@@ -702,6 +784,7 @@ lwfr_status lwfr_residual(lwfr_ctx* c, const double* d_u, double dt, int32_t mod
   if (mode < 0 || mode > 2) return fail(LWFR_E_INVALID_ARG, "mode must be 0, 1 or 2");
   const size_t n = (size_t)c->M * c->E * c->P;
   if (ranges_overlap(d_u, d_R, n * sizeof(double))) return fail(LWFR_E_INVALID_ARG, "R aliases u");
+  if (lwfr_status st = dirichlet_ready(c, dt); st != LWFR_OK) return st;
   KParams kp = c->kp;
   kp.dt_in = dt;
   if (mode == 0) { kp.blending = 0; kp.alpha_force = -1.0; }
@@ -728,6 +811,7 @@ lwfr_status lwfr_step_taped(lwfr_ctx* c, const double* d_u_in, double* d_u_out, 
   const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
   if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
   if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
+  if (lwfr_status st = dirichlet_ready(c, dt); st != LWFR_OK) return st;
   KParams kp = with_tape(c, c->kp, d_tape);
   kp.dt_in = dt > 0.0 ? dt : 0.0;
   kp.ch_in = -1.0;
@@ -789,6 +873,7 @@ lwfr_status lwfr_graph_capture(lwfr_ctx* c, double* d_u_a, double* d_u_b, int32_
   if (nsteps < 1 || nsteps > 100000) return fail(LWFR_E_INVALID_ARG, "nsteps must be in 1..100000");
   const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
   if (ranges_overlap(d_u_a, d_u_b, bytes)) return fail(LWFR_E_INVALID_ARG, "u_a and u_b overlap");
+  if (c->dirichlet) return fail(LWFR_E_UNSUPPORTED, "graph capture of a context with a Dirichlet side");
   KParams kp = c->kp;
   kp.dt_in = 0.0;
   kp.ch_in = -1.0;
@@ -848,6 +933,11 @@ lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch**
       lwfr_batch_destroy(b);
       return fail(LWFR_E_UNSUPPORTED, "batches have no adjoint");
     }
+    for (int k = 0; k < 4; ++k)
+      if (cfgs[i].bc[k] == LWFR_BC_DIRICHLET) {
+        lwfr_batch_destroy(b);
+        return fail(LWFR_E_UNSUPPORTED, "batches have no Dirichlet sides");
+      }
     lwfr_ctx* c = nullptr;
     lwfr_status st = lwfr_init(&cfgs[i], &c);
     if (st != LWFR_OK) {

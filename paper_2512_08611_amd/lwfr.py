@@ -11,13 +11,14 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # LWFR_LIBRARY selects another build of the same library (e.g. a tuning variant)
 LIBPATH = os.environ.get("LWFR_LIBRARY", os.path.join(_HERE, "liblwfr.so"))
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
 LWFR_E_INADMISSIBLE, LWFR_E_NONFINITE, LWFR_E_WORKSPACE, LWFR_E_STATE = 4, 5, 6, 7
 LWFR_EQ_SW1D, LWFR_EQ_SW2D, LWFR_EQ_GLMMHD2D, LWFR_EQ_LINADV1D, LWFR_EQ_VARADV1D = 1, 2, 3, 4, 5
 LWFR_CFG_ADJOINT = 1
 LWFR_CFG_GLL = 2
+LWFR_BC_PERIODIC, LWFR_BC_OUTFLOW, LWFR_BC_WALL, LWFR_BC_DIRICHLET = 0, 1, 2, 3
 LWFR_FLAG_ALG2, LWFR_FLAG_LOW_INADM, LWFR_FLAG_ALG1, LWFR_FLAG_NONFINITE, LWFR_FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
 
 NVARS = {1: 3, 2: 4, 3: 9, 4: 1, 5: 2}
@@ -47,6 +48,7 @@ class lwfr_config(ctypes.Structure):
         ("alpha_min", ctypes.c_double),
         ("alpha_force", ctypes.c_double),
         ("flags", ctypes.c_uint32),
+        ("bc", ctypes.c_int32 * 4),
     ]
 
 
@@ -59,6 +61,8 @@ _SIGS = {
     "lwfr_cfl_number": [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
     "lwfr_cfl_number_for": [ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double)],
     "lwfr_bind": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "lwfr_boundary_data_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "lwfr_set_boundary_data": [ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_step_fixed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
@@ -95,7 +99,7 @@ _SIGS = {
 }
 TIMING_KERNELS = ("k_pre", "k_dt", "k_ch", "k_ch_fin", "k_stages", "k_faces", "k_update", "k_residual",
                   "k_adj_update", "k_adj_faces", "k_adj_stages", "kb_pre", "kb_dt", "kb_stages", "kb_faces",
-                  "kb_update")
+                  "kb_update", "k_bfaces")
 LWFR_PHASE_PRE, LWFR_PHASE_STAGES, LWFR_PHASE_FACES, LWFR_PHASE_UPDATE = 0, 1, 2, 3
 
 
@@ -131,7 +135,8 @@ def _ptr(t):
 
 def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81,
                 cfl_safety=0.9, cfl_number=0.0, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0,
-                flags=0):
+                flags=0, bc=(0, 0, 0, 0)):
+    """bc: LWFR_BC_* of the sides (x lo, x hi, y lo, y hi); periodic by default."""
     c = lwfr_config()
     c.abi_version = ABI_VERSION
     c.equation, c.degree = equation, degree
@@ -142,6 +147,8 @@ def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0
     c.gamma, c.gravity, c.cfl_safety, c.cfl_number = gamma, gravity, cfl_safety, cfl_number
     c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
     c.flags = flags
+    for i in range(4):
+        c.bc[i] = bc[i]
     return c
 
 
@@ -185,6 +192,17 @@ def lwfr_bind(ctx, workspace, stream=None):
         stream = torch.cuda.current_stream(workspace.device)
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib().lwfr_bind(ctx, ctypes.c_void_p(workspace.data_ptr()), nbytes, ctypes.c_void_p(stream.cuda_stream)))
+
+
+def lwfr_boundary_data_size(ctx):
+    n = ctypes.c_size_t()
+    _check(lib().lwfr_boundary_data_size(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def lwfr_set_boundary_data(ctx, ghost):
+    """ghost: float64 device tensor of lwfr_boundary_data_size(ctx) doubles, kept alive by the caller."""
+    _check(lib().lwfr_set_boundary_data(ctx, _ptr(ghost)))
 
 
 def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
@@ -280,6 +298,13 @@ class Stepper:
         self.npts = n1 ** self.dim
         self.shape = (self.nvars, self.nelem, self.npts)
         self.xi, self.w = lwfr_reference_nodes(self.ctx, n1)
+
+    def boundary_data_size(self):
+        return lwfr_boundary_data_size(self.ctx)
+
+    def set_boundary_data(self, ghost):
+        self.ghost = ghost  # the library reads it at every step
+        lwfr_set_boundary_data(self.ctx, ghost)
 
     def step(self, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
         lwfr_step(self.ctx, u_in, u_out, dt, dt_ch, alpha, flags)

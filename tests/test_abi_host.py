@@ -131,3 +131,40 @@ def test_batch_host_side():
     assert L.lwfr_batch_init(bad, 2, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
     assert "problem 1" in lwfr.lwfr_last_error()
     assert L.lwfr_batch_init(arr, 0, ctypes.byref(h)) == lwfr.LWFR_E_INVALID_ARG
+
+
+def test_boundary_validation():
+    """Side kinds: accepted combinations, rejected ones, Dirichlet data size and setter."""
+    B = lwfr
+    ok = [(lwfr.LWFR_EQ_SW2D, (B.LWFR_BC_WALL,) * 4), (lwfr.LWFR_EQ_SW1D, (B.LWFR_BC_WALL, B.LWFR_BC_OUTFLOW, 0, 0)),
+          (lwfr.LWFR_EQ_GLMMHD2D, (B.LWFR_BC_OUTFLOW, B.LWFR_BC_OUTFLOW, 0, 0)),
+          (lwfr.LWFR_EQ_GLMMHD2D, (0, 0, B.LWFR_BC_DIRICHLET, B.LWFR_BC_OUTFLOW)),
+          (lwfr.LWFR_EQ_VARADV1D, (B.LWFR_BC_DIRICHLET, B.LWFR_BC_OUTFLOW, 7, 7))]  # y sides ignored in 1-D
+    for eq, bc in ok:
+        ctx = lwfr.lwfr_init(lwfr.make_config(eq, 3, (5, 4), bc=bc))
+        lwfr.lwfr_destroy(ctx)
+    bad = [(lwfr.LWFR_EQ_GLMMHD2D, (B.LWFR_BC_WALL, B.LWFR_BC_WALL, 0, 0), lwfr.LWFR_E_INVALID_ARG),
+           (lwfr.LWFR_EQ_SW2D, (B.LWFR_BC_OUTFLOW, 0, 0, 0), lwfr.LWFR_E_INVALID_ARG),
+           (lwfr.LWFR_EQ_SW2D, (0, 0, 4, 4), lwfr.LWFR_E_INVALID_ARG),
+           (lwfr.LWFR_EQ_SW2D, (0, 0, -1, 1), lwfr.LWFR_E_INVALID_ARG)]
+    for eq, bc, st in bad:
+        with pytest.raises(lwfr.LwfrError) as ei:
+            lwfr.lwfr_init(lwfr.make_config(eq, 3, (5, 4), bc=bc))
+        assert ei.value.status == st, bc
+    with pytest.raises(lwfr.LwfrError) as ei:
+        lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_SW2D, 3, (5, 4), bc=(1, 1, 0, 0), flags=lwfr.LWFR_CFG_ADJOINT))
+    assert ei.value.status == lwfr.LWFR_E_UNSUPPORTED
+    # data size = the oracle's layout; setter only for contexts with a Dirichlet side
+    for eq, nel, N in [(lwfr.LWFR_EQ_GLMMHD2D, (5, 4), 3), (lwfr.LWFR_EQ_VARADV1D, (6, 1), 2)]:
+        ctx = lwfr.lwfr_init(lwfr.make_config(eq, N, nel, bc=(3, 1, 3, 1)))
+        oc = oracle.make_cfg({3: oracle.EQ_MHD2D, 5: oracle.EQ_VARADV1D}[eq], N, *nel)
+        assert lwfr.lwfr_boundary_data_size(ctx) == oracle.ghost_size(oc)
+        assert lwfr.lib().lwfr_set_boundary_data(ctx, ctypes.c_void_p(4096)) == lwfr.LWFR_OK
+        lwfr.lwfr_destroy(ctx)
+    ctx = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_SW2D, 2, (5, 4), bc=(1, 1, 2, 2)))
+    assert lwfr.lib().lwfr_set_boundary_data(ctx, ctypes.c_void_p(4096)) == lwfr.LWFR_E_STATE
+    lwfr.lwfr_destroy(ctx)
+    cfgs = [lwfr.make_config(lwfr.LWFR_EQ_SW2D, 2, (4, 4), bc=(3, 1, 0, 0))]
+    arr = (lwfr.lwfr_config * 1)(*cfgs)
+    h = ctypes.c_void_p()
+    assert lwfr.lib().lwfr_batch_init(arr, 1, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
