@@ -26,10 +26,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-EQ_SW1D, EQ_SW2D, EQ_MHD2D, EQ_LINADV1D, EQ_VARADV1D = 1, 2, 3, 4, 5
-NVARS = {EQ_SW1D: 3, EQ_SW2D: 4, EQ_MHD2D: 9, EQ_LINADV1D: 1, EQ_VARADV1D: 2}
-DIMS = {EQ_SW1D: 1, EQ_SW2D: 2, EQ_MHD2D: 2, EQ_LINADV1D: 1, EQ_VARADV1D: 1}
-NCONSTR = {EQ_SW1D: 1, EQ_SW2D: 1, EQ_MHD2D: 2, EQ_LINADV1D: 0, EQ_VARADV1D: 0}
+EQ_SW1D, EQ_SW2D, EQ_MHD2D, EQ_LINADV1D, EQ_VARADV1D, EQ_JINXIN1D = 1, 2, 3, 4, 5, 6
+NVARS = {EQ_SW1D: 3, EQ_SW2D: 4, EQ_MHD2D: 9, EQ_LINADV1D: 1, EQ_VARADV1D: 2, EQ_JINXIN1D: 2}
+DIMS = {EQ_SW1D: 1, EQ_SW2D: 2, EQ_MHD2D: 2, EQ_LINADV1D: 1, EQ_VARADV1D: 1, EQ_JINXIN1D: 1}
+NCONSTR = {EQ_SW1D: 1, EQ_SW2D: 1, EQ_MHD2D: 2, EQ_LINADV1D: 0, EQ_VARADV1D: 0, EQ_JINXIN1D: 0}
+IMEX_HT112, IMEX_SSP3 = 1, 2
 
 FLAG_ALG2, FLAG_LOW_INADM, FLAG_ALG1, FLAG_NONFINITE, FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
 
@@ -45,6 +46,9 @@ class OraCfg(ctypes.Structure):
         ("gll", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 4),
         ("ghost", ctypes.c_void_p),
+        ("imex", ctypes.c_int32),
+        ("relax_a", ctypes.c_double), ("relax_eps", ctypes.c_double),
+        ("relax_l", ctypes.c_double), ("relax_q", ctypes.c_double),
     ]
 
 
@@ -66,22 +70,28 @@ BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_DIRICHLET = 0, 1, 2, 3
 
 def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81, cs=0.9,
              cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0, gll=False,
-             bc=(0, 0, 0, 0)):
+             bc=(0, 0, 0, 0), imex=0, relax=(3.0, 1e-2, 0.0, 1.0)):
     """gll: Gauss-Lobatto-Legendre solution points with the g_2 correction (App. B)
     instead of Gauss-Legendre points with the Radau correction.
     bc: boundary kinds of the sides (x lo, x hi, y lo, y hi), BC_* (periodic by
-    default); BC_DIRICHLET data go with each call (`ghost=` of step)."""
+    default); BC_DIRICHLET data go with each call (`ghost=` of step).
+    imex: IMEX pair (IMEX_HT112, IMEX_SSP3) in place of the degree's explicit
+    tableau; required by systems with a source.  relax: Jin-Xin (a, eps, l, q),
+    f(u) = l u + q u^2/2 (Burgers by default).
+    cfl=None takes the Fourier limit of the scheme these select."""
     c = OraCfg()
     c.eq, c.N, c.nx, c.ny = eq, N, nx, (ny if DIMS[eq] == 2 else 1)
     c.lo[0], c.lo[1] = lo
     c.hi[0], c.hi[1] = hi
     c.gamma, c.gravity, c.cs = gamma, gravity, cs
-    c.cfl = cfl_number(N, gll) if cfl is None else cfl
+    c.cfl = cfl_number(N, gll, imex) if cfl is None else cfl
     c.blending, c.alpha_max, c.alpha_min, c.alpha_force = blending, alpha_max, alpha_min, alpha_force
     c.gll = 1 if gll else 0
     for i in range(4):
         c.bc[i] = bc[i]
     c.ghost = None
+    c.imex = imex
+    c.relax_a, c.relax_eps, c.relax_l, c.relax_q = relax
     return c
 
 
@@ -114,6 +124,26 @@ def tableau(N):
     assert lib().ora_tableau(N, ctypes.byref(s), _p(A), _p(b)) == 0
     n = s.value
     return A[: n * n].reshape(n, n).copy(), b[:n].copy()
+
+
+def tableau_imex(imex):
+    """(A~, b~, A, b) of IMEX pair imex: explicit and implicit parts."""
+    s = ctypes.c_int(0)
+    A, b, Ai, bi = np.zeros(36), np.zeros(6), np.zeros(36), np.zeros(6)
+    assert lib().ora_tableau_imex(imex, ctypes.byref(s), _p(A), _p(b), _p(Ai), _p(bi)) == 0
+    n = s.value
+    return A[: n * n].reshape(n, n).copy(), b[:n].copy(), Ai[: n * n].reshape(n, n).copy(), bi[:n].copy()
+
+
+def jinxin(what, u, a=3.0, eps=1e-2, c=0.0, l=0.0, q=1.0):
+    """Jin-Xin pointwise parts: what in {'flux', 'source', 'implicit'} ('implicit': the
+    solution x of x - c s(x) = u)."""
+    code = {"flux": 0, "source": 1, "implicit": 2}[what]
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(2)
+    assert lib().ora_jinxin(code, ctypes.c_double(a), ctypes.c_double(eps), ctypes.c_double(l), ctypes.c_double(q),
+                            ctypes.c_double(c), _p(u), _p(out)) == 0
+    return out
 
 
 def physics(eq, what, d, u, w=None, gamma=5.0 / 3.0, gravity=9.81, ch=0.0):

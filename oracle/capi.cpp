@@ -19,6 +19,8 @@ struct ora_cfg {
   int32_t gll;
   int32_t bc[4];        // sides (x lo, x hi, y lo, y hi): 0 periodic, 1 outflow, 2 wall, 3 Dirichlet
   const double* ghost;  // Dirichlet data (see Config::ghost)
+  int32_t imex;         // IMEX pair of a system with a source: 1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)
+  double relax_a, relax_eps, relax_l, relax_q;  // Jin-Xin a, eps and f(u) = l u + q u^2/2
 };
 
 static Config to_cfg(const ora_cfg* c) {
@@ -31,6 +33,11 @@ static Config to_cfg(const ora_cfg* c) {
   k.gll = c->gll;
   for (int i = 0; i < 4; ++i) k.bc[i / 2][i % 2] = c->bc[i];
   k.ghost = c->ghost;
+  k.imex = c->imex;
+  k.relax_a = c->relax_a;
+  k.relax_eps = c->relax_eps;
+  k.relax_l = c->relax_l;
+  k.relax_q = c->relax_q;
   return k;
 }
 
@@ -41,6 +48,8 @@ static int dispatch(const ora_cfg* c, Fn fn, bool steps_ = true) {
   Config k = to_cfg(c);
   if (k.N < 0 || k.N > 4 || k.nx < 1 || k.ny < 1) return 1;
   if (k.gll && k.N < 1) return 1;
+  if (k.imex < 0 || k.imex > 2) return 1;
+  if (k.eq == EQ_JINXIN1D && (k.imex == 0 || !(k.relax_eps > 0.0) || !(k.relax_a > 0.0))) return 1;
   for (int d = 0; d < 2; ++d) {
     if ((k.bc[d][0] == BC_PERIODIC) != (k.bc[d][1] == BC_PERIODIC)) return 3;
     for (int sd = 0; sd < 2; ++sd) {
@@ -55,6 +64,7 @@ static int dispatch(const ora_cfg* c, Fn fn, bool steps_ = true) {
     case EQ_MHD2D: { MHD2D ph{k.gamma}; Scheme<MHD2D> s(ph, k); fn(s); return 0; }
     case EQ_LINADV1D: { LinAdv1D ph; Scheme<LinAdv1D> s(ph, k); fn(s); return 0; }
     case EQ_VARADV1D: { VarAdv1D ph; Scheme<VarAdv1D> s(ph, k); fn(s); return 0; }
+    case EQ_JINXIN1D: { JinXin1D ph{k.relax_a, k.relax_eps, k.relax_l, k.relax_q}; Scheme<JinXin1D> s(ph, k); fn(s); return 0; }
   }
   return 2;
 }
@@ -84,6 +94,31 @@ int ora_tableau(int N, int* s, double* A, double* b) {
   std::memcpy(A, t.A.data(), t.s * t.s * sizeof(double));
   std::memcpy(b, t.b.data(), t.s * sizeof(double));
   return 0;
+}
+
+// IMEX pair imex (1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)): explicit (A, b) and
+// implicit (Ai, bi) parts, s x s row-major (arrays of at least 36 and 6).
+int ora_tableau_imex(int imex, int* s, double* A, double* b, double* Ai, double* bi) {
+  if (imex < 1 || imex > 2) return 1;
+  Tableau t(1, imex);
+  *s = t.s;
+  std::memcpy(A, t.A.data(), t.s * t.s * sizeof(double));
+  std::memcpy(b, t.b.data(), t.s * sizeof(double));
+  std::memcpy(Ai, t.Ai.data(), t.s * t.s * sizeof(double));
+  std::memcpy(bi, t.bi.data(), t.s * sizeof(double));
+  return 0;
+}
+
+// Jin-Xin pointwise parts: what = 0 flux, 1 source s(u), 2 the solution of
+// u - c s(u) = r (r in u).
+int ora_jinxin(int what, double a, double eps, double l, double q, double c, const double* u, double* out) {
+  JinXin1D ph{a, eps, l, q};
+  switch (what) {
+    case 0: ph.flux<double>(0, u, out, 0.0); return 0;
+    case 1: ph.source<double>(u, out); return 0;
+    case 2: ph.implicit<double>(u, c, out); return 0;
+  }
+  return 1;
 }
 
 // Pointwise physics: what = 0 flux f_d(u), 1 B_d(u) w, 2 sigma_d(u) (out[0]),

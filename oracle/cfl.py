@@ -15,6 +15,11 @@ scheme itself.  For u_t + u_x = 0 (f = u, wave speed 1) with nu = dt/dx:
   u_e^{n+1} = u_e - nu [ D T u_e + g_L' (V_R^T T u_{e-1} - V_L^T T u_e) ].
 With u_{e-1} = exp(-i theta) u_e this is u_e^{n+1} = G(theta) u_e; CFL(N) is
 the largest nu with spectral radius rho(G(theta)) <= 1 for all theta.
+
+With an IMEX pair (systems with a source) the flux terms use its explicit
+part (A~, b~), whose order can be below N+1; then T = sum_i b~_i R_i with the
+stage operators R_1 = I, R_i = I + sum_{k<i} a~_ik (-nu D) R_k (the source is
+zero in this linear analysis).
 """
 import functools
 import math
@@ -22,27 +27,44 @@ import math
 import numpy as np
 
 
-def amplification(N, nu, theta, re):
+def time_average_operator(N, nu, D, tableau=None):
+    """T with U = T u: the Taylor weights, or the explicit tableau (A~, b~) if given."""
+    n1 = N + 1
+    if tableau is None:
+        T = np.zeros((n1, n1))
+        Pk = np.eye(n1)
+        for k in range(N + 1):
+            T = T + Pk / math.factorial(k + 1)
+            Pk = Pk @ (-nu * D)
+        return T
+    A, b = tableau
+    R = []
+    for i in range(len(b)):
+        Ri = np.eye(n1)
+        for k in range(i):
+            if A[i, k] != 0.0:
+                Ri = Ri + A[i, k] * (-nu * D) @ R[k]
+        R.append(Ri)
+    return sum(b[i] * R[i] for i in range(len(b)))
+
+
+def amplification(N, nu, theta, re, tableau=None):
     D = re["D"]
     n1 = N + 1
-    T = np.zeros((n1, n1))
-    Pk = np.eye(n1)
-    for k in range(N + 1):
-        T = T + Pk / math.factorial(k + 1)
-        Pk = Pk @ (-nu * D)
+    T = time_average_operator(N, nu, D, tableau)
     gL = re["gLp"].reshape(n1, 1)
     VR = re["VR"].reshape(1, n1)
     VL = re["VL"].reshape(1, n1)
     return np.eye(n1) - nu * (D @ T + gL @ (np.exp(-1j * theta) * VR - VL) @ T)
 
 
-def max_growth(N, nu, re, ntheta=721):
+def max_growth(N, nu, re, ntheta=721, tableau=None):
     thetas = np.linspace(0.0, np.pi, ntheta)[1:]
-    return max(np.max(np.abs(np.linalg.eigvals(amplification(N, nu, t, re)))) for t in thetas)
+    return max(np.max(np.abs(np.linalg.eigvals(amplification(N, nu, t, re, tableau)))) for t in thetas)
 
 
 @functools.lru_cache(maxsize=None)
-def cfl_number(N, gll=False):
+def cfl_number(N, gll=False, imex=0):
     """Largest nu with rho(G) <= 1 + tol for degree N (bisection to 1e-10 in nu);
     gll: Gauss-Lobatto-Legendre points with the g_2 correction.
 
@@ -50,16 +72,21 @@ def cfl_number(N, gll=False):
     undamped modes a weak growth of order (nu theta)^6 (about 5e-6 per step
     just below the limit); the limit is the sharp loss of stability of the
     high-frequency modes, so there a growth below tol = 1e-5 per step counts as
-    stable.
+    stable.  imex: the explicit part of that IMEX pair in place of the degree's
+    tableau (same tolerances).
     """
     tol = 1e-12 if N <= 3 else 1e-5
-    from . import refel
+    from . import refel, tableau_imex
 
     re = refel(N, gll)
+    tab = None
+    if imex:
+        A, b, _, _ = tableau_imex(imex)
+        tab = (A, b)
     lo, hi = 0.0, 1.5
     while hi - lo > 1e-10:
         mid = 0.5 * (lo + hi)
-        if max_growth(N, mid, re) <= 1.0 + tol:
+        if max_growth(N, mid, re, tableau=tab) <= 1.0 + tol:
             lo = mid
         else:
             hi = mid

@@ -10,12 +10,16 @@
 //   indicator(u)       the variable the smoothness indicator looks at
 // and in double only:
 //   speeds(d,u,absv,c) |v_d| and the largest characteristic speed without GLM.
+// Systems with a source term (SRC = true, §2 eq. con.law.source) also provide
+//   source(u,s)        s(u)
+//   implicit(r,c,u)    the solution u of u - c s(u) = r (c >= 0), the pointwise
+//                      implicit stage equation of eq. crkfr.inner.
 #pragma once
 #include "scalar.hpp"
 
 namespace ora {
 
-enum { EQ_SW1D = 1, EQ_SW2D = 2, EQ_MHD2D = 3, EQ_LINADV1D = 4, EQ_VARADV1D = 5 };
+enum { EQ_SW1D = 1, EQ_SW2D = 2, EQ_MHD2D = 3, EQ_LINADV1D = 4, EQ_VARADV1D = 5, EQ_JINXIN1D = 6 };
 
 // ---------------------------------------------------------------------------
 // Shallow water with bathymetry b carried as a state variable, as the paper
@@ -24,6 +28,7 @@ enum { EQ_SW1D = 1, EQ_SW2D = 2, EQ_MHD2D = 3, EQ_LINADV1D = 4, EQ_VARADV1D = 5 
 // (b_t = 0), hence its row of f and B is zero.
 struct SW1D {
   static constexpr int M = 3, DIM = 1, K = 1;
+  static constexpr bool SRC = false;
   // columns of B_d that are not identically zero (B_d(u) w reads only these w_c)
   static constexpr int NCOL = 1;
   static int ncol(int, int) { return 2; }
@@ -49,6 +54,7 @@ struct SW1D {
 
 struct SW2D {
   static constexpr int M = 4, DIM = 2, K = 1;
+  static constexpr bool SRC = false;
   static constexpr int NCOL = 1;
   static int ncol(int, int) { return 3; }
   double g;
@@ -85,6 +91,7 @@ struct SW2D {
 // p = (gamma-1)(E - rho|v|^2/2 - |B|^2/2 - psi^2/2).
 struct MHD2D {
   static constexpr int M = 9, DIM = 2, K = 2;
+  static constexpr bool SRC = false;
   static constexpr int NCOL = 2;
   static int ncol(int d, int i) { return i == 0 ? 5 + d : 8; }
   double gamma;
@@ -158,6 +165,7 @@ struct MHD2D {
 // eq. scalar.cons.law with f = u).
 struct LinAdv1D {
   static constexpr int M = 1, DIM = 1, K = 0;
+  static constexpr bool SRC = false;
   static constexpr int NCOL = 0;
   static int ncol(int, int) { return 0; }
   template <class T> void flux(int, const T* u, T* f, double) const { f[0] = u[0]; }
@@ -172,6 +180,7 @@ struct LinAdv1D {
 // eq. var.coeff.adv.non.cons): u = (v, a), f = 0, B(u) w = (u_2 w_1, 0).
 struct VarAdv1D {
   static constexpr int M = 2, DIM = 1, K = 0;
+  static constexpr bool SRC = false;
   static constexpr int NCOL = 1;
   static int ncol(int, int) { return 0; }
   template <class T> void flux(int, const T*, T* f, double) const { f[0] = T(0.0); f[1] = T(0.0); }
@@ -180,6 +189,36 @@ struct VarAdv1D {
   template <class T> T constraint(int, const T* u) const { return u[0]; }
   template <class T> T indicator(const T* u) const { return u[0]; }
   void speeds(int, const double* u, double& absv, double& c) const { absv = 0.0; c = std::fabs(u[1]); }
+};
+
+// Jin-Xin relaxation system (§5.1 eqs. jinxin1, jinxin2): u = (u, v), flux
+// (v, a^2 u), no non-conservative product, source (0, -(v - f(u))/eps) with
+// f(u) = l u + q u^2/2 (the paper's case is Burgers, l = 0, q = 1; q = 0 gives
+// the linear system with exact Fourier solutions).  Eigenvalues of the flux
+// Jacobian: +-a.  No admissibility constraint; the indicator looks at u.
+struct JinXin1D {
+  static constexpr int M = 2, DIM = 1, K = 0;
+  static constexpr bool SRC = true;
+  static constexpr int NCOL = 0;
+  static int ncol(int, int) { return 0; }
+  double a, eps, l, q;
+  template <class T> T f(const T& u) const { return T(l) * u + T(0.5 * q) * u * u; }
+  template <class T> void flux(int, const T* u, T* fo, double) const { fo[0] = u[1]; fo[1] = T(a * a) * u[0]; }
+  template <class T> void ncprod(int, const T*, const T*, T* o) const { o[0] = T(0.0); o[1] = T(0.0); }
+  template <class T> T sigma(int, const T*, double) const { return T(a); }
+  template <class T> T constraint(int, const T* u) const { return u[0]; }
+  template <class T> T indicator(const T* u) const { return u[0]; }
+  void speeds(int, const double*, double& absv, double& c) const { absv = 0.0; c = a; }
+  template <class T> void source(const T* u, T* s) const {
+    s[0] = T(0.0);
+    s[1] = -(u[1] - f(u[0])) / T(eps);
+  }
+  // u - c s(u) = r: the first component has no source, so u = r_1, and the
+  // second is linear in v: v + (c/eps)(v - f(u)) = r_2
+  template <class T> void implicit(const T* r, double c, T* u) const {
+    u[0] = r[0];
+    u[1] = (r[1] + T(c / eps) * f(r[0])) / T(1.0 + c / eps);
+  }
 };
 
 }  // namespace ora

@@ -43,6 +43,9 @@ struct Config {
   double alpha_max, alpha_min;
   double alpha_force;  // >= 0: every alpha_e is set to this value (tests, residual modes)
   int gll = 0;         // 1: Gauss-Lobatto-Legendre solution points with g_2 correction (App. B)
+  int imex = 0;        // IMEX pair of a system with a source (tableau.hpp): 1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)
+  // Jin-Xin characteristic speed a, relaxation time eps, f(u) = l u + q u^2/2
+  double relax_a = 3.0, relax_eps = 1e-2, relax_l = 0.0, relax_q = 1.0;
   // boundary condition of side (d, s): BC_PERIODIC, BC_OUTFLOW (the ghost copies
   // the inside face), BC_WALL (mirror with the normal momentum reversed; shallow
   // water only), BC_DIRICHLET (ghost face data given in `ghost`).  A direction is
@@ -85,7 +88,7 @@ struct Scheme {
   double dx[2];
 
   Scheme(const Phys& p, const Config& c)
-      : ph(p), cfg(c), re(c.N, c.gll != 0), tb(c.N), N(c.N), n1(c.N + 1) {
+      : ph(p), cfg(c), re(c.N, c.gll != 0), tb(c.N, c.imex), N(c.N), n1(c.N + 1) {
     P = DIM == 1 ? n1 : n1 * n1;
     nfp = DIM == 1 ? 1 : n1;
     nx = c.nx; ny = DIM == 1 ? 1 : c.ny;
@@ -231,6 +234,7 @@ struct Scheme {
     std::vector<T> Bl;   // [v][e][p] B^loc
     std::vector<T> Fnc;  // [d][side][v][e][q]
     std::vector<T> Ftr, Utr, untr;  // traces [d][side][v][e][q]
+    std::vector<T> S;    // [v][e][p] time-averaged source (eq. avg.source; systems with a source)
   };
   size_t tidx(int d, int side, int v, int e, int q) const {
     return ((((size_t)d * 2 + side) * M + v) * E + e) * nfp + q;
@@ -246,7 +250,9 @@ struct Scheme {
     L.Ftr.assign(L.Fnc.size(), T(0.0));
     L.Utr.assign(L.Fnc.size(), T(0.0));
     L.untr.assign(L.Fnc.size(), T(0.0));
+    L.S.assign(Phys::SRC ? (size_t)M * E * P : 0, T(0.0));
     std::vector<T> Lst((size_t)s * M * P), uj((size_t)M * P), f((size_t)DIM * M * P);
+    std::vector<T> Sst(Phys::SRC ? (size_t)s * M * P : 0);
     std::vector<T> a(M), fo(M), w(M), o(M), du(M), nc(M);
     for (int e = 0; e < E; ++e) {
       for (int j = 0; j < s; ++j) {
@@ -263,6 +269,33 @@ struct Scheme {
               }
             uj[(size_t)v * P + p] = any ? un[idx(v, e, p)] - T(dt) * acc : un[idx(v, e, p)];
           }
+        if constexpr (Phys::SRC) {
+          // implicit source part of eq. crkfr.inner: + dt sum_{k<j} a_jk s(u^(k)),
+          // then u^(j) solves u - dt a_jj s(u) = (explicit part) when a_jj != 0
+          for (int p = 0; p < P; ++p) {
+            T r[M], x[M];
+            for (int v = 0; v < M; ++v) {
+              T acc = T(0.0);
+              bool any = false;
+              for (int k = 0; k < j; ++k)
+                if (tb.Ai[j * s + k] != 0.0) {
+                  T t = T(tb.Ai[j * s + k]) * Sst[((size_t)k * M + v) * P + p];
+                  acc = any ? acc + t : t;
+                  any = true;
+                }
+              r[v] = any ? uj[(size_t)v * P + p] + T(dt) * acc : uj[(size_t)v * P + p];
+            }
+            const double ajj = tb.Ai[j * s + j];
+            if (ajj != 0.0) ph.implicit(r, dt * ajj, x);
+            else for (int v = 0; v < M; ++v) x[v] = r[v];
+            for (int v = 0; v < M; ++v) uj[(size_t)v * P + p] = x[v];
+            ph.source(x, r);
+            for (int v = 0; v < M; ++v) {
+              Sst[((size_t)j * M + v) * P + p] = r[v];
+              if (tb.bi[j] != 0.0) L.S[idx(v, e, p)] = L.S[idx(v, e, p)] + T(tb.bi[j]) * r[v];
+            }
+          }
+        }
         // fluxes at the solution points
         for (int p = 0; p < P; ++p) {
           for (int v = 0; v < M; ++v) a[v] = uj[(size_t)v * P + p];
@@ -597,6 +630,8 @@ struct Scheme {
             R = R + (dF + cR * T(re.gRp[i]) + cL * T(re.gLp[i])) / T(dx[d]);
           }
           uH[(size_t)v * P + p] = un[idx(v, e, p)] - T(dt) * R;
+          // + dt S (eq. crkfr with the time-averaged source of eq. avg.source)
+          if constexpr (Phys::SRC) uH[(size_t)v * P + p] = uH[(size_t)v * P + p] + T(dt) * L.S[idx(v, e, p)];
         }
       if (cfg.blending == 0) {
         for (int v = 0; v < M; ++v)
@@ -628,6 +663,14 @@ struct Scheme {
             for (int v = 0; v < M; ++v) R[v] = R[v] + (right[v] - left[v]) / T(re.w[i] * dx[d]);
           }
           for (int v = 0; v < M; ++v) uL[(size_t)v * P + p] = un[idx(v, e, p)] - T(dt) * R[v];
+          // the source enters the subcell update implicitly (eq. low.order.update):
+          // u^L = r + dt s(u^L)
+          if constexpr (Phys::SRC) {
+            T r[M], x[M];
+            for (int v = 0; v < M; ++v) r[v] = uL[(size_t)v * P + p];
+            ph.implicit(r, dt, x);
+            for (int v = 0; v < M; ++v) uL[(size_t)v * P + p] = x[v];
+          }
         }
         // blend (eq. blended.scheme)
         double al = alpha[e];

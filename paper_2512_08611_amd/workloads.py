@@ -16,6 +16,8 @@ Workloads (sizes are those the time step is measured and checked on):
                    inside elements (density ratio <= 10, pressure ratio <= 100)
   * sw2d_random    2-D shallow water, seeded smooth bed and depth 1 + 0.2 noise
   * alfven         2-D GLM-MHD Alfven wave (paper §5.5, exact solution)
+  * jinxin_sine    1-D Jin-Xin relaxation for Burgers (paper §5.1 eq. jin.xin.ic) on
+                   [-1, 1], in equilibrium v = u^2/2
 """
 import math
 
@@ -79,6 +81,23 @@ def varadv_periodic(xi, nx, seed=0):
     """u = (v, a) with v = sin(2 pi x), a = 1 + sin(2 pi x)/2 (periodic variable coefficient)."""
     x = coords_1d(xi, nx)
     return np.stack([np.sin(2 * math.pi * x), 1.0 + 0.5 * np.sin(2 * math.pi * x)])
+
+
+def jinxin_sine(xi, nx, lo=-1.0, hi=1.0):
+    """u = 2 + sin(pi (x - 0.7)) (eq. jin.xin.ic), v = u^2/2: the equilibrium of the Burgers
+    relaxation (the paper gives no initial v)."""
+    x = coords_1d(xi, nx, lo, hi)
+    u = 2.0 + np.sin(math.pi * (x - 0.7))
+    return np.stack([u, 0.5 * u * u])
+
+
+def jinxin_random(xi, nx, seed=0, lo=-1.0, hi=1.0):
+    """smooth u in [1, 3] and v off equilibrium by a seeded smooth perturbation"""
+    rng = np.random.default_rng(seed)
+    x = coords_1d(xi, nx, lo, hi)
+    u = 2.0 + 0.5 * np.sin(math.pi * x + rng.uniform(0, 6)) + 0.3 * np.sin(3 * math.pi * x + rng.uniform(0, 6))
+    v = 0.5 * u * u + 0.2 * np.cos(2 * math.pi * x + rng.uniform(0, 6))
+    return np.stack([u, v])
 
 
 # ------------------------------------------------------------------ MHD ----
