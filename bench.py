@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-problem measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the rotor run and the GLL variant (profiling runs of the main workload)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 256 MiB (reference kernel for the HBM byte counters)")
     return ap.parse_args()
@@ -345,9 +347,10 @@ def main():
         out["adjoint_over_forward"] = adjoint_over_forward(torch, lwfr, workloads, np)
     if not args.no_batch:
         out["batched"] = batched(torch, lwfr, workloads, np)
-    out["rotor"] = rotor_run(torch, lwfr, workloads, np)
-    out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_GLL, K,
-                                   "Gauss-Lobatto-Legendre points with the g_2 correction")
+    if not args.no_extras:
+        out["rotor"] = rotor_run(torch, lwfr, workloads, np)
+        out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_GLL, K,
+                                       "Gauss-Lobatto-Legendre points with the g_2 correction")
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

@@ -57,7 +57,9 @@ typedef enum {
   LWFR_EQ_SW2D = 2,
   LWFR_EQ_GLMMHD2D = 3,  /* ideal GLM-MHD with Godunov-Powell and GLM terms (§5.5 eq. glm.mhd) */
   LWFR_EQ_LINADV1D = 4,  /* u_t + u_x = 0 (test system) */
-  LWFR_EQ_VARADV1D = 5   /* v_t + a v_x = 0 as a non-conservative system (§5.1 eq. var.coeff.adv.non.cons) */
+  LWFR_EQ_VARADV1D = 5,  /* v_t + a v_x = 0 as a non-conservative system (§5.1 eq. var.coeff.adv.non.cons) */
+  LWFR_EQ_JINXIN1D = 6   /* Jin-Xin relaxation (§5.1 eqs. jinxin1, jinxin2): u = (u, v), flux (v, a^2 u),
+                            stiff source (0, -(v - f(u))/eps), f(u) = l u + q u^2/2; needs an IMEX flag */
 } lwfr_equation;
 
 typedef enum {
@@ -105,6 +107,8 @@ typedef struct {
   uint32_t flags;        /* LWFR_CFG_* bits */
   int32_t bc[4];         /* lwfr_boundary of the sides x lo, x hi, y lo, y hi (y ignored in
                             1-D); a direction is periodic on both sides or on neither */
+  double source[4];      /* LWFR_EQ_JINXIN1D: a > 0, eps > 0, l, q (the paper's Burgers case:
+                            3, eps, 0, 1); ignored by the other systems */
 } lwfr_config;
 
 /* lwfr_config.flags: reserve the workspace of lwfr_adjoint_step */
@@ -115,6 +119,18 @@ typedef struct {
  * place of Gauss-Legendre points with the Radau correction.  Subcell widths
  * are the GLL weights; cfl_number = 0 takes the Fourier limit of this scheme. */
 #define LWFR_CFG_GLL 2u
+/* lwfr_config.flags: the IMEX pair of App. C that a system with a stiff source
+ * (LWFR_EQ_JINXIN1D, which needs one of them) takes in its inner stages (§2
+ * eq. crkfr.inner: explicit part on the local flux terms, pointwise implicit
+ * solves for the source), with the averaged source of eq. avg.source in the
+ * update and the source taken implicitly in the subcell update (eq.
+ * low.order.update).  HT(1,1,2): second order (eq. ht112.butcher);
+ * SSP3-IMEX(4,3,3): third order, L-stable (eq. ssp33.butcher, with the
+ * implicit rows (alpha), (-alpha, alpha), (0, 1-alpha, alpha),
+ * (beta, eta, 1/2-beta-eta-alpha, alpha), whose sums are the nodes).
+ * cfl_number = 0 takes the Fourier limit of the pair's explicit part. */
+#define LWFR_CFG_IMEX_HT112 4u
+#define LWFR_CFG_IMEX_SSP3 8u
 
 /* Validates cfg and builds the reference element, tableau and launch shapes on
  * the host.  No device work.  *out receives a context owned by the caller
@@ -137,7 +153,7 @@ lwfr_status lwfr_reference_nodes(const lwfr_ctx* ctx, double* xi, double* w);
 /* The library's Fourier (von Neumann) CFL(N) of the linearised scheme. */
 lwfr_status lwfr_cfl_number(int32_t degree, double* cfl);
 /* As lwfr_cfl_number for the scheme that lwfr_config.flags cfg_flags select
- * (LWFR_CFG_GLL). */
+ * (LWFR_CFG_GLL, LWFR_CFG_IMEX_*). */
 lwfr_status lwfr_cfl_number_for(int32_t degree, uint32_t cfg_flags, double* cfl);
 
 /* Doubles of the Dirichlet data of the context: for each side b = 2 d + s

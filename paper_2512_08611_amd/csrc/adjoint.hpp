@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   const bool act = e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   const size_t nf = (size_t)kp.E * NFP;
 
   double un[M], lam[M], gH[M], gL[M], gun[M];
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) k_adj_faces(const KParams kp, const AdjPa
   const int d = gid / nf;
   const int fi = gid - d * nf;
   const int e = fi / NFP, q = fi - (fi / NFP) * NFP;
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   if (d == 0) adj_face_point<Ph, N, 0>(kp, ap, un_g, e, q, pp);
   else if constexpr (DIM == 2) adj_face_point<Ph, N, 1>(kp, ap, un_g, e, q, pp);
 }
@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   const bool act = e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   const size_t nf = (size_t)kp.E * NFP;
 
   double un[M];

@@ -71,7 +71,12 @@ struct KParams {
   const double* ghost;        // Dirichlet face data, per side 2d+s: [3][M][lines_d*nfp]
   double* theta_left;         // [ny*nfp + nx*nfp] Algorithm 1 theta of the left boundary half faces
   uint32_t* guard_left;
+  double ra, reps, rl, rq;    // relaxation systems: a, eps, f(u) = rl u + rq u^2/2
 };
+
+__device__ inline PhysParams phys_params(const KParams& kp, double ch) {
+  return PhysParams{kp.g, kp.gamma, ch, kp.ra, kp.reps, kp.rl, kp.rq};
+}
 
 __device__ inline int nbr_elem(const KParams& kp, int e, int d, int side) {
   int ex = e % kp.nx, ey = e / kp.nx;
@@ -134,7 +139,7 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
   const int le = tid / P, p = tid - le * P;
   const int e = blk * EPB + le;
   const bool act = le < EPB && e < kp.E;
-  const PhysParams pp{kp.g, kp.gamma, 0.0};
+  const PhysParams pp = phys_params(kp, 0.0);
   const bool want_alpha = kp.blending >= 1 && kp.alpha_force < 0.0;
   // lanes without an element read element 0 (unconditional loads pipeline;
   // a load under a lane condition waits for its data before the next one)
@@ -329,10 +334,19 @@ __global__ void __launch_bounds__(1024) k_ch_fin(const KParams kp, double* d_dt_
 // Output: the volume part of the high order residual, B^loc + sum_d D_d F_d/dx_d,
 // which by linearity of D_d equals sum_s b_s L^(s) (written to the output state
 // buffer), and the face traces of F_d, U and u^n.
-template <int N>
-__host__ __device__ constexpr int first_nz(int t) {
+template <class Tab>
+__host__ __device__ constexpr int first_nz_t(int t) {
   for (int k = 0; k < t; ++k)
-    if (Tableau<N>::a(t, k) != 0.0) return k;
+    if (Tab::a(t, k) != 0.0) return k;
+  return -1;
+}
+template <int N>
+__host__ __device__ constexpr int first_nz(int t) { return first_nz_t<Tableau<N>>(t); }
+// first source term of stage t in the implicit part (k < t)
+template <class Tab>
+__host__ __device__ constexpr int first_nzi(int t) {
+  for (int k = 0; k < t; ++k)
+    if (Tab::ai(t, k) != 0.0) return k;
   return -1;
 }
 
@@ -344,13 +358,16 @@ struct StagesLds {
   double s_buf[EL][NBUF][P + LWFR_STAGES_PAD];
 };
 
-template <class Ph, int N, int EPB, int NT>
+// Tab: the explicit tableau of degree N, or for a system with a source its
+// IMEX pair (the source enters each stage through the implicit part, eq.
+// crkfr.inner, and its b-weighted average, eq. avg.source, is subtracted from
+// the volume residual).
+template <class Ph, int N, int EPB, int NT, class Tab = Tableau<N>>
 __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, NT>& L,
                                             const double* __restrict__ un_g, double* __restrict__ rvol_g,
                                             double* d_alpha_out, int blk) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
   constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
-  using Tab = Tableau<N>;
   constexpr int S = Tab::S;
   auto& s_buf = L.s_buf;
 
@@ -360,7 +377,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
   const bool act = le < EPB && e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
 
   double un[M];
 #pragma unroll
@@ -373,9 +390,10 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
   }
 
   double Fa[DIM][M], Ua[M], Ra[M], Sp[S][M], u[M];
+  double Q[Ph::SRC ? S : 1][M], Sa[M];  // implicit-part sums and the averaged source
 #pragma unroll
   for (int v = 0; v < M; ++v) {
-    Ua[v] = 0.0; Ra[v] = 0.0;
+    Ua[v] = 0.0; Ra[v] = 0.0; Sa[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Fa[d][v] = 0.0;
   }
@@ -383,7 +401,31 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
 #pragma unroll
   for (int st = 0; st < S; ++st) {
 #pragma unroll
-    for (int v = 0; v < M; ++v) u[v] = first_nz<N>(st) >= 0 ? un[v] - dt * Sp[st][v] : un[v];
+    for (int v = 0; v < M; ++v) u[v] = first_nz_t<Tab>(st) >= 0 ? un[v] - dt * Sp[st][v] : un[v];
+    if constexpr (Ph::SRC) {
+      // + dt sum_{k<st} a_st,k s(u^(k)), then the pointwise implicit solve
+      double r[M], sv[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) r[v] = first_nzi<Tab>(st) >= 0 ? u[v] + dt * Q[st][v] : u[v];
+      if (Tab::ai(st, st) != 0.0) Ph::implicit(r, dt * Tab::ai(st, st), u, pp);
+      else {
+#pragma unroll
+        for (int v = 0; v < M; ++v) u[v] = r[v];
+      }
+      Ph::source(u, sv, pp);
+      if (Tab::bi(st) != 0.0) {
+#pragma unroll
+        for (int v = 0; v < M; ++v) Sa[v] += Tab::bi(st) * sv[v];
+      }
+#pragma unroll
+      for (int t = st + 1; t < S; ++t) {
+        const double a = Tab::ai(t, st);
+        if (a != 0.0) {
+#pragma unroll
+          for (int v = 0; v < M; ++v) Q[t][v] = first_nzi<Tab>(t) == st ? a * sv[v] : Q[t][v] + a * sv[v];
+        }
+      }
+    }
     double f[DIM][M];
     Ph::template flux<0>(u, f[0], pp);
     if constexpr (DIM == 2) Ph::template flux<1>(u, f[1], pp);
@@ -447,9 +489,13 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
       const double a = Tab::a(t, st);
       if (a != 0.0) {
 #pragma unroll
-        for (int v = 0; v < M; ++v) Sp[t][v] = first_nz<N>(t) == st ? a * Ls[v] : Sp[t][v] + a * Ls[v];
+        for (int v = 0; v < M; ++v) Sp[t][v] = first_nz_t<Tab>(t) == st ? a * Ls[v] : Sp[t][v] + a * Ls[v];
       }
     }
+  }
+  if constexpr (Ph::SRC) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) Ra[v] -= Sa[v];
   }
 
   // time-averaged flux and solution to LDS for the face traces
@@ -579,7 +625,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
   const int vo = d ? H0 : 0;          // first variable of the lane's half
   const double dt = kp.scal[0];
   const double idx = d ? kp.inv_dx[1] : kp.inv_dx[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
 
   // u^n of the lane's half (lane 1 with H1 < H0 pads with its last variable)
   double uo[H0];
@@ -750,11 +796,12 @@ constexpr int stage_lanes() {
 template <class Ph, int N, int NT>
 using StageLdsT = typename std::conditional<stage_lanes<Ph>() == 2, Stages2Lds<Ph, N, NT>, StagesLds<Ph, N, NT>>::type;
 
-template <class Ph, int N, int EPB, int NT>
+template <class Ph, int N, int EPB, int NT, class Tab = Tableau<N>>
 __device__ __forceinline__ void stage_body(const KParams& kp, StageLdsT<Ph, N, NT>& L, const double* __restrict__ un_g,
                                            double* __restrict__ rvol_g, double* d_alpha_out, int blk) {
+  static_assert(stage_lanes<Ph>() == 1 || std::is_same<Tab, Tableau<N>>::value, "IMEX pairs use the one-lane kernel");
   if constexpr (stage_lanes<Ph>() == 2) stages2_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
-  else stages_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
+  else stages_body<Ph, N, EPB, NT, Tab>(kp, L, un_g, rvol_g, d_alpha_out, blk);
 }
 
 // threads of a stage workgroup of EPB elements
@@ -763,12 +810,12 @@ constexpr int stage_threads() {
   return stage_lanes<Ph>() == 2 ? stages2_threads(EPB, ipow(N + 1, Ph::DIM)) : EPB * ipow(N + 1, Ph::DIM);
 }
 
-template <class Ph, int N, int EPB>
+template <class Ph, int N, int EPB, class Tab = Tableau<N>>
 __global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
     k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
   constexpr int NT = stage_threads<Ph, N, EPB>();
   __shared__ StageLdsT<Ph, N, NT> L;
-  stage_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
+  stage_body<Ph, N, EPB, NT, Tab>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -943,7 +990,7 @@ __device__ __forceinline__ void faces_body(const KParams& kp, const double* __re
   const int fi = gid - d * nf;
   const int e = fi / NFP, q = fi - (fi / NFP) * NFP;
   const double dt = kp.scal[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   if (d == 0) face_point<Ph, N, 0>(kp, un_g, e, q, dt, pp);
   else if constexpr (DIM == 2) face_point<Ph, N, 1>(kp, un_g, e, q, dt, pp);
 }
@@ -1092,7 +1139,7 @@ __device__ inline void bface_point(const KParams& kp, const double* __restrict__
   const int j = line * NFP + q;
   const size_t nf = (size_t)kp.E * NFP;
   const double dt = kp.scal[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   const int ei = half == 0 ? eN : e0;  // the inside element
   const int fs = half == 0 ? 1 : 0;    // its face: right (1) or left (0)
   HalfSide<M> in, gh;
@@ -1201,7 +1248,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   const bool act = le < EPB && e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
-  const PhysParams pp{kp.g, kp.gamma, kp.scal[1]};
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   const size_t nf = (size_t)kp.E * NFP;
 
   // lanes without an element read element 0 (unconditional loads pipeline)
@@ -1299,6 +1346,13 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     double uL[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) uL[v] = un[v] - dt * RL[v];
+    if constexpr (Ph::SRC) {
+      // the source enters the subcell update implicitly (eq. low.order.update)
+      double x[M];
+      Ph::implicit(uL, dt, x, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) uL[v] = x[v];
+    }
     const double al = kp.alpha[es];
 #pragma unroll
     for (int v = 0; v < M; ++v) us[v] = (1.0 - al) * uH[v] + al * uL[v];

@@ -75,6 +75,7 @@ bool eq_info(int eq, EqInfo& info) {
     case LWFR_EQ_GLMMHD2D: info = {MHD2D::M, MHD2D::DIM, MHD2D::K}; return true;
     case LWFR_EQ_LINADV1D: info = {LinAdv1D::M, LinAdv1D::DIM, LinAdv1D::K}; return true;
     case LWFR_EQ_VARADV1D: info = {VarAdv1D::M, VarAdv1D::DIM, VarAdv1D::K}; return true;
+    case LWFR_EQ_JINXIN1D: info = {JinXin1D::M, JinXin1D::DIM, JinXin1D::K}; return true;
   }
   return false;
 }
@@ -153,8 +154,9 @@ struct TimedLaunch {
     LWFR_CHECK_LAUNCH(name);                 \
   } while (0)
 
-// The launch sequence of one step for system Ph at degree N.
-template <class Ph, int N>
+// The launch sequence of one step for system Ph at degree N (Tab: the stage
+// tableau, an IMEX pair for systems with a source).
+template <class Ph, int N, class Tab = Tableau<N>>
 lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
                         double* d_alpha, uint32_t* d_flags) {
   constexpr int DIM = Ph::DIM, P = ipow(N + 1, DIM), NFP = DIM == 1 ? 1 : N + 1;
@@ -170,7 +172,7 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   }
   const int nblk_el = (E + EPB - 1) / EPB;
   constexpr int EPBS = epb_stages<Ph, N>();
-  LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPBS>), dim3((E + EPBS - 1) / EPBS),
+  LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPBS, Tab>), dim3((E + EPBS - 1) / EPBS),
               dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
   const int nfp_total = DIM * E * NFP;
   LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
@@ -230,13 +232,28 @@ lwfr_status dispatch_adjoint(lwfr_ctx* c, const KParams& kp, const double* u_n, 
 template <class Ph>
 lwfr_status launch_step_n(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
                           double* d_alpha, uint32_t* d_flags) {
-  switch (c->N) {
-    case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+  if constexpr (Ph::SRC) {
+    const bool ht = (c->cfg.flags & LWFR_CFG_IMEX_HT112) != 0;
+    switch (c->N) {
+      case 1: return ht ? launch_step<Ph, 1, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
+                        : launch_step<Ph, 1, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 2: return ht ? launch_step<Ph, 2, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
+                        : launch_step<Ph, 2, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 3: return ht ? launch_step<Ph, 3, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
+                        : launch_step<Ph, 3, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 4: return ht ? launch_step<Ph, 4, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
+                        : launch_step<Ph, 4, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    }
+    return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
+  } else {
+    switch (c->N) {
+      case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    }
+    return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
   }
-  return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
 }
 
 lwfr_status dispatch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
@@ -247,6 +264,7 @@ lwfr_status dispatch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, do
     case LWFR_EQ_GLMMHD2D: return launch_step_n<MHD2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
     case LWFR_EQ_LINADV1D: return launch_step_n<LinAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
     case LWFR_EQ_VARADV1D: return launch_step_n<VarAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case LWFR_EQ_JINXIN1D: return launch_step_n<JinXin1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
   }
   return fail(LWFR_E_UNSUPPORTED, "unknown equation");
 }
@@ -554,7 +572,10 @@ lwfr_status lwfr_cfl_number(int32_t degree, double* cfl) {
 lwfr_status lwfr_cfl_number_for(int32_t degree, uint32_t cfg_flags, double* cfl) {
   if (!cfl) return fail(LWFR_E_INVALID_ARG, "cfl is null");
   if (degree < 1 || degree > 4) return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
-  *cfl = fourier_cfl(degree, (cfg_flags & LWFR_CFG_GLL) != 0);
+  const bool gll = (cfg_flags & LWFR_CFG_GLL) != 0;
+  if (cfg_flags & LWFR_CFG_IMEX_HT112) *cfl = fourier_cfl_imex<ImexHT>(degree, gll);
+  else if (cfg_flags & LWFR_CFG_IMEX_SSP3) *cfl = fourier_cfl_imex<ImexSSP3>(degree, gll);
+  else *cfl = fourier_cfl(degree, gll);
   return LWFR_OK;
 }
 
@@ -595,6 +616,20 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   }
   if (nonperiodic && (cfg->flags & LWFR_CFG_ADJOINT))
     return fail(LWFR_E_UNSUPPORTED, "the adjoint step needs a periodic mesh");
+  {
+    const uint32_t imex = cfg->flags & (LWFR_CFG_IMEX_HT112 | LWFR_CFG_IMEX_SSP3);
+    if (imex == (LWFR_CFG_IMEX_HT112 | LWFR_CFG_IMEX_SSP3))
+      return fail(LWFR_E_INVALID_ARG, "at most one IMEX pair");
+    if (cfg->equation == LWFR_EQ_JINXIN1D) {
+      if (!imex) return fail(LWFR_E_INVALID_ARG, "a system with a source needs an IMEX pair (LWFR_CFG_IMEX_*)");
+      if (!(cfg->source[0] > 0.0) || !(cfg->source[1] > 0.0) || !std::isfinite(cfg->source[2]) ||
+          !std::isfinite(cfg->source[3]))
+        return fail(LWFR_E_INVALID_ARG, "Jin-Xin needs a > 0, eps > 0 and finite l, q");
+      if (cfg->flags & LWFR_CFG_ADJOINT) return fail(LWFR_E_UNSUPPORTED, "no adjoint for systems with a source");
+    } else if (imex) {
+      return fail(LWFR_E_UNSUPPORTED, "IMEX pairs are for systems with a source");
+    }
+  }
 
   lwfr_ctx* c = new lwfr_ctx();
   c->cfg = *cfg;
@@ -610,7 +645,10 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   }
   const bool gll = (cfg->flags & LWFR_CFG_GLL) != 0;
   c->rd = make_refdata(c->N, gll);
-  c->cfl = cfg->cfl_number > 0.0 ? cfg->cfl_number : fourier_cfl(c->N, gll);
+  if (cfg->cfl_number > 0.0) c->cfl = cfg->cfl_number;
+  else if (cfg->flags & LWFR_CFG_IMEX_HT112) c->cfl = fourier_cfl_imex<ImexHT>(c->N, gll);
+  else if (cfg->flags & LWFR_CFG_IMEX_SSP3) c->cfl = fourier_cfl_imex<ImexSSP3>(c->N, gll);
+  else c->cfl = fourier_cfl(c->N, gll);
 
   KParams& kp = c->kp;
   std::memset(&kp, 0, sizeof(kp));
@@ -627,6 +665,9 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     for (int d = 0; d < 2; ++d) kp.inv_wdx[d][a] = 1.0 / (c->rd.w[a] * kp.dx[d]);
   }
   kp.g = cfg->gravity; kp.gamma = cfg->gamma;
+  if (cfg->equation == LWFR_EQ_JINXIN1D) {
+    kp.ra = cfg->source[0]; kp.reps = cfg->source[1]; kp.rl = cfg->source[2]; kp.rq = cfg->source[3];
+  }
   kp.blending = cfg->blending;
   kp.alpha_max = cfg->alpha_max; kp.alpha_min = cfg->alpha_min; kp.alpha_force = cfg->alpha_force;
   kp.ind_T = 0.5 * std::pow(10.0, -1.8 * std::pow(c->N + 1.0, 0.25));

@@ -10,6 +10,10 @@
 //   constraint(k,u)   P_k(u) of the admissible set (eq. uad.form)
 //   indicator(u)      variable seen by the smoothness indicator
 //   speeds<d>(u,|v|,c) ideal wave speeds used for the time step
+//   SRC               true for a system with a source term s(u); it then has
+//   source(u,s)       s(u)
+//   implicit(r,c,x)   the solution x of x - c s(x) = r, c >= 0 (the pointwise
+//                     implicit stage equation of §2 eq. crkfr.inner)
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -19,11 +23,13 @@ struct PhysParams {
   double g;       // gravity
   double gamma;   // ratio of specific heats
   double ch;      // GLM cleaning speed (device value for the current step)
+  double ra, reps, rl, rq;  // relaxation: speed a, time eps, f(u) = rl u + rq u^2/2
 };
 
 // Shallow water with the bed b carried as a variable: B u_x = (0, g h b_x, 0).
 struct SW1D {
   static constexpr int M = 3, DIM = 1, K = 1, NCD = 1;
+  static constexpr bool SRC = false;
   __host__ __device__ static constexpr int nc_comp(int, int) { return 2; }
   template <int d>
   __device__ static void flux(const double* u, double* f, const PhysParams& pp) {
@@ -72,6 +78,7 @@ struct SW1D {
 
 struct SW2D {
   static constexpr int M = 4, DIM = 2, K = 1, NCD = 1;
+  static constexpr bool SRC = false;
   __host__ __device__ static constexpr int flux_nc_alias(int) { return -1; }
   __host__ __device__ static constexpr int nc_comp(int, int) { return 3; }
   template <int d>
@@ -152,6 +159,7 @@ struct SW2D {
 // u = (rho, m1, m2, m3, E, B1, B2, B3, psi).
 struct MHD2D {
   static constexpr int M = 9, DIM = 2, K = 2, NCD = 2;
+  static constexpr bool SRC = false;
   __host__ __device__ static constexpr int nc_comp(int d, int i) { return i == 0 ? 5 + d : 8; }
   // flux components equal to c_h times a non-conservative column in every
   // direction (f_d[8] = c_h B_d): index of that column, else -1
@@ -419,6 +427,7 @@ struct MHD2D {
 // Linear advection u_t + u_x = 0.
 struct LinAdv1D {
   static constexpr int M = 1, DIM = 1, K = 0, NCD = 0;
+  static constexpr bool SRC = false;
   __host__ __device__ static constexpr int nc_comp(int, int) { return 0; }
   template <int d> __device__ static void flux(const double* u, double* f, const PhysParams&) { f[0] = u[0]; }
   template <int d> __device__ static void ncprod(const double*, const double*, double* o, const PhysParams&) { o[0] = 0.0; }
@@ -438,6 +447,7 @@ struct LinAdv1D {
 // f = 0, B(u) w = (u_2 w_1, 0) (§5.1 eq. var.coeff.adv.non.cons).
 struct VarAdv1D {
   static constexpr int M = 2, DIM = 1, K = 0, NCD = 1;
+  static constexpr bool SRC = false;
   __host__ __device__ static constexpr int nc_comp(int, int) { return 0; }
   template <int d> __device__ static void flux(const double*, double* f, const PhysParams&) { f[0] = 0.0; f[1] = 0.0; }
   template <int d> __device__ static void ncprod(const double* u, const double* w, double* o, const PhysParams&) {
@@ -458,6 +468,41 @@ struct VarAdv1D {
   }
   template <int d> __device__ static void sigma_vjp(const double* u, double sb, double* ub, const PhysParams&) {
     ub[1] += sb * (u[1] < 0.0 ? -1.0 : 1.0);
+  }
+};
+
+// Jin-Xin relaxation system (§5.1 eqs. jinxin1, jinxin2): u = (u, v), flux
+// (v, a^2 u), no non-conservative product, source (0, -(v - f(u))/eps) with
+// f(u) = l u + q u^2/2 (Burgers: l = 0, q = 1).  Flux eigenvalues +-a; no
+// admissibility constraint.
+struct JinXin1D {
+  static constexpr int M = 2, DIM = 1, K = 0, NCD = 0;
+  static constexpr bool SRC = true;
+  __host__ __device__ static constexpr int nc_comp(int, int) { return 0; }
+  __device__ static double feq(double u, const PhysParams& pp) { return pp.rl * u + 0.5 * pp.rq * u * u; }
+  template <int d> __device__ static void flux(const double* u, double* f, const PhysParams& pp) {
+    f[0] = u[1];
+    f[1] = pp.ra * pp.ra * u[0];
+  }
+  template <int d> __device__ static void ncprod(const double*, const double*, double* o, const PhysParams&) {
+    o[0] = 0.0; o[1] = 0.0;
+  }
+  template <int d> __device__ static double sigma(const double*, const PhysParams& pp) { return pp.ra; }
+  __device__ static double constraint(int, const double* u, const PhysParams&) { return u[0]; }
+  __device__ static double indicator(const double* u, const PhysParams&) { return u[0]; }
+  template <int d> __device__ static void speeds(const double*, double& av, double& c, const PhysParams& pp) {
+    av = 0.0; c = pp.ra;
+  }
+  __device__ static void source(const double* u, double* s, const PhysParams& pp) {
+    s[0] = 0.0;
+    s[1] = -(u[1] - feq(u[0], pp)) / pp.reps;
+  }
+  // x - c s(x) = r: x_1 = r_1 (no source in the first component); the second
+  // equation is linear in x_2: x_2 (1 + c/eps) = r_2 + (c/eps) f(r_1)
+  __device__ static void implicit(const double* r, double c, double* x, const PhysParams& pp) {
+    const double k = c / pp.reps;
+    x[0] = r[0];
+    x[1] = (r[1] + k * feq(r[0], pp)) / (1.0 + k);
   }
 };
 

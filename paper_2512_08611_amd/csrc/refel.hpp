@@ -178,23 +178,52 @@ inline double spectral_radius(int n, const cplx A[kMaxN1][kMaxN1]) {
   return rho;
 }
 
-inline double max_growth(const RefData& r, double nu) {
+// explicit tableau (s stages, A row-major s x s, weights b) for the time average
+struct ExplicitTab {
+  int s = 0;
+  double A[6][6] = {};
+  double b[6] = {};
+};
+
+// growth factor of the linear scheme at Courant number nu: the time average is
+// U = T u with T = sum_k (-nu D)^k/(k+1)! (an order N+1 tableau), or, for tab,
+// T = sum_i b_i R_i with R_1 = I, R_i = I + sum_{k<i} A_ik (-nu D) R_k
+inline double max_growth(const RefData& r, double nu, const ExplicitTab* tab = nullptr) {
   const int n = r.n1;
   double T[kMaxN1][kMaxN1] = {}, Pk[kMaxN1][kMaxN1] = {}, tmp[kMaxN1][kMaxN1];
-  for (int i = 0; i < n; ++i) Pk[i][i] = 1.0;
-  double fact = 1.0;
-  for (int k = 0; k <= r.N; ++k) {
-    fact *= (k + 1);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) T[i][j] += Pk[i][j] / fact;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int l = 0; l < n; ++l) s += Pk[i][l] * (-nu * r.D[l][j]);
-        tmp[i][j] = s;
+  if (!tab) {
+    for (int i = 0; i < n; ++i) Pk[i][i] = 1.0;
+    double fact = 1.0;
+    for (int k = 0; k <= r.N; ++k) {
+      fact *= (k + 1);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) T[i][j] += Pk[i][j] / fact;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          double s = 0.0;
+          for (int l = 0; l < n; ++l) s += Pk[i][l] * (-nu * r.D[l][j]);
+          tmp[i][j] = s;
+        }
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Pk[i][j] = tmp[i][j];
+    }
+  } else {
+    static thread_local double R[6][kMaxN1][kMaxN1];
+    for (int st = 0; st < tab->s; ++st) {
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) R[st][i][j] = i == j ? 1.0 : 0.0;
+      for (int k = 0; k < st; ++k) {
+        if (tab->A[st][k] == 0.0) continue;
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int l = 0; l < n; ++l) acc += -nu * r.D[i][l] * R[k][l][j];
+            R[st][i][j] += tab->A[st][k] * acc;
+          }
       }
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) Pk[i][j] = tmp[i][j];
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) T[i][j] += tab->b[st] * R[st][i][j];
+    }
   }
   double DT[kMaxN1][kMaxN1], RT[kMaxN1], LT[kMaxN1];
   for (int i = 0; i < n; ++i)
@@ -223,7 +252,7 @@ inline double max_growth(const RefData& r, double nu) {
 }
 }  // namespace detail
 
-inline double fourier_cfl(int N, bool gll = false) {
+inline double fourier_cfl(int N, bool gll = false, const detail::ExplicitTab* tab = nullptr) {
   const RefData r = make_refdata(N, gll);
   // degree 4: order-5 Taylor weights give nearly undamped modes a weak growth
   // (about 5e-6 per step below the limit); the limit is the sharp loss of
@@ -232,7 +261,7 @@ inline double fourier_cfl(int N, bool gll = false) {
   double lo = 0.0, hi = 1.5;
   while (hi - lo > 1e-9) {
     const double mid = 0.5 * (lo + hi);
-    if (detail::max_growth(r, mid) <= 1.0 + tol) lo = mid;
+    if (detail::max_growth(r, mid, tab) <= 1.0 + tol) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -242,14 +271,19 @@ inline double fourier_cfl(int N, bool gll = false) {
 // eq. crkfr.inner, explicit part only): N=1 Heun (HT(1,1,2), App. C),
 // N=2 SSPRK(3,3) (explicit part of SSP3-IMEX(4,3,3), App. C), N=3 classical
 // RK4, N=4 Butcher's six-stage fifth-order method.
+// Non-IMEX tableaux have no implicit part (ai, bi are zero; unused).
 template <int N> struct Tableau;
 template <> struct Tableau<1> {
   static constexpr int S = 2;
+  static constexpr double ai(int, int) { return 0.0; }
+  static constexpr double bi(int) { return 0.0; }
   static constexpr double a(int i, int j) { return (i == 1 && j == 0) ? 1.0 : 0.0; }
   static constexpr double b(int j) { return 0.5; }
 };
 template <> struct Tableau<2> {
   static constexpr int S = 3;
+  static constexpr double ai(int, int) { return 0.0; }
+  static constexpr double bi(int) { return 0.0; }
   static constexpr double a(int i, int j) {
     return (i == 1 && j == 0) ? 1.0 : (i == 2 && j < 2) ? 0.25 : 0.0;
   }
@@ -257,11 +291,15 @@ template <> struct Tableau<2> {
 };
 template <> struct Tableau<3> {
   static constexpr int S = 4;
+  static constexpr double ai(int, int) { return 0.0; }
+  static constexpr double bi(int) { return 0.0; }
   static constexpr double a(int i, int j) { return (i == j + 1) ? (i == 3 ? 1.0 : 0.5) : 0.0; }
   static constexpr double b(int j) { return (j == 0 || j == 3) ? 1.0 / 6.0 : 1.0 / 3.0; }
 };
 template <> struct Tableau<4> {
   static constexpr int S = 6;
+  static constexpr double ai(int, int) { return 0.0; }
+  static constexpr double bi(int) { return 0.0; }
   static constexpr double a(int i, int j) {
     return i == 1 ? (j == 0 ? 0.25 : 0.0)
          : i == 2 ? (j < 2 ? 0.125 : 0.0)
@@ -275,5 +313,47 @@ template <> struct Tableau<4> {
     return (j == 0 || j == 5) ? 7.0 / 90.0 : (j == 2 || j == 4) ? 32.0 / 90.0 : j == 3 ? 12.0 / 90.0 : 0.0;
   }
 };
+
+// IMEX pairs of App. C for systems with a stiff source (§2 eq. crkfr.inner):
+// explicit part (a, b) on the local flux terms, diagonally implicit part
+// (ai, bi) on the source.
+//   ImexHT:   HT(1,1,2) (eq. ht112.butcher): Heun with the trapezoidal rule.
+//   ImexSSP3: SSP3-IMEX(4,3,3) of Pareschi and Russo (eq. ssp33.butcher), with
+//             the implicit rows (alpha), (-alpha, alpha), (0, 1-alpha, alpha),
+//             (beta, eta, 1/2-beta-eta-alpha, alpha): the printed rows are
+//             garbled, these satisfy c_i = sum_j a_ij and the order conditions.
+struct ImexHT {
+  static constexpr int S = 2;
+  static constexpr double a(int i, int j) { return (i == 1 && j == 0) ? 1.0 : 0.0; }
+  static constexpr double b(int) { return 0.5; }
+  static constexpr double ai(int i, int j) { return i == 1 ? 0.5 : 0.0; }
+  static constexpr double bi(int) { return 0.5; }
+};
+struct ImexSSP3 {
+  static constexpr int S = 4;
+  static constexpr double kA = 0.241694260788, kB = 0.0604235651970, kE = 0.12915286960590;
+  static constexpr double a(int i, int j) { return i == 2 ? (j == 1 ? 1.0 : 0.0) : i == 3 ? (j == 1 || j == 2 ? 0.25 : 0.0) : 0.0; }
+  static constexpr double b(int j) { return j == 0 ? 0.0 : j == 3 ? 2.0 / 3.0 : 1.0 / 6.0; }
+  static constexpr double ai(int i, int j) {
+    return i == j ? kA
+         : i == 1 ? (j == 0 ? -kA : 0.0)
+         : i == 2 ? (j == 1 ? 1.0 - kA : 0.0)
+         : i == 3 ? (j == 0 ? kB : j == 1 ? kE : j == 2 ? 0.5 - kB - kE - kA : 0.0)
+                  : 0.0;
+  }
+  static constexpr double bi(int j) { return b(j); }
+};
+
+// Fourier limit of degree N with the explicit part of IMEX pair Tab
+template <class Tab>
+inline double fourier_cfl_imex(int N, bool gll) {
+  detail::ExplicitTab t;
+  t.s = Tab::S;
+  for (int i = 0; i < Tab::S; ++i) {
+    t.b[i] = Tab::b(i);
+    for (int j = 0; j < i; ++j) t.A[i][j] = Tab::a(i, j);
+  }
+  return fourier_cfl(N, gll, &t);
+}
 
 }  // namespace lwfr

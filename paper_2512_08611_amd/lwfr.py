@@ -16,13 +16,15 @@ ABI_VERSION = 2
 LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
 LWFR_E_INADMISSIBLE, LWFR_E_NONFINITE, LWFR_E_WORKSPACE, LWFR_E_STATE = 4, 5, 6, 7
 LWFR_EQ_SW1D, LWFR_EQ_SW2D, LWFR_EQ_GLMMHD2D, LWFR_EQ_LINADV1D, LWFR_EQ_VARADV1D = 1, 2, 3, 4, 5
+LWFR_EQ_JINXIN1D = 6
 LWFR_CFG_ADJOINT = 1
 LWFR_CFG_GLL = 2
+LWFR_CFG_IMEX_HT112, LWFR_CFG_IMEX_SSP3 = 4, 8
 LWFR_BC_PERIODIC, LWFR_BC_OUTFLOW, LWFR_BC_WALL, LWFR_BC_DIRICHLET = 0, 1, 2, 3
 LWFR_FLAG_ALG2, LWFR_FLAG_LOW_INADM, LWFR_FLAG_ALG1, LWFR_FLAG_NONFINITE, LWFR_FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
 
-NVARS = {1: 3, 2: 4, 3: 9, 4: 1, 5: 2}
-DIMS = {1: 1, 2: 2, 3: 2, 4: 1, 5: 1}
+NVARS = {1: 3, 2: 4, 3: 9, 4: 1, 5: 2, 6: 2}
+DIMS = {1: 1, 2: 2, 3: 2, 4: 1, 5: 1, 6: 1}
 
 
 class LwfrError(RuntimeError):
@@ -49,6 +51,7 @@ class lwfr_config(ctypes.Structure):
         ("alpha_force", ctypes.c_double),
         ("flags", ctypes.c_uint32),
         ("bc", ctypes.c_int32 * 4),
+        ("source", ctypes.c_double * 4),
     ]
 
 
@@ -135,8 +138,9 @@ def _ptr(t):
 
 def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81,
                 cfl_safety=0.9, cfl_number=0.0, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0,
-                flags=0, bc=(0, 0, 0, 0)):
-    """bc: LWFR_BC_* of the sides (x lo, x hi, y lo, y hi); periodic by default."""
+                flags=0, bc=(0, 0, 0, 0), source=(3.0, 1e-2, 0.0, 1.0)):
+    """bc: LWFR_BC_* of the sides (x lo, x hi, y lo, y hi); periodic by default.
+    source: Jin-Xin (a, eps, l, q), f(u) = l u + q u^2/2 (LWFR_EQ_JINXIN1D only)."""
     c = lwfr_config()
     c.abi_version = ABI_VERSION
     c.equation, c.degree = equation, degree
@@ -149,6 +153,7 @@ def make_config(equation, degree, nelem, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0
     c.flags = flags
     for i in range(4):
         c.bc[i] = bc[i]
+        c.source[i] = source[i]
     return c
 
 

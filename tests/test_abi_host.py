@@ -168,3 +168,37 @@ def test_boundary_validation():
     arr = (lwfr.lwfr_config * 1)(*cfgs)
     h = ctypes.c_void_p()
     assert lwfr.lib().lwfr_batch_init(arr, 1, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("imex", [1, 2])
+def test_imex_cfl_matches_oracle(N, imex):
+    """Fourier limit with the explicit part of an IMEX pair: library (host) vs oracle."""
+    flag = {1: lwfr.LWFR_CFG_IMEX_HT112, 2: lwfr.LWFR_CFG_IMEX_SSP3}[imex]
+    c = oracle.cfl_number(N, False, imex)
+    if imex == 1 and N == 3:
+        # the second-order explicit part leaves degree 3 a band of weak growth whose
+        # edge moves with the growth tolerance (1e-11 here, 1e-12 in the oracle)
+        assert 0.005 < lwfr.lwfr_cfl_number(N, flag) < 0.02 and 0.005 < c < 0.02
+        return
+    assert abs(lwfr.lwfr_cfl_number(N, flag) - c) < 2e-6 * c
+
+
+def test_imex_validation():
+    J = lwfr.LWFR_EQ_JINXIN1D
+    ok = lwfr.lwfr_init(lwfr.make_config(J, 3, 10, flags=lwfr.LWFR_CFG_IMEX_SSP3))
+    lwfr.lwfr_destroy(ok)
+    cases = [
+        (dict(equation=J), lwfr.LWFR_E_INVALID_ARG),  # a source needs an IMEX pair
+        (dict(equation=J, flags=lwfr.LWFR_CFG_IMEX_SSP3 | lwfr.LWFR_CFG_IMEX_HT112), lwfr.LWFR_E_INVALID_ARG),
+        (dict(equation=J, flags=lwfr.LWFR_CFG_IMEX_SSP3, source=(3.0, 0.0, 0.0, 1.0)), lwfr.LWFR_E_INVALID_ARG),
+        (dict(equation=J, flags=lwfr.LWFR_CFG_IMEX_SSP3, source=(-1.0, 1e-2, 0.0, 1.0)), lwfr.LWFR_E_INVALID_ARG),
+        (dict(equation=J, flags=lwfr.LWFR_CFG_IMEX_HT112 | lwfr.LWFR_CFG_ADJOINT), lwfr.LWFR_E_UNSUPPORTED),
+        (dict(equation=lwfr.LWFR_EQ_SW1D, flags=lwfr.LWFR_CFG_IMEX_HT112), lwfr.LWFR_E_UNSUPPORTED),
+    ]
+    for kw, st in cases:
+        args = dict(degree=3, nelem=10)
+        args.update(kw)
+        with pytest.raises(lwfr.LwfrError) as ei:
+            lwfr.lwfr_init(lwfr.make_config(**args))
+        assert ei.value.status == st, kw

@@ -1,0 +1,171 @@
+"""IMEX steps for a stiff source on the GPU: the Jin-Xin relaxation system (§5.1
+eqs. jinxin1, jinxin2) with HT(1,1,2) and SSP3-IMEX(4,3,3) (App. C), through the
+C ABI.
+
+  * one step against the oracle to the parity bar of the other systems (1e-12
+    per value relative to max(|value|, 1e-2 max|u^n|), dt to 1e-13, alpha_e to
+    1e-12, flags bit-exact), N = 1..4, blending off / indicator / limiting,
+    eps = 1e-1 and 1e-3, the Burgers flux and the linear one, data off
+    equilibrium;
+  * eps = 1e-12 (the paper's stiffest case): u to 1e-12; v to the conditioning
+    of the averaged source, whose rounding in v - f(u) is amplified by dt/eps;
+  * the paper's run (eq. jin.xin.ic, a = 3, SSP3-IMEX(4,3,3), N = 3, t = 0.25) for
+    eps = 1e-1, 1e-2, 1e-3, 1e-12: bounded, u within its initial range, and
+    steps compared with the oracle along the way;
+  * the linear relaxation system against its exact Fourier solution: the GPU
+    run's order.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+import oracle
+from paper_2512_08611_amd import lwfr
+from paper_2512_08611_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+FLAG = {1: lwfr.LWFR_CFG_IMEX_HT112, 2: lwfr.LWFR_CFG_IMEX_SSP3}
+
+
+class JX:
+    def __init__(self, imex, N, nx, eps, l=0.0, q=1.0, a=3.0, blending=2, alpha_force=-1.0, lo=-1.0, hi=1.0):
+        cfl = oracle.cfl_number(N, False, imex)
+        self.src = (a, eps, l, q)
+        self.cfg = lwfr.make_config(lwfr.LWFR_EQ_JINXIN1D, N, nx, lo=(lo, 0.0), hi=(hi, 1.0), cfl_number=cfl,
+                                    blending=blending, alpha_force=alpha_force, flags=FLAG[imex], source=self.src)
+        self.st = lwfr.Stepper(self.cfg, DEV)
+        self.oc = oracle.make_cfg(oracle.EQ_JINXIN1D, N, nx, lo=(lo, 0.0), hi=(hi, 1.0), cfl=cfl, blending=blending,
+                                  alpha_force=alpha_force, imex=imex, relax=self.src)
+        self.N, self.nx, self.lo, self.hi = N, nx, lo, hi
+
+    def gpu(self, u, dt=0.0):
+        ud = torch.tensor(u, dtype=torch.float64, device=DEV)
+        out = torch.empty_like(ud)
+        dtch = torch.zeros(2, dtype=torch.float64, device=DEV)
+        al = torch.zeros(self.nx, dtype=torch.float64, device=DEV)
+        fl = torch.zeros(self.nx, dtype=torch.int32, device=DEV)
+        self.st.step(ud, out, dt, dtch, al, fl)
+        torch.cuda.synchronize()
+        return dict(u=out.cpu().numpy(), dt=float(dtch[0]), alpha=al.cpu().numpy(),
+                    flags=fl.cpu().numpy().astype(np.uint32))
+
+    def check(self, u, dt=0.0, vtol=None):
+        g = self.gpu(u, dt)
+        o = oracle.step(self.oc, u, dt=dt)
+        assert abs(g["dt"] - o["dt"]) <= 1e-13 * o["dt"]
+        scale = np.maximum(np.abs(o["u"]), 1e-2 * np.abs(u).max())
+        err = np.abs(g["u"] - o["u"]) / scale
+        print(f"IMEX PARITY N={self.N} eps={self.src[1]:.0e} u={err[0].max():.2e} v={err[1].max():.2e}", flush=True)
+        assert err[0].max() <= 1e-12
+        if vtol is None:
+            assert err[1].max() <= 1e-12
+        else:
+            assert np.abs(g["u"][1] - o["u"][1]).max() <= vtol
+        assert np.abs(g["alpha"] - o["alpha"]).max() <= 1e-12
+        np.testing.assert_array_equal(g["flags"], o["flags"])
+        return g, o
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
+@pytest.mark.parametrize("imex", [1, 2])
+@pytest.mark.parametrize("blending", [0, 1, 2])
+@pytest.mark.parametrize("eps", [1e-1, 1e-3])
+@pytest.mark.parametrize("flux", ["burgers", "linear"])
+def test_parity(N, imex, blending, eps, flux):
+    l, q = (0.0, 1.0) if flux == "burgers" else (0.5, 0.0)
+    p = JX(imex, N, 37, eps, l, q, blending=blending)
+    xi = oracle.refel(N)["xi"]
+    for seed in (0, 1):
+        p.check(W.jinxin_random(xi, 37, seed))
+    p.check(W.jinxin_sine(xi, 37))
+
+
+@pytest.mark.parametrize("N", [2, 3])
+@pytest.mark.parametrize("blending", [0, 2])
+def test_parity_subcell_and_blend(N, blending):
+    xi = oracle.refel(N)["xi"]
+    for af in (1.0, 0.3):
+        p = JX(2, N, 29, 1e-2, blending=1, alpha_force=af)
+        p.check(W.jinxin_random(xi, 29, 3))
+
+
+@pytest.mark.parametrize("N", [1, 3])
+def test_stiff_parity(N):
+    eps = 1e-12
+    p = JX(2, N, 40, eps)
+    u = W.jinxin_random(oracle.refel(N)["xi"], 40, 5)
+    dt = oracle.dt_ch(p.oc, u)[0]
+    fmax = 0.5 * np.abs(u[0]).max() ** 2
+    p.check(u, vtol=50 * dt * 2.2e-16 * fmax / eps)
+
+
+def test_paper_run_to_t025():
+    N, nx, tend = 3, 100, 0.25
+    xi = None
+    for eps in (1e-1, 1e-2, 1e-3, 1e-12):
+        p = JX(2, N, nx, eps)
+        xi = np.array(p.st.xi)
+        u0 = W.jinxin_sine(xi, nx)
+        ua = torch.tensor(u0, dtype=torch.float64, device=DEV)
+        ub = torch.empty_like(ua)
+        dtch = torch.zeros(2, dtype=torch.float64, device=DEV)
+        t, k = 0.0, 0
+        fmax = 0.5 * 3.0 ** 2
+        while t < tend:
+            compare = k % 25 == 0
+            if compare:
+                un = ua.cpu().numpy()
+            p.st.step(ua, ub, 0.0, dtch)
+            dt = float(dtch[0])
+            if t + dt > tend:
+                dt = tend - t
+                p.st.step(ua, ub, dt, dtch)
+            if compare:
+                o = oracle.step(p.oc, un, dt=dt)["u"]
+                g = ub.cpu().numpy()
+                assert (np.abs(g[0] - o[0]) / np.maximum(np.abs(o[0]), 1e-2)).max() <= 1e-12
+                vtol = max(1e-12 * fmax, 50 * dt * 2.2e-16 * fmax / eps)
+                assert np.abs(g[1] - o[1]).max() <= vtol
+            ua, ub = ub, ua
+            t += dt
+            k += 1
+        st, flags = p.st.query()
+        assert st == lwfr.LWFR_OK, flags
+        u = ua.cpu().numpy()
+        print(f"JINXIN eps={eps:.0e} steps={k} u in [{u[0].min():.4f}, {u[0].max():.4f}] "
+              f"max|v - u^2/2|={np.abs(u[1] - 0.5 * u[0] ** 2).max():.2e}", flush=True)
+        assert np.isfinite(u).all()
+        assert u[0].min() > 1.0 - 0.05 and u[0].max() < 3.0 + 0.05
+
+
+def linear_exact(x, t, a, eps, l, k=2 * math.pi):
+    Mx = np.array([[0, -1j * k], [-1j * k * a * a + l / eps, -1 / eps]])
+    y = scipy.linalg.expm(Mx * t) @ np.array([1.0, l], dtype=complex)
+    return np.real(y[0] * np.exp(1j * k * x)), np.real(y[1] * np.exp(1j * k * x))
+
+
+@pytest.mark.parametrize("imex,N,ns,rate", [(1, 1, (32, 64), 2), (2, 2, (16, 32), 3), (2, 3, (16, 32), 3)])
+def test_linear_order_on_gpu(imex, N, ns, rate):
+    a, eps, l, tend = 1.0, 0.05, 0.5, 0.25
+    errs = []
+    for nx in ns:
+        p = JX(imex, N, nx, eps, l, 0.0, a=a, blending=0, lo=0.0, hi=1.0)
+        x = W.coords_1d(np.array(p.st.xi), nx)
+        u = torch.tensor(np.stack(linear_exact(x, 0.0, a, eps, l)), dtype=torch.float64, device=DEV)
+        v = torch.empty_like(u)
+        dt = oracle.dt_ch(p.oc, u.cpu().numpy())[0]
+        n = int(math.ceil(tend / dt))
+        for _ in range(n):
+            p.st.step(u, v, tend / n)
+            u, v = v, u
+        ue, ve = linear_exact(x, tend, a, eps, l)
+        g = u.cpu().numpy()
+        w = np.array(p.st.w)
+        errs.append(math.sqrt((((g[0] - ue) ** 2 + (g[1] - ve) ** 2) * w).sum() / nx))
+    got = math.log(errs[0] / errs[1]) / math.log(ns[1] / ns[0])
+    print(f"IMEX ORDER imex={imex} N={N} errs={errs} rate={got:.2f}", flush=True)
+    assert got > rate - 0.3
