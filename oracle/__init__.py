@@ -49,6 +49,7 @@ class OraCfg(ctypes.Structure):
         ("imex", ctypes.c_int32),
         ("relax_a", ctypes.c_double), ("relax_eps", ctypes.c_double),
         ("relax_l", ctypes.c_double), ("relax_q", ctypes.c_double),
+        ("alw", ctypes.c_int32),
     ]
 
 
@@ -70,7 +71,7 @@ BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_DIRICHLET = 0, 1, 2, 3
 
 def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81, cs=0.9,
              cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0, gll=False,
-             bc=(0, 0, 0, 0), imex=0, relax=(3.0, 1e-2, 0.0, 1.0)):
+             bc=(0, 0, 0, 0), imex=0, relax=(3.0, 1e-2, 0.0, 1.0), alw=False):
     """gll: Gauss-Lobatto-Legendre solution points with the g_2 correction (App. B)
     instead of Gauss-Legendre points with the Radau correction.
     bc: boundary kinds of the sides (x lo, x hi, y lo, y hi), BC_* (periodic by
@@ -78,6 +79,8 @@ def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gra
     imex: IMEX pair (IMEX_HT112, IMEX_SSP3) in place of the degree's explicit
     tableau; required by systems with a source.  relax: Jin-Xin (a, eps, l, q),
     f(u) = l u + q u^2/2 (Burgers by default).
+    alw: time averages by the approximate Lax-Wendroff procedure (finite
+    differences in time along Taylor states) instead of the cRK stages.
     cfl=None takes the Fourier limit of the scheme these select."""
     c = OraCfg()
     c.eq, c.N, c.nx, c.ny = eq, N, nx, (ny if DIMS[eq] == 2 else 1)
@@ -92,6 +95,7 @@ def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gra
     c.ghost = None
     c.imex = imex
     c.relax_a, c.relax_eps, c.relax_l, c.relax_q = relax
+    c.alw = 1 if alw else 0
     return c
 
 
@@ -219,6 +223,17 @@ def ghost_size(c):
         lines = c.ny if d == 0 else c.nx
         tot += 2 * 3 * M * lines * nfp(c)
     return tot
+
+
+def time_averages(c, u, dt, ch=0.0):
+    """(F [d][v][e][p], U, B^loc) of the element-local stage (or approximate LW) procedure."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    d = DIMS[c.eq]
+    F = np.zeros((d,) + u.shape)
+    U, Bl = np.zeros_like(u), np.zeros_like(u)
+    assert lib().ora_time_averages(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch), _p(F), _p(U),
+                                   _p(Bl)) == 0
+    return F, U, Bl
 
 
 def residual(c, u, dt, mode, ch=-1.0):

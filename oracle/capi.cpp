@@ -21,6 +21,7 @@ struct ora_cfg {
   const double* ghost;  // Dirichlet data (see Config::ghost)
   int32_t imex;         // IMEX pair of a system with a source: 1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)
   double relax_a, relax_eps, relax_l, relax_q;  // Jin-Xin a, eps and f(u) = l u + q u^2/2
+  int32_t alw;          // 1: approximate Lax-Wendroff time averages
 };
 
 static Config to_cfg(const ora_cfg* c) {
@@ -38,6 +39,7 @@ static Config to_cfg(const ora_cfg* c) {
   k.relax_eps = c->relax_eps;
   k.relax_l = c->relax_l;
   k.relax_q = c->relax_q;
+  k.alw = c->alw;
   return k;
 }
 
@@ -49,6 +51,7 @@ static int dispatch(const ora_cfg* c, Fn fn, bool steps_ = true) {
   if (k.N < 0 || k.N > 4 || k.nx < 1 || k.ny < 1) return 1;
   if (k.gll && k.N < 1) return 1;
   if (k.imex < 0 || k.imex > 2) return 1;
+  if (k.alw && (k.imex || k.N < 1)) return 1;
   if (k.eq == EQ_JINXIN1D && (k.imex == 0 || !(k.relax_eps > 0.0) || !(k.relax_a > 0.0))) return 1;
   for (int d = 0; d < 2; ++d) {
     if ((k.bc[d][0] == BC_PERIODIC) != (k.bc[d][1] == BC_PERIODIC)) return 3;
@@ -199,6 +202,20 @@ int ora_step(const ora_cfg* c, const double* u, double* unew, double dt_in, doub
     if (alpha_out) std::memcpy(alpha_out, alpha.data(), alpha.size() * sizeof(double));
     if (tie) std::memcpy(tie, t.data(), t.size());
   });
+}
+
+// Element-local time averages of one step (the stages, or the approximate LW
+// procedure with cfg alw): F [d][v][e][p], U [v][e][p], B^loc [v][e][p].
+int ora_time_averages(const ora_cfg* c, const double* u, double dt, double ch, double* F, double* U, double* Bl) {
+  return dispatch(c, [&](auto& s) {
+    using S = std::decay_t<decltype(s)>;
+    typename S::template Local<double> L;
+    if (s.cfg.alw) s.stages_alw(u, dt, ch, L);
+    else s.stages(u, dt, ch, L);
+    std::memcpy(F, L.F.data(), L.F.size() * sizeof(double));
+    std::memcpy(U, L.U.data(), L.U.size() * sizeof(double));
+    std::memcpy(Bl, L.Bl.data(), L.Bl.size() * sizeof(double));
+  }, false);
 }
 
 // Residual R = (u^n - u^{n+1})/dt; mode 0: high order only (alpha = 0, no

@@ -44,6 +44,7 @@ struct Config {
   double alpha_force;  // >= 0: every alpha_e is set to this value (tests, residual modes)
   int gll = 0;         // 1: Gauss-Lobatto-Legendre solution points with g_2 correction (App. B)
   int imex = 0;        // IMEX pair of a system with a source (tableau.hpp): 1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)
+  int alw = 0;         // 1: time averages by the approximate Lax-Wendroff procedure (stages_alw)
   // Jin-Xin characteristic speed a, relaxation time eps, f(u) = l u + q u^2/2
   double relax_a = 3.0, relax_eps = 1e-2, relax_l = 0.0, relax_q = 1.0;
   // boundary condition of side (d, s): BC_PERIODIC, BC_OUTFLOW (the ghost copies
@@ -341,6 +342,123 @@ struct Scheme {
                   L.F[(size_t)d * M * E * P + idx(v, e, p)] + bj * f[((size_t)d * M + v) * P + p];
           }
         }
+      }
+    }
+  }
+
+  // ---------------- 3'. element-local time averages, approximate Lax-Wendroff ---
+  // The Lax-Wendroff form of the time averages that the cRK stages reproduce
+  // (§5: cRKFR is linearly equivalent to LWFR):
+  //   F_d = sum_{k=0}^{N} dt^k/(k+1)! d_t^k f_d,  U = sum_k dt^k/(k+1)! d_t^k u,
+  //   B^loc = sum_k dt^k/(k+1)! d_t^k [ sum_d B_d(u) u_{x_d} ],
+  // with d_t^{k+1} u = -( sum_d D_d d_t^k f_d / dx_d + d_t^k [B u_x] ) (the local
+  // operator) and d_t^k f, d_t^k [B u_x] from central differences in time of
+  // f(u(tau)), B(u(tau)) D u(tau) at tau = j dt along the Taylor state
+  // u(tau) = sum_{m<=k} tau^m/m! d_t^m u.  Stencils (derived from Taylor series,
+  // order enough for the step's order N+1): j in {-1,0,1} for N <= 2,
+  // {-2..2} for N >= 3;  dt^k d_t^k g ~
+  //   k=1: (g1 - g-1)/2                | (-g2 + 8g1 - 8g-1 + g-2)/12
+  //   k=2: g1 - 2g0 + g-1              | (-g2 + 16g1 - 30g0 + 16g-1 - g-2)/12
+  //   k=3: (g2 - 2g1 + 2g-1 - g-2)/2
+  //   k=4: g2 - 4g1 + 6g0 - 4g-1 + g-2
+  static double fd_weight(int N, int k, int j) {
+    if (k == 0) return j == 0 ? 1.0 : 0.0;
+    if (N <= 2) {
+      if (j < -1 || j > 1) return 0.0;
+      if (k == 1) return 0.5 * j;
+      return j == 0 ? -2.0 : 1.0;  // k == 2
+    }
+    static const double w[5][5] = {
+        {0, 0, 1, 0, 0},
+        {1.0 / 12, -8.0 / 12, 0, 8.0 / 12, -1.0 / 12},
+        {-1.0 / 12, 16.0 / 12, -30.0 / 12, 16.0 / 12, -1.0 / 12},
+        {-0.5, 1.0, 0, -1.0, 0.5},
+        {1, -4, 6, -4, 1}};
+    return w[k][j + 2];
+  }
+
+  template <class T>
+  void stages_alw(const T* un, double dt, double ch, Local<T>& L) const {
+    L.F.assign((size_t)DIM * M * E * P, T(0.0));
+    L.U.assign((size_t)M * E * P, T(0.0));
+    L.Bl.assign((size_t)M * E * P, T(0.0));
+    L.Fnc.assign((size_t)DIM * 2 * M * E * nfp, T(0.0));
+    L.Ftr.assign(L.Fnc.size(), T(0.0));
+    L.Utr.assign(L.Fnc.size(), T(0.0));
+    L.untr.assign(L.Fnc.size(), T(0.0));
+    const int J = N <= 2 ? 1 : 2;  // stencil half width
+    // c[m][v][p]: d_t^m u at the nodes; fk[d][v][p]: dt^k d_t^k f_d; hk[v][p]: dt^k d_t^k [B u_x]
+    std::vector<T> c((size_t)(N + 1) * M * P), fk((size_t)DIM * M * P), hk((size_t)M * P);
+    std::vector<T> st((size_t)M * P);
+    T a[M], fo[M], du[M], nc[M];
+    double fact = 1.0;
+    for (int e = 0; e < E; ++e) {
+      for (int v = 0; v < M; ++v)
+        for (int p = 0; p < P; ++p) c[(size_t)v * P + p] = un[idx(v, e, p)];
+      fact = 1.0;
+      for (int k = 0; k <= N; ++k) {
+        fact *= (k + 1);  // (k+1)!
+        for (size_t i = 0; i < fk.size(); ++i) fk[i] = T(0.0);
+        for (size_t i = 0; i < hk.size(); ++i) hk[i] = T(0.0);
+        for (int j = -J; j <= J; ++j) {
+          const double wj = fd_weight(N, k, j);
+          if (wj == 0.0) continue;
+          // Taylor state at tau = j dt truncated after d_t^k u
+          for (int v = 0; v < M; ++v)
+            for (int p = 0; p < P; ++p) {
+              T sacc = c[(size_t)v * P + p];
+              double tm = 1.0;
+              for (int m = 1; m <= k; ++m) {
+                tm *= (j * dt) / m;
+                sacc = sacc + T(tm) * c[((size_t)m * M + v) * P + p];
+              }
+              st[(size_t)v * P + p] = sacc;
+            }
+          for (int p = 0; p < P; ++p) {
+            for (int v = 0; v < M; ++v) a[v] = st[(size_t)v * P + p];
+            for (int d = 0; d < DIM; ++d) {
+              ph.flux(d, a, fo, ch);
+              for (int v = 0; v < M; ++v) fk[((size_t)d * M + v) * P + p] = fk[((size_t)d * M + v) * P + p] + T(wj) * fo[v];
+            }
+            // B(u(tau)) D u(tau) / dx, summed over directions
+            for (int d = 0; d < DIM; ++d) {
+              int i = pos(d, p), q = line(d, p);
+              for (int v = 0; v < M; ++v) du[v] = T(0.0);
+              for (int cc = 0; cc < Phys::NCOL; ++cc) {
+                const int v = Phys::ncol(d, cc);
+                T dv = T(0.0);
+                for (int r = 0; r < n1; ++r) dv = dv + T(re.D[i * n1 + r]) * st[(size_t)v * P + node(d, q, r)];
+                du[v] = dv;
+              }
+              ph.ncprod(d, a, du, nc);
+              for (int v = 0; v < M; ++v) hk[(size_t)v * P + p] = hk[(size_t)v * P + p] + T(wj) * nc[v] / T(dx[d]);
+            }
+          }
+        }
+        // accumulate the time averages
+        for (int v = 0; v < M; ++v)
+          for (int p = 0; p < P; ++p) {
+            const double tk = std::pow(dt, k) / fact;  // dt^k/(k+1)!
+            L.U[idx(v, e, p)] = L.U[idx(v, e, p)] + T(tk) * c[((size_t)k * M + v) * P + p];
+            L.Bl[idx(v, e, p)] = L.Bl[idx(v, e, p)] + hk[(size_t)v * P + p] / T(fact);
+            for (int d = 0; d < DIM; ++d)
+              L.F[(size_t)d * M * E * P + idx(v, e, p)] =
+                  L.F[(size_t)d * M * E * P + idx(v, e, p)] + fk[((size_t)d * M + v) * P + p] / T(fact);
+          }
+        if (k == N) break;
+        // d_t^{k+1} u = -(sum_d D_d d_t^k f_d / dx_d + d_t^k [B u_x]); fk, hk hold dt^k d_t^k
+        const double idtk = 1.0 / std::pow(dt, k);
+        for (int p = 0; p < P; ++p)
+          for (int v = 0; v < M; ++v) {
+            T r = hk[(size_t)v * P + p];
+            for (int d = 0; d < DIM; ++d) {
+              int i = pos(d, p), q = line(d, p);
+              T df = T(0.0);
+              for (int rr = 0; rr < n1; ++rr) df = df + T(re.D[i * n1 + rr]) * fk[((size_t)d * M + v) * P + node(d, q, rr)];
+              r = r + df / T(dx[d]);
+            }
+            c[((size_t)(k + 1) * M + v) * P + p] = -T(idtk) * r;
+          }
       }
     }
   }
@@ -717,7 +835,8 @@ struct Scheme {
             double* theta_face, double* theta_elem) const {
     Local<T> L;
     Faces<T> Fc;
-    stages(un, dt, ch, L);
+    if (cfg.alw) stages_alw(un, dt, ch, L);
+    else stages(un, dt, ch, L);
     face_traces(un, L);
     faces(un, L, alpha, dt, ch, Fc);
     if (theta_face) std::copy(Fc.theta.begin(), Fc.theta.end(), theta_face);
