@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-problem measurement")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the rotor run and the GLL variant (profiling runs of the main workload)")
+                    help="skip the rotor run and the variants (GLL, approximate LW, Jin-Xin IMEX): profiling runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 256 MiB (reference kernel for the HBM byte counters)")
     return ap.parse_args()
@@ -200,6 +200,38 @@ def variant_timing(torch, lwfr, workloads, np, n, N, flags, steps, name):
         "kernels_ms_per_launch": {k: ms / c for k, (ms, c) in kern.items() if c},
         "step_status": int(status),
         "flags_or": int(flags_or),
+    }
+
+
+def jinxin_timing(torch, lwfr, workloads, np, steps, nx=1 << 20, N=3, eps=1e-12):
+    """The Jin-Xin relaxation system (eq. jin.xin.ic on [-1, 1], a = 3, Burgers flux) with
+    SSP3-IMEX(4,3,3) at the paper's stiffest eps, N = 3, nx elements: DOF-updates/s."""
+    dev = torch.device("cuda:0")
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_JINXIN1D, N, nx, lo=(-1.0, 0.0), hi=(1.0, 1.0), blending=2,
+                           flags=lwfr.LWFR_CFG_IMEX_SSP3, source=(3.0, eps, 0.0, 1.0))
+    st = lwfr.Stepper(cfg, dev)
+    ua = torch.tensor(workloads.jinxin_sine(np.array(st.xi), nx), dtype=torch.float64, device=dev)
+    ub = torch.empty_like(ua)
+    for _ in range(3):
+        st.step(ua, ub)
+        ua, ub = ub, ua
+    lwfr.lwfr_timing_begin(st.ctx, 8 * steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step(ua, ub)
+        ua, ub = ub, ua
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = lwfr.lwfr_timing_end(st.ctx)
+    status, flags_or = st.query()
+    dofs = nx * (N + 1) * 2
+    return {
+        "workload": f"Jin-Xin relaxation (Burgers, a=3, eps={eps:g}), {nx} elements, N={N}, SSP3-IMEX(4,3,3)",
+        "value": nx * (N + 1) * steps / wall, "unit": "DOF-updates/s (solution points x steps)",
+        "ms_per_step": wall / steps * 1e3, "variables": 2, "doubles_per_state": dofs,
+        "kernels_ms_per_launch": {k: ms / c for k, (ms, c) in kern.items() if c},
+        "step_status": int(status), "flags_or": int(flags_or),
     }
 
 
@@ -351,6 +383,9 @@ def main():
         out["rotor"] = rotor_run(torch, lwfr, workloads, np)
         out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_GLL, K,
                                        "Gauss-Lobatto-Legendre points with the g_2 correction")
+        out["alw"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_ALW, K,
+                                    "approximate Lax-Wendroff time averages in place of the cRK stages")
+        out["imex_jinxin"] = jinxin_timing(torch, lwfr, workloads, np, K)
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)

@@ -131,6 +131,15 @@ typedef struct {
  * cfl_number = 0 takes the Fourier limit of the pair's explicit part. */
 #define LWFR_CFG_IMEX_HT112 4u
 #define LWFR_CFG_IMEX_SSP3 8u
+/* lwfr_config.flags: element-local time averages by the approximate Lax-Wendroff
+ * procedure instead of the cRK inner stages: F_d, U and B^loc as Taylor series
+ * in time up to dt^N, the time derivatives of f_d and of B(u) u_x by central
+ * differences (3 points for N <= 2, 5 for N >= 3) along Taylor-extrapolated
+ * states, d_t^{k+1} u from the local operator.  The paper's cRK stages are
+ * linearly equivalent to this Lax-Wendroff form (§5); the stencils are this
+ * library's.  Not with an IMEX pair, LWFR_CFG_ADJOINT or in batches
+ * (LWFR_E_UNSUPPORTED). */
+#define LWFR_CFG_ALW 16u
 
 /* Validates cfg and builds the reference element, tableau and launch shapes on
  * the host.  No device work.  *out receives a context owned by the caller
@@ -153,7 +162,8 @@ lwfr_status lwfr_reference_nodes(const lwfr_ctx* ctx, double* xi, double* w);
 /* The library's Fourier (von Neumann) CFL(N) of the linearised scheme. */
 lwfr_status lwfr_cfl_number(int32_t degree, double* cfl);
 /* As lwfr_cfl_number for the scheme that lwfr_config.flags cfg_flags select
- * (LWFR_CFG_GLL, LWFR_CFG_IMEX_*). */
+ * (LWFR_CFG_GLL, LWFR_CFG_IMEX_*; LWFR_CFG_ALW has the limit of the cRK stages:
+ * both are the Lax-Wendroff scheme for linear problems). */
 lwfr_status lwfr_cfl_number_for(int32_t degree, uint32_t cfg_flags, double* cfl);
 
 /* Doubles of the Dirichlet data of the context: for each side b = 2 d + s

@@ -358,6 +358,75 @@ struct StagesLds {
   double s_buf[EL][NBUF][P + LWFR_STAGES_PAD];
 };
 
+// Outputs of the element-local phase, shared by the stage body and the
+// approximate Lax-Wendroff body: the volume residual Ra, the face traces of the
+// time averages F_d, U and of u^n, and the smoothed blending coefficient.
+// sb: the element's LDS rows (at least DIM*M + M of them); every thread of the
+// workgroup calls it (it synchronises).
+template <class Ph, int N, int NB, int PS>
+__device__ __forceinline__ void stage_outputs(const KParams& kp, double (&sb)[NB][PS], int p, int e, bool act,
+                                              const double (&Fa)[Ph::DIM][Ph::M], const double (&Ua)[Ph::M],
+                                              const double (&Ra)[Ph::M], const double* __restrict__ un_g,
+                                              double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  static_assert(NB >= DIM * M + M && PS >= P, "LDS rows");
+  // time-averaged flux and solution to LDS for the face traces
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int v = 0; v < M; ++v) sb[d * M + v][p] = Fa[d][v];
+#pragma unroll
+  for (int v = 0; v < M; ++v) sb[DIM * M + v][p] = Ua[v];
+  __syncthreads();
+
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) rvol_g[((size_t)v * kp.E + e) * P + p] = Ra[v];
+    // face traces: (variable, face point) pairs of the element, variable
+    // slowest, over the element's threads
+    constexpr int NFT = 2 * DIM * NFP;
+    for (int w = p; w < NFT * M; w += P) {
+      const int v = w / NFT, t = w - v * NFT;
+      const int d = t / (2 * NFP);
+      const int rem = t - d * 2 * NFP;
+      const int side = rem / NFP;
+      const int q = rem - side * NFP;
+      const double* V = side ? kp.VR : kp.VL;
+      const size_t nf = (size_t)kp.E * NFP;
+      const size_t fo = (size_t)e * NFP + q;
+      {
+        double tf = 0.0, tu = 0.0, tn = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+          const int nd = d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r);
+          tf += V[r] * sb[d * M + v][nd];
+          tu += V[r] * sb[DIM * M + v][nd];
+          tn += V[r] * un_g[((size_t)v * kp.E + e) * P + nd];
+        }
+        const size_t o = ((size_t)(d * 2 + side) * M + v) * nf + fo;
+        kp.Ftr[o] = tf;
+        kp.Utr[o] = tu;
+        kp.untr[o] = tn;
+      }
+    }
+    // blending coefficient of the element (smoothed over face neighbours)
+    if (p == 0) {
+      double a;
+      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
+      else if (kp.blending == 0) a = 0.0;
+      else {
+        a = kp.alpha_raw[e];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, d, sd)]);
+      }
+      kp.alpha[e] = a;
+      if (d_alpha_out) d_alpha_out[e] = a;
+    }
+  }
+}
+
 // Tab: the explicit tableau of degree N, or for a system with a source its
 // IMEX pair (the source enters each stage through the implicit part, eq.
 // crkfr.inner, and its b-weighted average, eq. avg.source, is subtracted from
@@ -498,61 +567,171 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
     for (int v = 0; v < M; ++v) Ra[v] -= Sa[v];
   }
 
-  // time-averaged flux and solution to LDS for the face traces
-#pragma unroll
-  for (int d = 0; d < DIM; ++d)
-#pragma unroll
-    for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = Fa[d][v];
-#pragma unroll
-  for (int v = 0; v < M; ++v) s_buf[le][DIM * M + v][p] = Ua[v];
-  __syncthreads();
+  stage_outputs<Ph, N>(kp, s_buf[le], p, e, act, Fa, Ua, Ra, un_g, rvol_g, d_alpha_out);
+}
 
-  if (act) {
+// ------------------------------------------------------------------------
+// Approximate Lax-Wendroff time averages (the alternative to the cRK stages):
+//   F_d = sum_{k<=N} dt^k/(k+1)! d_t^k f_d, U = sum_k dt^k/(k+1)! d_t^k u,
+//   B^loc = sum_k dt^k/(k+1)! d_t^k [B u_x],
+// with d_t^{k+1} u = -(sum_d D_d d_t^k f_d / dx_d + d_t^k [B u_x]) and the time
+// derivatives of f_d and B(u) u_x from central differences at tau = j dt along
+// the Taylor state u(tau) = sum_{m<=k} tau^m/m! d_t^m u (3 points for N <= 2,
+// 5 for N >= 3).  One thread per solution point keeps the Taylor coefficients
+// c[m] and the derivatives along each line of the components B reads; the
+// D_d products go through LDS.
+
+// weight of tau = j dt in dt^k d_t^k g (j in -2..2)
+__host__ __device__ constexpr double alw_weight(int N, int k, int j) {
+  return k == 0 ? (j == 0 ? 1.0 : 0.0)
+       : N <= 2 ? ((j < -1 || j > 1) ? 0.0 : k == 1 ? 0.5 * j : (j == 0 ? -2.0 : 1.0))
+       : k == 1 ? (j == -2 ? 1.0 / 12 : j == -1 ? -8.0 / 12 : j == 1 ? 8.0 / 12 : j == 2 ? -1.0 / 12 : 0.0)
+       : k == 2 ? (j == 0 ? -30.0 / 12 : (j == -1 || j == 1) ? 16.0 / 12 : -1.0 / 12)
+       : k == 3 ? (j == -2 ? -0.5 : j == -1 ? 1.0 : j == 1 ? -1.0 : j == 2 ? 0.5 : 0.0)
+                : (j == 0 ? 6.0 : (j == -1 || j == 1) ? -4.0 : 1.0);
+}
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void alw_body(const KParams& kp, StagesLds<Ph, N, NT>& L, const double* __restrict__ un_g,
+                                         double* __restrict__ rvol_g, double* d_alpha_out, int blk) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
+  constexpr int NCD = Ph::NCD > 0 ? Ph::NCD : 1;
+  constexpr int J = N <= 2 ? 1 : 2;
+  auto& s_buf = L.s_buf;
+  const int tid = threadIdx.x;
+  const int le = tid / P, p = tid - le * P;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
+  const int i = p % n1, j = p / n1;
+  const double dt = kp.scal[0];
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
+
+  double c[N + 1][M];        // d_t^m u at this node
+  double Dc[N + 1][DIM][NCD];  // D_d (d_t^m u) of the components B_d reads, / dx_d
 #pragma unroll
-    for (int v = 0; v < M; ++v) rvol_g[((size_t)v * kp.E + e) * P + p] = Ra[v];
-    // face traces: (variable, face point) pairs of the element, variable
-    // slowest, over the element's threads
-    constexpr int NFT = 2 * DIM * NFP;
-    for (int w = p; w < NFT * M; w += P) {
-      const int v = w / NFT, t = w - v * NFT;
-      const int d = t / (2 * NFP);
-      const int rem = t - d * 2 * NFP;
-      const int side = rem / NFP;
-      const int q = rem - side * NFP;
-      const double* V = side ? kp.VR : kp.VL;
-      const size_t nf = (size_t)kp.E * NFP;
-      const size_t fo = (size_t)e * NFP + q;
-      {
-        double tf = 0.0, tu = 0.0, tn = 0.0;
+  for (int v = 0; v < M; ++v) c[0][v] = un_g[((size_t)v * kp.E + (act ? e : 0)) * P + p];
+  // derivative along direction d of LDS row `row` at this node
+  auto dline = [&](int d, int row) {
+    const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
+    double acc = 0.0;
 #pragma unroll
-        for (int r = 0; r < n1; ++r) {
-          const int nd = d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r);
-          tf += V[r] * s_buf[le][d * M + v][nd];
-          tu += V[r] * s_buf[le][DIM * M + v][nd];
-          tn += V[r] * un_g[((size_t)v * kp.E + e) * P + nd];
+    for (int r = 0; r < n1; ++r) acc += kp.D[ii][r] * s_buf[le][row][node_at<n1>(d, q, r)];
+    return acc;
+  };
+  // D_d of the nc components of c[m]
+  auto nc_derivs = [&](int m) {
+    if constexpr (Ph::NCD > 0) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int cc = 0; cc < Ph::NCD; ++cc) s_buf[le][d * NCD + cc][p] = c[m][Ph::nc_comp(d, cc)];
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int cc = 0; cc < Ph::NCD; ++cc) Dc[m][d][cc] = dline(d, d * NCD + cc) * kp.inv_dx[d];
+      __syncthreads();
+    }
+  };
+  nc_derivs(0);
+
+  double Fa[DIM][M], Ua[M], Ra[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    Ua[v] = 0.0; Ra[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Fa[d][v] = 0.0;
+  }
+  double fact = 1.0, dtk = 1.0;  // (k+1)!, dt^k
+#pragma unroll
+  for (int k = 0; k <= N; ++k) {
+    fact *= (k + 1);
+    double fk[DIM][M], hk[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      hk[v] = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) fk[d][v] = 0.0;
+    }
+#pragma unroll
+    for (int jj = -J; jj <= J; ++jj) {
+      const double wj = alw_weight(N, k, jj);
+      if (wj == 0.0) continue;
+      // Taylor state and its line derivatives at tau = jj dt
+      double st[M], tm[N + 1];
+      tm[0] = 1.0;
+#pragma unroll
+      for (int m = 1; m <= k; ++m) tm[m] = tm[m - 1] * (jj * dt) / m;
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double a = c[0][v];
+#pragma unroll
+        for (int m = 1; m <= k; ++m) a += tm[m] * c[m][v];
+        st[v] = a;
+      }
+      double f[M];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if (d == 0) Ph::template flux<0>(st, f, pp);
+        else Ph::template flux<(DIM > 1 ? 1 : 0)>(st, f, pp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) fk[d][v] += wj * f[v];
+        if constexpr (Ph::NCD > 0) {
+          double w[M], nc[M];
+#pragma unroll
+          for (int v = 0; v < M; ++v) w[v] = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < Ph::NCD; ++cc) {
+            double a = Dc[0][d][cc];
+#pragma unroll
+            for (int m = 1; m <= k; ++m) a += tm[m] * Dc[m][d][cc];
+            w[Ph::nc_comp(d, cc)] = a;
+          }
+          if (d == 0) Ph::template ncprod<0>(st, w, nc, pp);
+          else Ph::template ncprod<(DIM > 1 ? 1 : 0)>(st, w, nc, pp);
+#pragma unroll
+          for (int v = 0; v < M; ++v) hk[v] += wj * nc[v];
         }
-        const size_t o = ((size_t)(d * 2 + side) * M + v) * nf + fo;
-        kp.Ftr[o] = tf;
-        kp.Utr[o] = tu;
-        kp.untr[o] = tn;
       }
     }
-    // blending coefficient of the element (smoothed over face neighbours)
-    if (p == 0) {
-      double a;
-      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
-      else if (kp.blending == 0) a = 0.0;
-      else {
-        a = kp.alpha_raw[e];
+    // sum_d D_d fk_d / dx_d through LDS
+    double r[M];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d)
+    for (int d = 0; d < DIM; ++d)
 #pragma unroll
-          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, d, sd)]);
-      }
-      kp.alpha[e] = a;
-      if (d_alpha_out) d_alpha_out[e] = a;
+      for (int v = 0; v < M; ++v) s_buf[le][d * M + v][p] = fk[d][v];
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double a = hk[v];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) a += dline(d, d * M + v) * kp.inv_dx[d];
+      r[v] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      Ua[v] += dtk / fact * c[k][v];
+      Ra[v] += r[v] / fact;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) Fa[d][v] += fk[d][v] / fact;
+    }
+    if (k < N) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) c[k + 1][v] = -r[v] / dtk;
+      nc_derivs(k + 1);
+      dtk *= dt;
     }
   }
+  stage_outputs<Ph, N>(kp, s_buf[le], p, e, act, Fa, Ua, Ra, un_g, rvol_g, d_alpha_out);
+}
+
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+    k_stages_alw(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
+  __shared__ StagesLds<Ph, N, NT> L;
+  alw_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------

@@ -172,8 +172,14 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   }
   const int nblk_el = (E + EPB - 1) / EPB;
   constexpr int EPBS = epb_stages<Ph, N>();
-  LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPBS, Tab>), dim3((E + EPBS - 1) / EPBS),
-              dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
+  if (c->cfg.flags & LWFR_CFG_ALW) {
+    if constexpr (!Ph::SRC)
+      LWFR_LAUNCH(KID_STAGES, "k_stages_alw", (k_stages_alw<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp,
+                  u_in, u_out, d_alpha);
+  } else {
+    LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPBS, Tab>), dim3((E + EPBS - 1) / EPBS),
+                dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
+  }
   const int nfp_total = DIM * E * NFP;
   LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
   if (c->bface_threads > 0)
@@ -629,6 +635,8 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     } else if (imex) {
       return fail(LWFR_E_UNSUPPORTED, "IMEX pairs are for systems with a source");
     }
+    if ((cfg->flags & LWFR_CFG_ALW) && (imex || (cfg->flags & LWFR_CFG_ADJOINT)))
+      return fail(LWFR_E_UNSUPPORTED, "the approximate Lax-Wendroff averages have no IMEX or adjoint form");
   }
 
   lwfr_ctx* c = new lwfr_ctx();
@@ -973,6 +981,10 @@ lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch**
     if (cfgs[i].flags & LWFR_CFG_ADJOINT) {
       lwfr_batch_destroy(b);
       return fail(LWFR_E_UNSUPPORTED, "batches have no adjoint");
+    }
+    if (cfgs[i].flags & LWFR_CFG_ALW) {
+      lwfr_batch_destroy(b);
+      return fail(LWFR_E_UNSUPPORTED, "batches use the cRK stages");
     }
     for (int k = 0; k < 4; ++k)
       if (cfgs[i].bc[k] == LWFR_BC_DIRICHLET) {

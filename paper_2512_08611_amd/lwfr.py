@@ -20,6 +20,7 @@ LWFR_EQ_JINXIN1D = 6
 LWFR_CFG_ADJOINT = 1
 LWFR_CFG_GLL = 2
 LWFR_CFG_IMEX_HT112, LWFR_CFG_IMEX_SSP3 = 4, 8
+LWFR_CFG_ALW = 16
 LWFR_BC_PERIODIC, LWFR_BC_OUTFLOW, LWFR_BC_WALL, LWFR_BC_DIRICHLET = 0, 1, 2, 3
 LWFR_FLAG_ALG2, LWFR_FLAG_LOW_INADM, LWFR_FLAG_ALG1, LWFR_FLAG_NONFINITE, LWFR_FLAG_ALG1_GUARD = 1, 2, 4, 8, 16
 

@@ -202,3 +202,19 @@ def test_imex_validation():
         with pytest.raises(lwfr.LwfrError) as ei:
             lwfr.lwfr_init(lwfr.make_config(**args))
         assert ei.value.status == st, kw
+
+
+def test_alw_validation():
+    A = lwfr.LWFR_CFG_ALW
+    for eq in (lwfr.LWFR_EQ_SW1D, lwfr.LWFR_EQ_GLMMHD2D):
+        lwfr.lwfr_destroy(lwfr.lwfr_init(lwfr.make_config(eq, 3, (4, 4), flags=A)))
+    for flags, eq in [(A | lwfr.LWFR_CFG_ADJOINT, lwfr.LWFR_EQ_SW1D),
+                      (A | lwfr.LWFR_CFG_IMEX_SSP3, lwfr.LWFR_EQ_JINXIN1D)]:
+        with pytest.raises(lwfr.LwfrError) as ei:
+            lwfr.lwfr_init(lwfr.make_config(eq, 3, 8, flags=flags))
+        assert ei.value.status == lwfr.LWFR_E_UNSUPPORTED
+    arr = (lwfr.lwfr_config * 1)(lwfr.make_config(lwfr.LWFR_EQ_SW2D, 2, (4, 4), flags=A))
+    h = ctypes.c_void_p()
+    assert lwfr.lib().lwfr_batch_init(arr, 1, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
+    # the same Fourier limit as the cRK stages
+    assert lwfr.lwfr_cfl_number(3, A) == lwfr.lwfr_cfl_number(3)
