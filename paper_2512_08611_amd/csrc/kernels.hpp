@@ -1174,6 +1174,171 @@ __device__ __forceinline__ void faces_body(const KParams& kp, const double* __re
   else if constexpr (DIM == 2) face_point<Ph, N, 1>(kp, un_g, e, q, dt, pp);
 }
 
+// ------------------------------------------------------------------------
+// Face kernel of the nine-variable systems with two lanes per face point: the
+// lane of the minus side (lower half-wave) holds the traces of element e at its
+// right face and the nodes next to it, the lane of the plus side (upper
+// half-wave) those of the neighbour at its left face.  Each evaluates its own
+// side's wave speed, flux, non-conservative products, lower order flux, subcell
+// flux and Algorithm 1 candidate; the values the formulas combine (C, U, the
+// node states and fluxes, sigma, theta) cross between the two with
+// v_permlane32_swap (cross_pair).  Same arithmetic as face_point, about half
+// the registers per lane.  Lane t of a workgroup: side (t >> 5) & 1, face point
+// slot 32 (t >> 6) + (t & 31).
+template <class Ph>
+constexpr int face_lanes() { return Ph::M >= 8 ? 2 : 1; }
+
+// (value on the minus lane, value on the plus lane) of x
+__device__ inline void pair_values(double x, double& lo, double& hi) {
+  lo = x; hi = x;
+  cross_pair(lo, hi);
+}
+
+template <class Ph, int N, int d>
+__device__ inline void face_point2(const KParams& kp, const double* __restrict__ un_g, int e, int q, int side,
+                                   double dt, const PhysParams& pp) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  const int en = nbr_elem(kp, e, d, 1);
+  const int eo = side ? en : e;         // the lane's element
+  const int ts = side ? 0 : 1;          // its face: left (0) or right (1)
+  const size_t nf = (size_t)kp.E * NFP;
+  const size_t fio = (size_t)eo * NFP + q;
+  auto tr = [&](int v) { return ((size_t)(d * 2 + ts) * M + v) * nf + fio; };
+  auto node = [&](int v, int r) { return un_g[((size_t)v * kp.E + eo) * P + node_at<n1>(d, q, r)]; };
+  double s[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) s[v] = node(v, side ? 0 : N);
+  double F[M], C[M];
+  {
+    double a[M], U[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      a[v] = kp.untr[tr(v)];
+      U[v] = kp.Utr[tr(v)];
+      C[v] = kp.Ftr[tr(v)];
+    }
+    const double sg = admissible<Ph>(a, pp) ? Ph::template sigma<d>(a, pp) : Ph::template sigma<d>(s, pp);
+    double sa, sb;
+    pair_values(sg, sa, sb);
+    const double lam = sa >= sb ? sa : sb;
+    double Unum[M], t[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double cl, ch, ul, uh;
+      pair_values(C[v], cl, ch);
+      pair_values(U[v], ul, uh);
+      F[v] = 0.5 * (cl + ch) - 0.5 * lam * (uh - ul);  // F^num
+      Unum[v] = 0.5 * (ul + uh);
+    }
+    Ph::template ncprod<d>(a, Unum, t, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) F[v] += t[v];
+    Ph::template ncprod<d>(a, U, t, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) C[v] += t[v];  // C^-/C^+ of the lane's side
+  }
+  const double af = kp.blending == 0 ? 0.0 : 0.5 * (kp.alpha[e] + kp.alpha[en]);
+  double Theta = 1.0;
+  bool guard = false;
+  if (!(af == 0.0 && kp.blending != 2)) {
+    // lower order flux at the face from the two neighbouring node states
+    double fLO[M];
+    {
+      double f[M], sl[M], sh[M], avg[M];
+      Ph::template flux<d>(s, f, pp);
+      double gl, gh;
+      pair_values(Ph::template sigma<d>(s, pp), gl, gh);
+      const double lam = gl >= gh ? gl : gh;
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double fl, fh;
+        pair_values(f[v], fl, fh);
+        pair_values(s[v], sl[v], sh[v]);
+        fLO[v] = 0.5 * (fl + fh) - 0.5 * lam * (sh[v] - sl[v]);
+        avg[v] = 0.5 * (sl[v] + sh[v]);
+      }
+      Ph::template ncprod<d>(s, avg, f, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) fLO[v] += f[v];
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) F[v] = (1.0 - af) * F[v] + af * fLO[v];
+    if (kp.blending == 2 && N >= 1) {
+      // Algorithm 1: the lane's subcell next to the face, DIM*dt in its update
+      double fin[M];
+      {
+        double si[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) si[v] = node(v, side ? 1 : N - 1);
+        if (side) low_flux<Ph, d>(s, si, fin, nullptr, pp);  // f^{e+1,-}_{1/2}
+        else low_flux<Ph, d>(si, s, nullptr, fin, pp);       // f^{e,+}_{N-1/2}
+      }
+      const double cs = DIM * dt * kp.inv_wdx[d][side ? 0 : N];
+#pragma unroll
+      for (int k = 0; k < Ph::K; ++k) {
+        double x[M];
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = s[v] - cs * (side ? fin[v] - fLO[v] : fLO[v] - fin[v]);
+        const double Plo = Ph::constraint(k, x, pp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) x[v] = s[v] - cs * (side ? fin[v] - F[v] : F[v] - fin[v]);
+        const double thl = theta_limit(0.1 * Plo, Plo, Ph::constraint(k, x, pp), guard);
+        double thN, th0;
+        pair_values(thl, thN, th0);
+        const double th = th0 <= thN ? th0 : thN;
+        if (th < 1.0) {
+#pragma unroll
+          for (int v = 0; v < M; ++v) F[v] = th * F[v] + (1.0 - th) * fLO[v];
+        }
+        Theta *= th;
+      }
+      double gl, gh;
+      pair_values(guard ? 1.0 : 0.0, gl, gh);
+      guard = (gl != 0.0) || (gh != 0.0);
+    }
+  }
+  // outputs: the minus lane F^- and D^-, the plus lane F^+ and D^+ (slot of the face = e's)
+  const size_t fiL = (size_t)e * NFP + q;
+  double* Fo = side ? kp.Fp : kp.Fm;
+  double* Do = side ? kp.Dp : kp.Dm;
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const size_t o = ((size_t)d * M + v) * nf + fiL;
+    Fo[o] = F[v];
+    Do[o] = F[v] - C[v];
+  }
+  if (!side) {
+    kp.theta_face[(size_t)d * nf + fiL] = Theta;
+    kp.guard_face[(size_t)d * nf + fiL] = guard ? 1u : 0u;
+  }
+}
+
+template <class Ph, int N>
+__device__ __forceinline__ void faces2_body(const KParams& kp, const double* __restrict__ un_g, int blk) {
+  constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
+  const int t = threadIdx.x;
+  const int side = (t >> 5) & 1;
+  const int gid = blk * (int)(blockDim.x / 2) + (((t >> 6) << 5) | (t & 31));
+  const int nf = kp.E * NFP;
+  if (gid >= DIM * nf) return;  // both lanes of a face point leave together
+  const int d = gid / nf;
+  const int fi = gid - d * nf;
+  const int e = fi / NFP, q = fi - (fi / NFP) * NFP;
+  const double dt = kp.scal[0];
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
+  if (d == 0) face_point2<Ph, N, 0>(kp, un_g, e, q, side, dt, pp);
+  else if constexpr (DIM == 2) face_point2<Ph, N, 1>(kp, un_g, e, q, side, dt, pp);
+}
+
+#ifndef FACES2_WAVES_PER_EU
+#define FACES2_WAVES_PER_EU 1
+#endif
+template <class Ph, int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES2_WAVES_PER_EU)))
+    k_faces2(const KParams kp, const double* __restrict__ un_g) {
+  faces2_body<Ph, N>(kp, un_g, blockIdx.x);
+}
+
 #ifndef FACES_WAVES_PER_EU
 #define FACES_WAVES_PER_EU 1
 #endif

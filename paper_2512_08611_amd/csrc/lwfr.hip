@@ -181,7 +181,10 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
                 dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
   }
   const int nfp_total = DIM * E * NFP;
-  LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
+  if constexpr (face_lanes<Ph>() == 2)
+    LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces2<Ph, N>), dim3((nfp_total + 127) / 128), dim3(256), 0, s, kp, u_in);
+  else
+    LWFR_LAUNCH(KID_FACES, "k_faces", (k_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp, u_in);
   if (c->bface_threads > 0)
     LWFR_LAUNCH(KID_BFACES, "k_bfaces", (k_bfaces<Ph, N>), dim3((c->bface_threads + 63) / 64), dim3(64), 0, s, kp,
                 u_in);
