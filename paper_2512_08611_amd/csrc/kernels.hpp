@@ -1761,34 +1761,28 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
     for (int v = 0; v < M; ++v) io[((size_t)v * kp.E + e) * P + p] = us[v];
   }
+  // Algorithm 1 activity on the element's faces: the element's threads read
+  // face points w = (side, d, q) (its right faces, then its left faces, whose
+  // slot is the left neighbour's, or a boundary half face)
+  for (int w = p; kp.blending == 2 && w < 2 * DIM * NFP; w += P) {
+    const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
+    const int ef = side ? (d == 0 ? eL[0] : eL[DIM - 1]) : es;
+    const size_t fo = (size_t)d * nf + (size_t)ef * NFP + q;
+    double th = kp.theta_face[fo];
+    uint32_t gu = kp.guard_face[fo];
+    if (side && on_boundary(kp, es, d, 0)) {  // a boundary half face
+      const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + (size_t)(d == 0 ? es / kp.nx : es % kp.nx) * NFP + q;
+      th = kp.theta_left[bl];
+      gu = kp.guard_left[bl];
+    }
+    fl |= (th < 1.0 ? 4u : 0u) | (gu ? 16u : 0u);
+  }
   s_fl[le][p] = fl;
   __syncthreads();
   if (act && p == 0) {
     uint32_t f = 0;
 #pragma unroll
     for (int r = 0; r < P; ++r) f |= s_fl[le][r];
-    // Algorithm 1 activity on the element's faces
-    if (kp.blending == 2) {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d)
-#pragma unroll
-        for (int q = 0; q < NFP; ++q) {
-          const size_t fu = (size_t)d * nf + (size_t)e * NFP + q;
-          const size_t fd = (size_t)d * nf + (size_t)eL[d] * NFP + q;
-          // both faces loaded unconditionally (no short-circuit between the loads)
-          const double tu = kp.theta_face[fu];
-          double td = kp.theta_face[fd];
-          const uint32_t gu = kp.guard_face[fu];
-          uint32_t gd = kp.guard_face[fd];
-          if (on_boundary(kp, e, d, 0)) {  // the left face is a boundary half face
-            const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + (size_t)(d == 0 ? e / kp.nx : e % kp.nx) * NFP + q;
-            td = kp.theta_left[bl];
-            gd = kp.guard_left[bl];
-          }
-          f |= ((tu < 1.0) | (td < 1.0)) ? 4u : 0u;
-          f |= (gu | gd) ? 16u : 0u;
-        }
-    }
     if (d_flags) d_flags[e] = f;
     if (f & 10u) atomicOr(kp.flag_or, f);
   }
