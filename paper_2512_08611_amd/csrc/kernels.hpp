@@ -122,7 +122,8 @@ template <class Ph, int N, int NT>
 struct PreLds {
   static constexpr int P = ipow(N + 1, Ph::DIM), EL = (NT + P - 1) / P;
   double s_u[EL][Ph::M][P];
-  double s_q[EL][P];
+  double s_q[EL][P];   // indicator variable at the nodes, then the squared modes
+  double s_t[EL][P];   // 2-D: the first pass of the modal projection
   double s_ub[EL][Ph::M];
   double s_lam[EL];
 };
@@ -133,6 +134,7 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
   auto& s_u = L.s_u;
   auto& s_q = L.s_q;
+  auto& s_t = L.s_t;
   auto& s_ub = L.s_ub;
   auto& s_lam = L.s_lam;
   const int tid = threadIdx.x;
@@ -161,6 +163,32 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
     }
     s_ub[le][v] = s;
   }
+  // smoothness indicator, part 1: the modes of q in the orthonormal Legendre
+  // basis, one thread per mode (1-D: m_k = sum_r w_r L_k(xi_r) q_r; 2-D in two
+  // passes, t[k][jj] = sum_i w_i L_k(xi_i) q(i, jj), then
+  // m[l][k] = sum_jj w_jj L_l(xi_jj) t[k][jj]); squared modes replace q in s_q
+  double mode = 0.0;
+  if (want_alpha) {
+    if constexpr (DIM == 1) {
+#pragma unroll
+      for (int r = 0; r < n1; ++r) mode += kp.w[r] * s_q[le][r] * kp.Leg[p][r];
+    } else {
+      const int k = p % n1, jj = p / n1;
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < n1; ++i) t += kp.w[i] * kp.Leg[k][i] * s_q[le][i + n1 * jj];
+      s_t[le][p] = t;
+    }
+  }
+  __syncthreads();
+  if (want_alpha) {
+    if constexpr (DIM == 2) {
+      const int k = p % n1, l = p / n1;
+#pragma unroll
+      for (int jj = 0; jj < n1; ++jj) mode += kp.w[jj] * kp.Leg[l][jj] * s_t[le][k + n1 * jj];
+    }
+    s_q[le][p] = mode * mode;
+  }
   __syncthreads();
   if (p == 0) {
     double lam = 0.0;
@@ -182,44 +210,16 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
     }
     s_lam[le] = lam;
   } else if (p == 1 % P && want_alpha && act) {
-    // smoothness indicator: energy fractions of the highest modes of q in the
-    // orthonormal Legendre basis, logistic map, clip and cap
+    // smoothness indicator, part 2: energy fractions of the highest modes,
+    // logistic map, clip and cap (mode (l, k) of degree max(k, l) at slot k + n1 l)
     double tot = 0.0, c1 = 0.0, c2 = 0.0;
-    if constexpr (DIM == 1) {
 #pragma unroll
-      for (int k = 0; k < n1; ++k) {
-        double m = 0.0;
-#pragma unroll
-        for (int r = 0; r < n1; ++r) m += kp.w[r] * s_q[le][r] * kp.Leg[k][r];
-        const double m2 = m * m;
-        tot += m2;
-        if (k <= N - 1) c1 += m2;
-        if (k <= N - 2) c2 += m2;
-      }
-    } else {
-      double t[n1][n1];  // t[k][jj] = sum_i w_i L_k(xi_i) q(i, jj)
-#pragma unroll
-      for (int k = 0; k < n1; ++k)
-#pragma unroll
-        for (int jj = 0; jj < n1; ++jj) {
-          double s = 0.0;
-#pragma unroll
-          for (int i = 0; i < n1; ++i) s += kp.w[i] * kp.Leg[k][i] * s_q[le][i + n1 * jj];
-          t[k][jj] = s;
-        }
-#pragma unroll
-      for (int l = 0; l < n1; ++l)
-#pragma unroll
-        for (int k = 0; k < n1; ++k) {
-          double m = 0.0;
-#pragma unroll
-          for (int jj = 0; jj < n1; ++jj) m += kp.w[jj] * kp.Leg[l][jj] * t[k][jj];
-          const double m2 = m * m;
-          const int deg = k > l ? k : l;
-          tot += m2;
-          if (deg <= N - 1) c1 += m2;
-          if (deg <= N - 2) c2 += m2;
-        }
+    for (int r = 0; r < P; ++r) {
+      const double m2 = s_q[le][r];
+      const int deg = DIM == 1 ? r : (r % n1 > r / n1 ? r % n1 : r / n1);
+      tot += m2;
+      if (deg <= N - 1) c1 += m2;
+      if (deg <= N - 2) c2 += m2;
     }
     double En = tot > 0.0 ? (tot - c1) / tot : 0.0;
     if (N >= 2) {
