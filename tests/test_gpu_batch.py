@@ -189,6 +189,50 @@ def test_single_problem_graph_matches_eager(stream):
         assert torch.equal(hist, dtch), rep
 
 
+@pytest.mark.parametrize("case", ["mhd4", "sw1d", "jinxin", "sw2d_walls"])
+def test_single_problem_graph_matches_eager_more(stream, case):
+    """Captured sequences form each step's element data in the previous step's update
+    (no k_pre after the first step): bit-identical to eager steps, which run k_pre."""
+    if case == "mhd4":
+        cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 4, (9, 7), blending=2)
+        gen = lambda xi: W.mhd_blocky(xi, 9, 7, 5, nblocks=4)
+    elif case == "sw1d":
+        cfg = lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 37, blending=2)
+        gen = lambda xi: W.sw1d_wave(xi, 37, 2)
+    elif case == "jinxin":
+        cfg = lwfr.make_config(lwfr.LWFR_EQ_JINXIN1D, 2, 41, lo=(-1.0, 0.0), blending=2,
+                               flags=lwfr.LWFR_CFG_IMEX_SSP3, source=(3.0, 1e-3, 0.0, 1.0))
+        gen = lambda xi: W.jinxin_sine(xi, 41)
+    else:
+        cfg = lwfr.make_config(lwfr.LWFR_EQ_SW2D, 3, (8, 8), blending=2, bc=(2, 2, 2, 2))
+        gen = lambda xi: sw2d_state(xi, 8, 4)
+    st = lwfr.Stepper(cfg, DEV, stream=stream)
+    u0 = torch.tensor(gen(np.array(st.xi)), dtype=torch.float64, device=DEV)
+    nsteps = 5
+    ua, ub = u0.clone(), torch.empty_like(u0)
+    dtch = torch.zeros((nsteps, 2), dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    for k in range(nsteps):
+        st.step(ua, ub, 0.0, dtch[k])
+        ua, ub = ub, ua
+    torch.cuda.synchronize()
+    ga, gb = u0.clone(), torch.empty_like(u0)
+    hist = torch.zeros((nsteps, 2), dtype=torch.float64, device=DEV)
+    st.graph_capture(ga, gb, nsteps, hist)
+    for rep in range(2):
+        ga.copy_(u0)
+        torch.cuda.synchronize()
+        st.graph_launch()
+        torch.cuda.synchronize()
+        got = ga if nsteps % 2 == 0 else gb
+        assert torch.equal(got, ua), rep
+        assert torch.equal(hist, dtch), rep
+    # eager work after the replays still sees consistent element data
+    st.step(u0, ub, 0.0, dtch[0])
+    torch.cuda.synchronize()
+    assert st.query()[0] == lwfr.LWFR_OK
+
+
 def test_graph_needs_a_stream():
     cfg = lwfr.make_config(lwfr.LWFR_EQ_SW2D, 2, (3, 3))
     b = lwfr.Batch([cfg], DEV, stream=torch.cuda.default_stream(DEV))
