@@ -349,6 +349,28 @@ def main():
         "algorithmic_flops_per_launch": flops * dofs if flops else None,
         "dominant_kernel_by_time": dom,
     }
+    # every kernel of the step against both rooflines: HBM bytes and hardware FP64
+    # operations per launch from the committed counter summary (while it matches
+    # the sources), durations measured live above
+    by_kernel = None
+    if (n, N) == (256, 4):
+        table = counters.read_table(os.path.join(ROOT, "profiles", "counters_mhd256_n4.md"))
+        if table:
+            by_kernel = {}
+            for name, row in table.items():
+                base = name.split("<")[0]
+                key = next((k for k in per_kernel if base == k or base.startswith(k + "2")), None)
+                if key is None or not per_kernel[key]["ms_per_launch"]:
+                    continue
+                sec = per_kernel[key]["ms_per_launch"] * 1e-3
+                ent = {"counted_kernel": name, "ms_per_launch": per_kernel[key]["ms_per_launch"]}
+                if "bytes" in row:
+                    gbs = row["bytes"] / sec / 1e9
+                    ent.update(hbm_bytes=row["bytes"], hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+                if "fp64_ops" in row:
+                    tf = row["fp64_ops"] / sec / 1e12
+                    ent.update(fp64_hw_ops=row["fp64_ops"], fp64_TFLOPs=tf, fp64_frac=tf / FP64_VECTOR_PEAK_TFLOPS)
+                by_kernel[key] = ent
     out = {
         "metric": METRIC,
         "value": value,
@@ -371,6 +393,7 @@ def main():
             "dof": dofs,
         },
         "roofline": roofline,
+        "rooflines_by_kernel": by_kernel,
         "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in per_kernel.items()},
         "step_status": int(status),
         "flags_or": int(flags),

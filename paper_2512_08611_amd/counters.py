@@ -6,6 +6,10 @@ bytes per launch from two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
 dispatch).  Each counter is scaled by what it reads for a plain device copy of
 known size in the same run (the copy bench.py --copy-calibration issues), so
 bytes = FETCH_SIZE * 1024 * copied/FETCH_SIZE(copy) and likewise for writes.
+An optional third counter run (SQ_INSTS_VALU_FMA_F64, _ADD_F64, _MUL_F64,
+_TRANS_F64: wave instructions per dispatch) gives the hardware FP64 operations
+per launch, (2 FMA + ADD + MUL) * 64 lanes, with the transcendental ones
+(square roots, reciprocals) listed beside.
 
 The summary carries a digest of the kernel sources (csrc/*, include/lwfr.h);
 bench.py reports the measured traffic only while the digest matches the
@@ -62,9 +66,12 @@ def _copy_factor(vals, copy_bytes):
     return copy_bytes / kib
 
 
-def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match):
-    """{kernel: {mean_us, calls, fetch_bytes, write_bytes}} for kernels whose name contains `match`,
-    and the two calibration factors."""
+FP64_COUNTERS = ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")
+
+
+def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match, fp64_csv=None):
+    """{kernel: {mean_us, calls, fetch_bytes, write_bytes[, fp64_ops, fp64_trans]}} for kernels whose
+    name contains `match`, and the two calibration factors."""
     out = {}
     for r in csv.DictReader(open(stats_csv)):
         k = _short(r["Name"])
@@ -79,6 +86,18 @@ def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match):
         w = [v for _, v in wv.get(k, [])]
         out[k]["fetch_bytes"] = ff * sum(f) / len(f) if f else None
         out[k]["write_bytes"] = fw * sum(w) / len(w) if w else None
+    if fp64_csv:
+        cm = {c: _counter_means(fp64_csv, c) for c in FP64_COUNTERS}
+
+        def mean(c, k):
+            vals = [v for _, v in cm[c].get(k, [])]
+            return sum(vals) / len(vals) if vals else None
+
+        for k in out:
+            fma, add, mul, tr = (mean(c, k) for c in FP64_COUNTERS)
+            if None not in (fma, add, mul):
+                out[k]["fp64_ops"] = (2 * fma + add + mul) * 64
+                out[k]["fp64_trans"] = (tr or 0.0) * 64
     return out, ff, fw
 
 
@@ -87,16 +106,25 @@ def write_md(path, title, summary, ff, fw, commands, digest):
     lines += ["```"] + list(commands) + ["```", ""]
     lines += [f"Calibration (256 MiB device copy in the same runs): FETCH_SIZE x {ff / 1024:.3f} KiB, "
               f"WRITE_SIZE x {fw / 1024:.3f} KiB per counted KiB.", ""]
-    lines += ["| kernel | calls | mean (us) | HBM read (MB/launch) | HBM write (MB/launch) | GB/s |", "|---|---|---|---|---|---|"]
+    lines += ["| kernel | calls | mean (us) | HBM read (MB/launch) | HBM write (MB/launch) | GB/s | % of 8 TB/s | "
+              "FP64 hw ops (G/launch) | TFLOP/s | % of 78.6 |", "|---|---|---|---|---|---|---|---|---|---|"]
     for k, v in sorted(summary.items(), key=lambda kv: -kv[1]["mean_us"] * kv[1]["calls"]):
         rd = v["fetch_bytes"] or 0.0
         wr = v["write_bytes"] or 0.0
         bw = (rd + wr) / (v["mean_us"] * 1e-6) / 1e9 if v["mean_us"] else 0.0
-        lines.append(f"| `{k}` | {v['calls']} | {v['mean_us']:.1f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {bw:.0f} |")
-    lines += ["", f"kernel sources sha256: {digest}", ""]
+        ops = v.get("fp64_ops")
+        fl = ops / (v["mean_us"] * 1e-6) / 1e12 if ops is not None and v["mean_us"] else None
+        fcols = f"{ops / 1e9:.2f} | {fl:.1f} | {100 * fl / 78.6:.1f}" if fl is not None else "- | - | -"
+        lines.append(f"| `{k}` | {v['calls']} | {v['mean_us']:.1f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {bw:.0f} | "
+                     f"{100 * bw / 8000:.1f} | {fcols} |")
+    lines += ["", "FP64 hw ops = (2 FMA + ADD + MUL) x 64 lanes from the SQ_INSTS_VALU_*_F64 counters "
+              "(transcendental instructions not counted).", ""]
+    lines += [f"kernel sources sha256: {digest}", ""]
     for k, v in sorted(summary.items()):
         if v["fetch_bytes"] is not None and v["write_bytes"] is not None:
             lines.append(f"traffic_bytes {k} {v['fetch_bytes'] + v['write_bytes']:.0f} mean_us {v['mean_us']:.3f}")
+        if v.get("fp64_ops") is not None:
+            lines.append(f"fp64_ops {k} {v['fp64_ops']:.0f} trans {v['fp64_trans']:.0f}")
     open(path, "w").write("\n".join(lines) + "\n")
 
 
@@ -119,18 +147,40 @@ def read_traffic(path, kernel_prefix, digest=None):
     return None, None
 
 
+def read_table(path, digest=None):
+    """{kernel name: {"bytes": HBM bytes per launch, "mean_us": ..., "fp64_ops": ...}} from a
+    summary, or {} if it is missing or its source digest differs from the sources."""
+    if not os.path.exists(path):
+        return {}
+    text = open(path).read()
+    m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != (digest or sources_digest()):
+        return {}
+    out = {}
+    for line in text.splitlines():
+        parts = line.split()
+        if line.startswith("traffic_bytes "):
+            name = " ".join(parts[1:-3])
+            out.setdefault(name, {}).update(bytes=float(parts[-3]), mean_us=float(parts[-1]))
+        elif line.startswith("fp64_ops "):
+            name = " ".join(parts[1:-3])
+            out.setdefault(name, {}).update(fp64_ops=float(parts[-3]), fp64_trans=float(parts[-1]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--stats", required=True, help="rocprofv3 --stats kernel_stats.csv")
     ap.add_argument("--fetch", required=True, help="counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write", required=True, help="counter_collection.csv of the WRITE_SIZE run")
+    ap.add_argument("--fp64", default=None, help="counter_collection.csv of the SQ_INSTS_VALU_*_F64 run")
     ap.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
     ap.add_argument("--match", default="MHD2D")
     ap.add_argument("--title", default="Kernel durations and HBM traffic")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    s, ff, fw = summarize(a.stats, a.fetch, a.write, a.copy_bytes, a.match)
+    s, ff, fw = summarize(a.stats, a.fetch, a.write, a.copy_bytes, a.match, a.fp64)
     write_md(a.out, a.title, s, ff, fw, a.command, sources_digest())
 
 
