@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 
   const int tid = threadIdx.x;
   const int le = tid / P, p = tid - le * P;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
@@ -298,7 +298,7 @@ template <class Ph, int N>
 __global__ void __launch_bounds__(256) k_adj_faces(const KParams kp, const AdjParams ap, const double* __restrict__ un_g) {
   constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
   const int nf = kp.E * NFP;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (gid >= DIM * nf) return;
   const int d = gid / nf;
   const int fi = gid - d * nf;
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 
   const int tid = threadIdx.x;
   const int le = tid / P, p = tid - le * P;
-  const int e = blockIdx.x * EPB + le;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = e < kp.E;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];

@@ -25,6 +25,23 @@ namespace lwfr {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// Workgroups of a launch go to the eight XCDs in turn, and each XCD has its own
+// L2.  Neighbouring workgroups share cache lines at their edges (the face data of
+// adjacent elements, the node rows either side of a y face), so the block index a
+// kernel works on is permuted to give each XCD one contiguous run of blocks, in
+// order: XCD x takes the blocks [x*per + min(x, rem), ...) of the launch.  A
+// bijection of [0, nb) for any nb.
+#ifndef LWFR_XCD_REMAP
+#define LWFR_XCD_REMAP 1
+#endif
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  if (!LWFR_XCD_REMAP) return b;
+  const int per = nb / kXcds, rem = nb - per * kXcds;
+  const int x = b % kXcds, i = b / kXcds;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 #ifndef STAGES_WAVES_PER_EU
 #define STAGES_WAVES_PER_EU 1
 #endif
@@ -244,7 +261,8 @@ template <class Ph, int N, int EPB>
 __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams kp, const double* __restrict__ un) {
   constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
   __shared__ PreLds<Ph, N, NT> L;
-  pre_body<Ph, N, EPB, NT>(kp, L, un, blockIdx.x, kp.part + blockIdx.x);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  pre_body<Ph, N, EPB, NT>(kp, L, un, b, kp.part + b);
 }
 
 // k_dt: one block of 1024 threads; Lambda and dt
@@ -731,7 +749,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
     k_stages_alw(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
   constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
   __shared__ StagesLds<Ph, N, NT> L;
-  alw_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
+  alw_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ------------------------------------------------------------------------
@@ -994,7 +1012,7 @@ __global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((
     k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
   constexpr int NT = stage_threads<Ph, N, EPB>();
   __shared__ StageLdsT<Ph, N, NT> L;
-  stage_body<Ph, N, EPB, NT, Tab>(kp, L, un_g, rvol_g, d_alpha_out, blockIdx.x);
+  stage_body<Ph, N, EPB, NT, Tab>(kp, L, un_g, rvol_g, d_alpha_out, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ------------------------------------------------------------------------
@@ -1056,6 +1074,15 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
     sL[v] = node(v, e, N);
     sR[v] = node(v, en, 0);
   }
+  // the next nodes inward (Algorithm 1) share those cache lines: read them now
+  double sLi[M], sRi[M];
+  if (kp.blending == 2 && N >= 1) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      sLi[v] = node(v, e, N - 1);
+      sRi[v] = node(v, en, 1);
+    }
+  }
   double Fm[M], Fp[M], Cm[M], Cp[M];
   {
     double a[M], b[M], UL[M], UR[M];
@@ -1109,12 +1136,6 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
       // next to the face
       double finL[M], finR[M];
       {
-        double sLi[M], sRi[M];
-#pragma unroll
-        for (int v = 0; v < M; ++v) {
-          sLi[v] = node(v, e, N - 1);
-          sRi[v] = node(v, en, 1);
-        }
         low_flux<Ph, d>(sLi, sL, nullptr, finL, pp);
         low_flux<Ph, d>(sR, sRi, finR, nullptr, pp);
       }
@@ -1208,6 +1229,13 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
   double s[M];
 #pragma unroll
   for (int v = 0; v < M; ++v) s[v] = node(v, side ? 0 : N);
+  // the next node inward (Algorithm 1) shares s's cache lines: read it now, while
+  // they are still in L2, rather than after the face flux
+  double si[M];
+  if (kp.blending == 2 && N >= 1) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) si[v] = node(v, side ? 1 : N - 1);
+  }
   double F[M], C[M];
   {
     double a[M], U[M];
@@ -1267,9 +1295,6 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
       // Algorithm 1: the lane's subcell next to the face, DIM*dt in its update
       double fin[M];
       {
-        double si[M];
-#pragma unroll
-        for (int v = 0; v < M; ++v) si[v] = node(v, side ? 1 : N - 1);
         if (side) low_flux<Ph, d>(s, si, fin, nullptr, pp);  // f^{e+1,-}_{1/2}
         else low_flux<Ph, d>(si, s, nullptr, fin, pp);       // f^{e,+}_{N-1/2}
       }
@@ -1336,7 +1361,7 @@ __device__ __forceinline__ void faces2_body(const KParams& kp, const double* __r
 template <class Ph, int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES2_WAVES_PER_EU)))
     k_faces2(const KParams kp, const double* __restrict__ un_g) {
-  faces2_body<Ph, N>(kp, un_g, blockIdx.x);
+  faces2_body<Ph, N>(kp, un_g, xcd_block(blockIdx.x, gridDim.x));
 }
 
 #ifndef FACES_WAVES_PER_EU
@@ -1347,7 +1372,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES2
 template <class Ph, int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES_WAVES_PER_EU)))
     k_faces(const KParams kp, const double* __restrict__ un_g) {
-  faces_body<Ph, N>(kp, un_g, blockIdx.x * blockDim.x + threadIdx.x);
+  faces_body<Ph, N>(kp, un_g, xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1793,7 +1818,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
     k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
   constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
   __shared__ UpdateLds<Ph, N, NT> L;
-  update_body<Ph, N, EPB, NT>(kp, L, un_g, io, d_flags, blockIdx.x);
+  update_body<Ph, N, EPB, NT>(kp, L, un_g, io, d_flags, xcd_block(blockIdx.x, gridDim.x));
 }
 
 __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ u, double* __restrict__ R, size_t n,
