@@ -9,7 +9,9 @@ bytes = FETCH_SIZE * 1024 * copied/FETCH_SIZE(copy) and likewise for writes.
 An optional third counter run (SQ_INSTS_VALU_FMA_F64, _ADD_F64, _MUL_F64,
 _TRANS_F64: wave instructions per dispatch) gives the hardware FP64 operations
 per launch, (2 FMA + ADD + MUL) * 64 lanes, with the transcendental ones
-(square roots, reciprocals) listed beside.
+(square roots, reciprocals) listed beside.  An optional fourth run counts the
+L2-to-fabric read requests by size (TCC_EA0_RDREQ_32B/_64B/_128B): their bytes
+need no calibration and check the scaled FETCH_SIZE kernel by kernel.
 
 The summary carries a digest of the kernel sources (csrc/*, include/lwfr.h);
 bench.py reports the measured traffic only while the digest matches the
@@ -66,12 +68,13 @@ def _copy_factor(vals, copy_bytes):
     return copy_bytes / kib
 
 
+RDREQ_COUNTERS = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64), ("TCC_EA0_RDREQ_128B_sum", 128))
 FP64_COUNTERS = ("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64")
 
 
-def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match, fp64_csv=None):
-    """{kernel: {mean_us, calls, fetch_bytes, write_bytes[, fp64_ops, fp64_trans]}} for kernels whose
-    name contains `match`, and the two calibration factors."""
+def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match, fp64_csv=None, rdreq_csv=None):
+    """{kernel: {mean_us, calls, fetch_bytes, write_bytes[, fp64_ops, fp64_trans][, read_bytes_req]}}
+    for kernels whose name contains `match`, and the two calibration factors."""
     out = {}
     for r in csv.DictReader(open(stats_csv)):
         k = _short(r["Name"])
@@ -98,6 +101,17 @@ def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match, fp64_csv=None)
             if None not in (fma, add, mul):
                 out[k]["fp64_ops"] = (2 * fma + add + mul) * 64
                 out[k]["fp64_trans"] = (tr or 0.0) * 64
+    if rdreq_csv:
+        rm = {c: _counter_means(rdreq_csv, c) for c, _ in RDREQ_COUNTERS}
+        for k in out:
+            tot = 0.0
+            for c, size in RDREQ_COUNTERS:
+                vals = [v for _, v in rm[c].get(k, [])]
+                if not vals:
+                    break
+                tot += size * sum(vals) / len(vals)
+            else:
+                out[k]["read_bytes_req"] = tot
     return out, ff, fw
 
 
@@ -119,6 +133,12 @@ def write_md(path, title, summary, ff, fw, commands, digest):
                      f"{100 * bw / 8000:.1f} | {fcols} |")
     lines += ["", "FP64 hw ops = (2 FMA + ADD + MUL) x 64 lanes from the SQ_INSTS_VALU_*_F64 counters "
               "(transcendental instructions not counted).", ""]
+    req = [(k, v) for k, v in sorted(summary.items()) if v.get("read_bytes_req") and v["fetch_bytes"]]
+    if req:
+        lines += ["Read bytes from the request-size counters (no calibration) against the scaled FETCH_SIZE:", ""]
+        lines += [f"- `{k}`: {v['read_bytes_req'] / 1e6:.1f} MB by request counts, {v['fetch_bytes'] / 1e6:.1f} MB "
+                  f"by FETCH_SIZE (ratio {v['read_bytes_req'] / v['fetch_bytes']:.4f})" for k, v in req]
+        lines += [""]
     lines += [f"kernel sources sha256: {digest}", ""]
     for k, v in sorted(summary.items()):
         if v["fetch_bytes"] is not None and v["write_bytes"] is not None:
@@ -174,13 +194,14 @@ def main():
     ap.add_argument("--fetch", required=True, help="counter_collection.csv of the FETCH_SIZE run")
     ap.add_argument("--write", required=True, help="counter_collection.csv of the WRITE_SIZE run")
     ap.add_argument("--fp64", default=None, help="counter_collection.csv of the SQ_INSTS_VALU_*_F64 run")
+    ap.add_argument("--rdreq", default=None, help="counter_collection.csv of the TCC_EA0_RDREQ_{32B,64B,128B} run")
     ap.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
     ap.add_argument("--match", default="MHD2D")
     ap.add_argument("--title", default="Kernel durations and HBM traffic")
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    s, ff, fw = summarize(a.stats, a.fetch, a.write, a.copy_bytes, a.match, a.fp64)
+    s, ff, fw = summarize(a.stats, a.fetch, a.write, a.copy_bytes, a.match, a.fp64, a.rdreq)
     write_md(a.out, a.title, s, ff, fw, a.command, sources_digest())
 
 
