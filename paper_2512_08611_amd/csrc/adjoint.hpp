@@ -532,4 +532,288 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   }
 }
 
+// ---- the same reverse sweep with two lanes per solution point (GLM-MHD).
+// As in the forward two-lane stage kernel, the lanes of a point sit in the two
+// halves of one wave: lane d works on direction d (its flux and
+// non-conservative VJPs and D_d^T contractions, in the frame where direction d
+// is x, see MHD2D::rot) and owns half of the variables' sums (stage sums, the
+// adjoint sums Q_k, lambda^n).  The stage states are recomputed with the forward
+// kernel's arithmetic, so they equal the forward step's bit for bit.
+template <class Ph, int N, int NT>
+struct AdjStages2Lds {
+  static constexpr int M = Ph::M, P = ipow(N + 1, 2), EL = (NT / 2 + P - 1) / P, NCD = Ph::NCD;
+  static constexpr int S = Tableau<N>::S;
+  // fields of an element slot: the S stage states (st*M + v), then the
+  // exchange fields at XB: forward f_x, f_y, the non-conservative columns of
+  // both directions; reverse Lb (M), the column adjoints of both directions
+  static constexpr int XB = S * M;
+  static constexpr int NF = XB + 2 * M + 2 * NCD;
+  // slot stride = P (mod 32): a half-wave's points stay consecutive in bank order
+  static constexpr int ES = NF * P + (((P - NF * P) % 32) + 32) % 32;
+  double s[EL][ES];
+};
+
+// elements per two-lane adjoint stage workgroup of 256 threads
+constexpr int epb_adj2(int P) { return 128 / P; }
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjParams& ap, AdjStages2Lds<Ph, N, NT>& L,
+                                                 const double* __restrict__ un_g, double* __restrict__ lam_out,
+                                                 int blk) {
+  static_assert(std::is_same<Ph, MHD2D>::value, "two-lane adjoint stage body is written for GLM-MHD");
+  constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NFP = n1, NCD = Ph::NCD;
+  constexpr int H0 = (M + 1) / 2, H1 = M - H0;
+  using Tab = Tableau<N>;
+  constexpr int S = Tab::S, XB = AdjStages2Lds<Ph, N, NT>::XB;
+  static_assert(2 * EPB * P <= NT, "workgroup too small for EPB elements");
+  auto& sb = L.s;
+
+  const int tid = threadIdx.x;
+  const int d = (tid >> 5) & 1, np = ((tid >> 6) << 5) | (tid & 31);
+  const int le = np / P, p = np - le * P;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
+  const int ea = act ? e : 0;  // lanes without an element read element 0
+  const int i = p % n1, j = p / n1;
+  const int q = d ? i : j;            // line of the lane's direction through p
+  const int ii = d ? j : i;           // position along that line
+  const int sq = d ? 1 : n1, sr = d ? n1 : 1;  // node(q, r) = q*sq + r*sr
+  const int vo = d ? H0 : 0;          // first variable of the lane's half
+  const int nown = d ? H1 : H0;       // variables in the lane's half
+  const double dt = kp.scal[0];
+  const double idx = d ? kp.inv_dx[1] : kp.inv_dx[0];
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
+  const size_t nf = (size_t)kp.E * NFP;
+
+  double Drow[n1], Dcol[n1];
+#pragma unroll
+  for (int r = 0; r < n1; ++r) {
+    Drow[r] = kp.D[ii][r];
+    Dcol[r] = kp.D[r][ii];
+  }
+
+  // ---- forward recomputation of the stage states (the lane's half to LDS)
+  {
+    double uo[H0], Sp[S][H0];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      const int v = vo + (k < nown ? k : 0);
+      uo[k] = un_g[((size_t)v * kp.E + ea) * P + p];
+    }
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+      double uh[H0], u[M];
+#pragma unroll
+      for (int k = 0; k < H0; ++k) uh[k] = first_nz<N>(st) >= 0 ? uo[k] - dt * Sp[st][k] : uo[k];
+#pragma unroll
+      for (int k = 0; k < H0; ++k)
+        if (k < nown) sb[le][(st * M + vo + k) * P + p] = uh[k];
+      if (st == S - 1) break;
+#pragma unroll
+      for (int k = 0; k < H0; ++k) {
+        double a = uh[k], b = uh[k];
+        cross_pair(a, b);
+        u[k] = a;
+        if (k < H1) u[H0 + k] = b;
+      }
+      double f[M];
+      Ph::flux_rd(u, d, f, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v)
+        if (Ph::flux_nc_alias(v) < 0) sb[le][(XB + d * M + v) * P + p] = f[v];
+#pragma unroll
+      for (int c = 0; c < NCD; ++c) {
+        const double x0 = u[Ph::nc_comp(0, c)], x1 = u[Ph::nc_comp(1, c)];
+        sb[le][(XB + 2 * M + d * NCD + c) * P + p] = d ? x1 : x0;
+      }
+      __syncthreads();
+      double Ld[M];
+      {
+        double wc[NCD], nc[M];
+#pragma unroll
+        for (int c = 0; c < NCD; ++c) {
+          double sacc = 0.0;
+#pragma unroll
+          for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][(XB + 2 * M + d * NCD + c) * P + (q * sq + r * sr)];
+          wc[c] = sacc;
+        }
+        Ph::ncprod_rd(u, wc, d, nc, pp);
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          double sacc = 0.0;
+          if (Ph::flux_nc_alias(v) >= 0) {
+            sacc = pp.ch * wc[Ph::flux_nc_alias(v)];
+          } else {
+#pragma unroll
+            for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][(XB + d * M + v) * P + (q * sq + r * sr)];
+          }
+          Ld[v] = (sacc + nc[v]) * idx;
+        }
+      }
+      __syncthreads();
+      double Lh[H0];
+#pragma unroll
+      for (int k = 0; k < H0; ++k) {
+        double a = Ld[k], b = k < H1 ? Ld[H0 + k] : 0.0;
+        cross_pair(a, b);
+        Lh[k] = a + b;
+      }
+#pragma unroll
+      for (int t = st + 1; t < S; ++t) {
+        const double a = Tab::a(t, st);
+        if (a != 0.0) {
+#pragma unroll
+          for (int k = 0; k < H0; ++k) Sp[t][k] = first_nz<N>(t) == st ? a * Lh[k] : Sp[t][k] + a * Lh[k];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- adjoints arriving from the faces and the update
+  double gF[M], gU[H0], gR[H0], gun[H0];
+  {
+    // F_d traces of the lane's direction, all variables, in the lane's frame
+    const size_t fo = (size_t)ea * NFP + q;
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const size_t o1 = ((size_t)(d * 2 + 1) * M + v) * nf + fo;
+      const size_t o0 = ((size_t)(d * 2 + 0) * M + v) * nf + fo;
+      gF[v] = kp.VR[ii] * ap.gFtr[o1] + kp.VL[ii] * ap.gFtr[o0];
+    }
+    Ph::rot(d, gF);
+  }
+#pragma unroll
+  for (int k = 0; k < H0; ++k) {
+    const int v = vo + (k < nown ? k : 0);
+    gR[k] = ap.g_rvol[((size_t)v * kp.E + ea) * P + p];
+    gun[k] = ap.g_un[((size_t)v * kp.E + ea) * P + p];
+    gU[k] = 0.0;
+  }
+  // U and u^n traces of both directions, the lane's half of the variables
+#pragma unroll
+  for (int dd = 0; dd < 2; ++dd) {
+    const int qd = dd == 0 ? j : i, id = dd == 0 ? i : j;
+    const size_t fo = (size_t)ea * NFP + qd;
+    const int eLd = nbr_elem(kp, ea, dd, 0);
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      const int v = vo + (k < nown ? k : 0);
+      const size_t o1 = ((size_t)(dd * 2 + 1) * M + v) * nf + fo;
+      const size_t o0 = ((size_t)(dd * 2 + 0) * M + v) * nf + fo;
+      gU[k] += kp.VR[id] * ap.gUtr[o1] + kp.VL[id] * ap.gUtr[o0];
+      gun[k] += kp.VR[id] * ap.guntr[o1] + kp.VL[id] * ap.guntr[o0];
+      if (id == N) gun[k] += ap.gsL[((size_t)dd * M + v) * nf + fo];
+      if (id == 0) gun[k] += ap.gsR[((size_t)dd * M + v) * nf + (size_t)eLd * NFP + qd];
+    }
+  }
+
+  // ---- reverse sweep over the stages
+  double Q[S][H0];
+#pragma unroll
+  for (int st = S - 1; st >= 0; --st) {
+    const double bs = Tab::b(st);
+    bool anyq = false;
+#pragma unroll
+    for (int t = st + 1; t < S; ++t) anyq = anyq || (Tab::a(t, st) != 0.0);
+    // Lb = b_s gR - dt Q_s on the lane's half, to LDS; the full Lb at the point
+    // from the pair
+    double Ld[M];
+    {
+      double Lbh[H0];
+#pragma unroll
+      for (int k = 0; k < H0; ++k) Lbh[k] = bs * gR[k] - (anyq ? dt * Q[st][k] : 0.0);
+#pragma unroll
+      for (int k = 0; k < H0; ++k)
+        if (k < nown) sb[le][(XB + vo + k) * P + p] = Lbh[k];
+#pragma unroll
+      for (int k = 0; k < H0; ++k) {
+        double a = Lbh[k], b = Lbh[k];
+        cross_pair(a, b);
+        Ld[k] = a * idx;
+        if (k < H1) Ld[H0 + k] = b * idx;
+      }
+    }
+    Ph::rot(d, Ld);
+    // the stage state in the lane's frame and D_d of its non-conservative columns
+    double u[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) u[v] = sb[le][(st * M + v) * P + p];
+    Ph::rot(d, u);
+    double w[M], wb[M], ubd[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) { w[v] = 0.0; wb[v] = 0.0; ubd[v] = 0.0; }
+#pragma unroll
+    for (int c = 0; c < NCD; ++c) {
+      const int fld = st * M + (d ? Ph::nc_comp(1, c) : Ph::nc_comp(0, c));
+      double sacc = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][fld * P + (q * sq + r * sr)];
+      w[Ph::nc_comp(0, c)] = sacc;
+    }
+    // B_d(u)^T Lb/dx_d: its u part to ubd, its column part to LDS
+    Ph::template ncprod_vjp<0>(u, w, Ld, ubd, wb, pp);
+#pragma unroll
+    for (int c = 0; c < NCD; ++c) sb[le][(XB + M + d * NCD + c) * P + p] = wb[Ph::nc_comp(0, c)];
+    __syncthreads();
+    // f_d'(u)^T (b_s F_db + D_d^T Lb/dx_d) and D_d^T of the column adjoints
+    {
+      double fb[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) sacc += Dcol[r] * sb[le][(XB + v) * P + (q * sq + r * sr)];
+        fb[v] = sacc * idx;
+      }
+      Ph::rot(d, fb);
+#pragma unroll
+      for (int v = 0; v < M; ++v) fb[v] += bs * gF[v];
+      Ph::template flux_vjp<0>(u, fb, ubd, pp);
+    }
+#pragma unroll
+    for (int c = 0; c < NCD; ++c) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) sacc += Dcol[r] * sb[le][(XB + M + d * NCD + c) * P + (q * sq + r * sr)];
+      ubd[Ph::nc_comp(0, c)] += sacc;
+    }
+    __syncthreads();
+    Ph::rot(d, ubd);
+    // ub on the lane's half: b_s gU + the contributions of both directions
+    double ubh[H0];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      double a = ubd[k], b = k < H1 ? ubd[H0 + k] : 0.0;
+      cross_pair(a, b);
+      ubh[k] = bs * gU[k] + (a + b);
+    }
+#pragma unroll
+    for (int k = 0; k < H0; ++k) gun[k] += ubh[k];
+#pragma unroll
+    for (int kk = 0; kk < st; ++kk) {
+      const double a = Tab::a(st, kk);
+      if (a != 0.0) {
+        bool first = true;
+#pragma unroll
+        for (int t = st + 1; t < S; ++t) first = first && (Tab::a(t, kk) == 0.0);
+#pragma unroll
+        for (int k = 0; k < H0; ++k) Q[kk][k] = first ? a * ubh[k] : Q[kk][k] + a * ubh[k];
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < H0; ++k)
+      if (k < nown) lam_out[((size_t)(vo + k) * kp.E + e) * P + p] = gun[k];
+  }
+}
+
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(256)
+    k_adj_stages2(const KParams kp, const AdjParams ap, const double* __restrict__ un_g, double* __restrict__ lam_out) {
+  __shared__ AdjStages2Lds<Ph, N, 256> L;
+  adj_stages2_body<Ph, N, EPB, 256>(kp, ap, L, un_g, lam_out, xcd_block(blockIdx.x, gridDim.x));
+}
+
 }  // namespace lwfr

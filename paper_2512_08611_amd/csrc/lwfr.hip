@@ -193,6 +193,11 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   return LWFR_OK;
 }
 
+// GLM-MHD's adjoint stage sweep with two lanes per solution point
+#ifndef LWFR_ADJ_STAGES2
+#define LWFR_ADJ_STAGES2 1
+#endif
+
 // elements per workgroup of the adjoint kernels: about one wave
 template <int N>
 constexpr int epb_adj(int DIM) {
@@ -211,8 +216,14 @@ lwfr_status launch_adjoint(lwfr_ctx* c, const KParams& kp, const double* u_n, co
   const int nfp_total = DIM * E * NFP;
   LWFR_LAUNCH(KID_ADJ_FACES, "k_adj_faces", (k_adj_faces<Ph, N>), dim3((nfp_total + 255) / 256), dim3(256), 0, s, kp,
               c->ap, u_n);
-  LWFR_LAUNCH(KID_ADJ_STAGES, "k_adj_stages", (k_adj_stages<Ph, N, EPB>), dim3(nblk), dim3(EPB * P), 0, s, kp, c->ap,
-              u_n, lam0);
+  if constexpr (std::is_same<Ph, MHD2D>::value && LWFR_ADJ_STAGES2) {
+    constexpr int EPB2 = epb_adj2(P);
+    LWFR_LAUNCH(KID_ADJ_STAGES, "k_adj_stages", (k_adj_stages2<Ph, N, EPB2>), dim3((E + EPB2 - 1) / EPB2), dim3(256),
+                0, s, kp, c->ap, u_n, lam0);
+  } else {
+    LWFR_LAUNCH(KID_ADJ_STAGES, "k_adj_stages", (k_adj_stages<Ph, N, EPB>), dim3(nblk), dim3(EPB * P), 0, s, kp,
+                c->ap, u_n, lam0);
+  }
   return LWFR_OK;
 }
 

@@ -280,6 +280,18 @@ struct MHD2D {
     av = fabs(u[1 + d] / u[0]); c = cfast<d>(u, pp);
   }
 
+  // the components with x and y exchanged when d = 1 (an involution R, the
+  // identity for d = 0).  The system is invariant under that exchange:
+  // f_y(u) = R f_x(R u) and B_y(u) w = R B_x(R u) R w, so a lane working on
+  // direction 1 can run the direction-0 code in the exchanged frame
+  __device__ static void rot(int d, double* x) {
+    const double a = x[1], b = x[2], c = x[5], e = x[6];
+    x[1] = d ? b : a;
+    x[2] = d ? a : b;
+    x[5] = d ? e : c;
+    x[6] = d ? c : e;
+  }
+
   // ---- reverse mode (hand-written adjoints of flux, ncprod and sigma above)
   template <int d>
   __device__ static void flux_vjp(const double* u, const double* fb, double* ub, const PhysParams& pp) {
