@@ -818,7 +818,12 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
   const int i = p % n1, j = p / n1;
   const int q = d ? i : j;            // line of the lane's direction through p
   const int ii = d ? j : i;           // position along that line
-  const int sq = d ? 1 : n1, sr = d ? n1 : 1;  // node(q, r) = q*sq + r*sr
+  // exchange slots of the stage loop: the direction-1 lanes write their values
+  // transposed (point (i, j) at i*n1 + j), so that every lane reads its line at
+  // q*n1 + r with the offsets along the line known at compile time (paired LDS
+  // reads, no per-read address arithmetic)
+  const int pw = d ? i * n1 + j : p;
+  constexpr int sq = n1, sr = 1;
   const int vo = d ? H0 : 0;          // first variable of the lane's half
   const double dt = kp.scal[0];
   const double idx = d ? kp.inv_dx[1] : kp.inv_dx[0];
@@ -859,11 +864,11 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     Ph::flux_rd(u, d, f, pp);
 #pragma unroll
     for (int v = 0; v < M; ++v)
-      if (Ph::flux_nc_alias(v) < 0) s_buf[le][(d * M + v) * P + (p)] = f[v];
+      if (Ph::flux_nc_alias(v) < 0) s_buf[le][(d * M + v) * P + pw] = f[v];
 #pragma unroll
     for (int c = 0; c < NCD; ++c) {
       const double x0 = u[Ph::nc_comp(0, c)], x1 = u[Ph::nc_comp(1, c)];
-      s_buf[le][(2 * M + d * NCD + c) * P + (p)] = d ? x1 : x0;
+      s_buf[le][(2 * M + d * NCD + c) * P + pw] = d ? x1 : x0;
     }
     const double bs = Tab::b(st);
     if (bs != 0.0) {
