@@ -59,8 +59,13 @@ __device__ inline void low_flux_vjp(const double* uL, const double* uR, const do
 }
 
 // ------------------------------------------------------------------------
+// two waves per SIMD: GLM-MHD then spills about 8 VGPRs (36 bytes per lane),
+// which costs less than the second wave gains
+#ifndef ADJ_UPDATE_WAVES_PER_EU
+#define ADJ_UPDATE_WAVES_PER_EU 2
+#endif
 template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(ADJ_UPDATE_WAVES_PER_EU)))
     k_adj_update(const KParams kp, const AdjParams ap, const double* __restrict__ un_g,
                  const double* __restrict__ lam_g) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
@@ -72,6 +77,9 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   const int le = tid / P, p = tid - le * P;
   const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = e < kp.E;
+  // lanes without an element compute on element 0 and store nothing: the loads
+  // stay unconditional (a load under a lane condition waits for all loads)
+  const int ea = act ? e : 0;
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
   const PhysParams pp = phys_params(kp, kp.scal[1]);
@@ -80,8 +88,8 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   double un[M], lam[M], gH[M], gL[M], gun[M];
 #pragma unroll
   for (int v = 0; v < M; ++v) {
-    un[v] = act ? un_g[((size_t)v * kp.E + e) * P + p] : 1.0;
-    lam[v] = act ? lam_g[((size_t)v * kp.E + e) * P + p] : 0.0;
+    un[v] = un_g[((size_t)v * kp.E + ea) * P + p];
+    lam[v] = lam_g[((size_t)v * kp.E + ea) * P + p];
     s_u[le][v][p] = un[v];
   }
   // u^{n+1} = Theta us + (1 - Theta) uL,  us = (1 - alpha) uH + alpha uL
@@ -89,8 +97,8 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 #pragma unroll
     for (int v = 0; v < M; ++v) { gH[v] = lam[v]; gL[v] = 0.0; }
   } else {
-    const double al = act ? kp.alpha[e] : 0.0;
-    const double th = (kp.blending == 2 && act) ? kp.theta_elem[e] : 1.0;
+    const double al = kp.alpha[ea];
+    const double th = kp.blending == 2 ? kp.theta_elem[ea] : 1.0;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       const double gs = th * lam[v];
@@ -105,7 +113,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   }
   int eL[DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) eL[d] = act ? nbr_elem(kp, e, d, 0) : 0;
+  for (int d = 0; d < DIM; ++d) eL[d] = nbr_elem(kp, ea, d, 0);
   __syncthreads();
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -294,8 +302,12 @@ __device__ inline void adj_face_point(const KParams& kp, const AdjParams& ap, co
   }
 }
 
+// a two-wave hint spills about 430 VGPRs for GLM-MHD: one wave
+#ifndef ADJ_FACES_WAVES_PER_EU
+#define ADJ_FACES_WAVES_PER_EU 1
+#endif
 template <class Ph, int N>
-__global__ void __launch_bounds__(256) k_adj_faces(const KParams kp, const AdjParams ap, const double* __restrict__ un_g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ADJ_FACES_WAVES_PER_EU))) k_adj_faces(const KParams kp, const AdjParams ap, const double* __restrict__ un_g) {
   constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
   const int nf = kp.E * NFP;
   const int gid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -330,6 +342,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   const int le = tid / P, p = tid - le * P;
   const int e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool act = e < kp.E;
+  const int ea = act ? e : 0;  // lanes without an element read element 0
   const int i = p % n1, j = p / n1;
   const double dt = kp.scal[0];
   const PhysParams pp = phys_params(kp, kp.scal[1]);
@@ -337,7 +350,7 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
 
   double un[M];
 #pragma unroll
-  for (int v = 0; v < M; ++v) un[v] = act ? un_g[((size_t)v * kp.E + e) * P + p] : 1.0;
+  for (int v = 0; v < M; ++v) un[v] = un_g[((size_t)v * kp.E + ea) * P + p];
   double Drow[DIM][n1], Dcol[DIM][n1];
 #pragma unroll
   for (int r = 0; r < n1; ++r) {
@@ -415,19 +428,17 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   double gF[DIM][M], gU[M], gR[M], gun[M];
 #pragma unroll
   for (int v = 0; v < M; ++v) {
-    gR[v] = act ? ap.g_rvol[((size_t)v * kp.E + e) * P + p] : 0.0;
-    gun[v] = act ? ap.g_un[((size_t)v * kp.E + e) * P + p] : 0.0;
+    gR[v] = ap.g_rvol[((size_t)v * kp.E + ea) * P + p];
+    gun[v] = ap.g_un[((size_t)v * kp.E + ea) * P + p];
     gU[v] = 0.0;
   }
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
-    const size_t fo = (size_t)e * NFP + q;
-    const int eLd = act ? nbr_elem(kp, e, d, 0) : 0;
+    const size_t fo = (size_t)ea * NFP + q;
+    const int eLd = nbr_elem(kp, ea, d, 0);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      gF[d][v] = 0.0;
-      if (!act) continue;
       const size_t o1 = ((size_t)(d * 2 + 1) * M + v) * nf + fo;
       const size_t o0 = ((size_t)(d * 2 + 0) * M + v) * nf + fo;
       gF[d][v] = kp.VR[ii] * ap.gFtr[o1] + kp.VL[ii] * ap.gFtr[o0];
@@ -578,6 +589,10 @@ __device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjPar
   const int q = d ? i : j;            // line of the lane's direction through p
   const int ii = d ? j : i;           // position along that line
   const int sq = d ? 1 : n1, sr = d ? n1 : 1;  // node(q, r) = q*sq + r*sr
+  // fields only the lane's own direction reads (the forward exchange, the
+  // column adjoints) are written transposed by the direction-1 lanes and read
+  // at q*n1 + r, offsets known at compile time
+  const int pw = d ? i * n1 + j : p;
   const int vo = d ? H0 : 0;          // first variable of the lane's half
   const int nown = d ? H1 : H0;       // variables in the lane's half
   const double dt = kp.scal[0];
@@ -620,11 +635,11 @@ __device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjPar
       Ph::flux_rd(u, d, f, pp);
 #pragma unroll
       for (int v = 0; v < M; ++v)
-        if (Ph::flux_nc_alias(v) < 0) sb[le][(XB + d * M + v) * P + p] = f[v];
+        if (Ph::flux_nc_alias(v) < 0) sb[le][(XB + d * M + v) * P + pw] = f[v];
 #pragma unroll
       for (int c = 0; c < NCD; ++c) {
         const double x0 = u[Ph::nc_comp(0, c)], x1 = u[Ph::nc_comp(1, c)];
-        sb[le][(XB + 2 * M + d * NCD + c) * P + p] = d ? x1 : x0;
+        sb[le][(XB + 2 * M + d * NCD + c) * P + pw] = d ? x1 : x0;
       }
       __syncthreads();
       double Ld[M];
@@ -634,7 +649,7 @@ __device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjPar
         for (int c = 0; c < NCD; ++c) {
           double sacc = 0.0;
 #pragma unroll
-          for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][(XB + 2 * M + d * NCD + c) * P + (q * sq + r * sr)];
+          for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][(XB + 2 * M + d * NCD + c) * P + (q * n1 + r)];
           wc[c] = sacc;
         }
         Ph::ncprod_rd(u, wc, d, nc, pp);
@@ -645,7 +660,7 @@ __device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjPar
             sacc = pp.ch * wc[Ph::flux_nc_alias(v)];
           } else {
 #pragma unroll
-            for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][(XB + d * M + v) * P + (q * sq + r * sr)];
+            for (int r = 0; r < n1; ++r) sacc += Drow[r] * sb[le][(XB + d * M + v) * P + (q * n1 + r)];
           }
           Ld[v] = (sacc + nc[v]) * idx;
         }
@@ -754,7 +769,7 @@ __device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjPar
     // B_d(u)^T Lb/dx_d: its u part to ubd, its column part to LDS
     Ph::template ncprod_vjp<0>(u, w, Ld, ubd, wb, pp);
 #pragma unroll
-    for (int c = 0; c < NCD; ++c) sb[le][(XB + M + d * NCD + c) * P + p] = wb[Ph::nc_comp(0, c)];
+    for (int c = 0; c < NCD; ++c) sb[le][(XB + M + d * NCD + c) * P + pw] = wb[Ph::nc_comp(0, c)];
     __syncthreads();
     // f_d'(u)^T (b_s F_db + D_d^T Lb/dx_d) and D_d^T of the column adjoints
     {
@@ -775,7 +790,7 @@ __device__ __forceinline__ void adj_stages2_body(const KParams& kp, const AdjPar
     for (int c = 0; c < NCD; ++c) {
       double sacc = 0.0;
 #pragma unroll
-      for (int r = 0; r < n1; ++r) sacc += Dcol[r] * sb[le][(XB + M + d * NCD + c) * P + (q * sq + r * sr)];
+      for (int r = 0; r < n1; ++r) sacc += Dcol[r] * sb[le][(XB + M + d * NCD + c) * P + (q * n1 + r)];
       ubd[Ph::nc_comp(0, c)] += sacc;
     }
     __syncthreads();
