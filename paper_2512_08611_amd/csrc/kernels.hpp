@@ -664,6 +664,7 @@ __device__ __forceinline__ void alw_body(const KParams& kp, StagesLds<Ph, N, NT>
 #pragma unroll
   for (int k = 0; k <= N; ++k) {
     fact *= (k + 1);
+    const double ifact = 1.0 / fact;  // constants after unrolling: no division left
     double fk[DIM][M], hk[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) {
@@ -679,7 +680,7 @@ __device__ __forceinline__ void alw_body(const KParams& kp, StagesLds<Ph, N, NT>
       double st[M], tm[N + 1];
       tm[0] = 1.0;
 #pragma unroll
-      for (int m = 1; m <= k; ++m) tm[m] = tm[m - 1] * (jj * dt) / m;
+      for (int m = 1; m <= k; ++m) tm[m] = tm[m - 1] * (jj * dt) * (1.0 / m);
 #pragma unroll
       for (int v = 0; v < M; ++v) {
         double a = c[0][v];
@@ -727,16 +728,18 @@ __device__ __forceinline__ void alw_body(const KParams& kp, StagesLds<Ph, N, NT>
       r[v] = a;
     }
     __syncthreads();
+    const double uw = dtk * ifact;
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      Ua[v] += dtk / fact * c[k][v];
-      Ra[v] += r[v] / fact;
+      Ua[v] += uw * c[k][v];
+      Ra[v] += r[v] * ifact;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) Fa[d][v] += fk[d][v] / fact;
+      for (int d = 0; d < DIM; ++d) Fa[d][v] += fk[d][v] * ifact;
     }
     if (k < N) {
+      const double idtk = -1.0 / dtk;
 #pragma unroll
-      for (int v = 0; v < M; ++v) c[k + 1][v] = -r[v] / dtk;
+      for (int v = 0; v < M; ++v) c[k + 1][v] = r[v] * idtk;
       nc_derivs(k + 1);
       dtk *= dt;
     }
@@ -798,6 +801,79 @@ struct Stages2Lds {
   static constexpr int ES = NBUF * P + (((P - NBUF * P) % 32) + 32) % 32;
   double s_buf[EL][ES];
 };
+
+// outputs of the two-lane stage kernels: the volume residual (lane's half of
+// the variables), the face traces of F (lane's direction), U and u^n, and the
+// element's blending coefficient.  Fa holds the lane's direction for all
+// variables; Ua, Ra and uo the lane's half.
+template <class Ph, int N, int NT>
+__device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N, NT>& L, int le, int p, int d, int e,
+                                             bool act, const double* Fa, const double* Ua, const double* Ra,
+                                             const double* uo, double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NFP = n1;
+  constexpr int H0 = (M + 1) / 2, H1 = M - H0;
+  const int vo = d ? H0 : 0;
+  auto& s_buf = L.s_buf;
+  // time-averaged flux (lane's direction), solution and u^n (lane's half) to LDS
+#pragma unroll
+  for (int v = 0; v < M; ++v) s_buf[le][(d * M + v) * P + (p)] = Fa[v];
+#pragma unroll
+  for (int k = 0; k < H0; ++k)
+    if (k < (d ? H1 : H0)) {
+      s_buf[le][(2 * M + vo + k) * P + (p)] = Ua[k];
+      s_buf[le][(3 * M + vo + k) * P + (p)] = uo[k];
+    }
+  __syncthreads();
+
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < H0; ++k)
+      if (k < (d ? H1 : H0)) rvol_g[((size_t)(vo + k) * kp.E + e) * P + p] = Ra[k];
+    // face traces: (variable, face point) pairs of the element, variable
+    // slowest, over the element's 2P lanes
+    constexpr int NFT = 4 * NFP;
+    const int tl = 2 * p + d;
+    for (int w = tl; w < NFT * M; w += 2 * P) {
+      const int v = w / NFT, t = w - v * NFT;
+      const int dd = t / (2 * NFP);
+      const int rem = t - dd * 2 * NFP;
+      const int side = rem / NFP;
+      const int qq = rem - side * NFP;
+      const double* V = side ? kp.VR : kp.VL;
+      const size_t nf = (size_t)kp.E * NFP;
+      const size_t fo = (size_t)e * NFP + qq;
+      {
+        double tf = 0.0, tu = 0.0, tn = 0.0;
+#pragma unroll
+        for (int r = 0; r < n1; ++r) {
+          const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
+          tf += V[r] * s_buf[le][(dd * M + v) * P + (nd)];
+          tu += V[r] * s_buf[le][(2 * M + v) * P + (nd)];
+          tn += V[r] * s_buf[le][(3 * M + v) * P + (nd)];
+        }
+        const size_t o = ((size_t)(dd * 2 + side) * M + v) * nf + fo;
+        kp.Ftr[o] = tf;
+        kp.Utr[o] = tu;
+        kp.untr[o] = tn;
+      }
+    }
+    // blending coefficient of the element (smoothed over face neighbours)
+    if (p == 0 && d == 0) {
+      double a;
+      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
+      else if (kp.blending == 0) a = 0.0;
+      else {
+        a = kp.alpha_raw[e];
+#pragma unroll
+        for (int dn = 0; dn < 2; ++dn)
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, dn, sd)]);
+      }
+      kp.alpha[e] = a;
+      if (d_alpha_out) d_alpha_out[e] = a;
+    }
+  }
+}
 
 template <class Ph, int N, int EPB, int NT>
 __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N, NT>& L,
@@ -927,65 +1003,171 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     }
   }
 
-  // time-averaged flux (lane's direction), solution and u^n (lane's half) to LDS
-#pragma unroll
-  for (int v = 0; v < M; ++v) s_buf[le][(d * M + v) * P + (p)] = Fa[v];
-#pragma unroll
-  for (int k = 0; k < H0; ++k)
-    if (k < (d ? H1 : H0)) {
-      s_buf[le][(2 * M + vo + k) * P + (p)] = Ua[k];
-      s_buf[le][(3 * M + vo + k) * P + (p)] = uo[k];
-    }
-  __syncthreads();
+  stages2_tail<Ph, N, NT>(kp, L, le, p, d, e, act, Fa, Ua, Ra, uo, rvol_g, d_alpha_out);
+}
 
-  if (act) {
+// Approximate Lax-Wendroff time averages with two lanes per solution point
+// (2-D systems with many variables).  Lane d evaluates f_d and B_d(u) D_d u at
+// the Taylor points and takes the derivatives along direction d; it owns half
+// of the variables' Taylor coefficients d_t^m u and sums, and the Taylor state
+// at each point crosses between the two lanes of a point.
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void alw2_body(const KParams& kp, Stages2Lds<Ph, N, NT>& L, const double* __restrict__ un_g,
+                                          double* __restrict__ rvol_g, double* d_alpha_out, int blk) {
+  static_assert(Ph::DIM == 2 && Ph::NCD > 0, "two-lane body is for 2-D systems");
+  constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NCD = Ph::NCD;
+  constexpr int H0 = (M + 1) / 2, H1 = M - H0;
+  constexpr int J = N <= 2 ? 1 : 2;
+  auto& s_buf = L.s_buf;
+  const int tid = threadIdx.x;
+  const int d = (tid >> 5) & 1, np = ((tid >> 6) << 5) | (tid & 31);
+  const int le = np / P, p = np - le * P;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
+  const int i = p % n1, j = p / n1;
+  const int q = d ? i : j, ii = d ? j : i;
+  const int pw = d ? i * n1 + j : p;  // exchange slot, transposed for direction 1
+  const int vo = d ? H0 : 0, nown = d ? H1 : H0;
+  const double dt = kp.scal[0];
+  const double idx = d ? kp.inv_dx[1] : kp.inv_dx[0];
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
+
+  double c[N + 1][H0];  // d_t^m u at this node, the lane's half
 #pragma unroll
-    for (int k = 0; k < H0; ++k)
-      if (k < (d ? H1 : H0)) rvol_g[((size_t)(vo + k) * kp.E + e) * P + p] = Ra[k];
-    // face traces: (variable, face point) pairs of the element, variable
-    // slowest, over the element's 2P lanes
-    constexpr int NFT = 4 * NFP;
-    const int tl = 2 * p + d;
-    for (int w = tl; w < NFT * M; w += 2 * P) {
-      const int v = w / NFT, t = w - v * NFT;
-      const int dd = t / (2 * NFP);
-      const int rem = t - dd * 2 * NFP;
-      const int side = rem / NFP;
-      const int qq = rem - side * NFP;
-      const double* V = side ? kp.VR : kp.VL;
-      const size_t nf = (size_t)kp.E * NFP;
-      const size_t fo = (size_t)e * NFP + qq;
-      {
-        double tf = 0.0, tu = 0.0, tn = 0.0;
+  for (int k = 0; k < H0; ++k) {
+    const int v = vo + (k < nown ? k : 0);
+    c[0][k] = un_g[((size_t)v * kp.E + (act ? e : 0)) * P + p];
+  }
+  double Drow[n1];
 #pragma unroll
-        for (int r = 0; r < n1; ++r) {
-          const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
-          tf += V[r] * s_buf[le][(dd * M + v) * P + (nd)];
-          tu += V[r] * s_buf[le][(2 * M + v) * P + (nd)];
-          tn += V[r] * s_buf[le][(3 * M + v) * P + (nd)];
-        }
-        const size_t o = ((size_t)(dd * 2 + side) * M + v) * nf + fo;
-        kp.Ftr[o] = tf;
-        kp.Utr[o] = tu;
-        kp.untr[o] = tn;
-      }
+  for (int r = 0; r < n1; ++r) Drow[r] = kp.D[ii][r];
+  // the full state at the point from the two lanes' halves
+  auto full = [&](const double* h, double* u) {
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      double a = h[k], b = h[k];
+      cross_pair(a, b);
+      u[k] = a;
+      if (k < H1) u[H0 + k] = b;
     }
-    // blending coefficient of the element (smoothed over face neighbours)
-    if (p == 0 && d == 0) {
-      double a;
-      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
-      else if (kp.blending == 0) a = 0.0;
-      else {
-        a = kp.alpha_raw[e];
+  };
+  double Dc[N + 1][NCD];  // D_d (d_t^m u) / dx_d of the components B_d reads
+  auto nc_derivs = [&](int m) {
+    double u[M];
+    full(c[m], u);
 #pragma unroll
-        for (int dn = 0; dn < 2; ++dn)
+    for (int cc = 0; cc < NCD; ++cc) {
+      const double x0 = u[Ph::nc_comp(0, cc)], x1 = u[Ph::nc_comp(1, cc)];
+      s_buf[le][(2 * M + d * NCD + cc) * P + pw] = d ? x1 : x0;
+    }
+    __syncthreads();
 #pragma unroll
-          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, dn, sd)]);
+    for (int cc = 0; cc < NCD; ++cc) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) acc += Drow[r] * s_buf[le][(2 * M + d * NCD + cc) * P + q * n1 + r];
+      Dc[m][cc] = acc * idx;
+    }
+    __syncthreads();
+  };
+  nc_derivs(0);
+
+  double Fa[M], Ua[H0], Ra[H0];
+#pragma unroll
+  for (int v = 0; v < M; ++v) Fa[v] = 0.0;
+#pragma unroll
+  for (int k = 0; k < H0; ++k) { Ua[k] = 0.0; Ra[k] = 0.0; }
+  double fact = 1.0, dtk = 1.0;  // (k+1)!, dt^k
+#pragma unroll
+  for (int k = 0; k <= N; ++k) {
+    fact *= (k + 1);
+    const double ifact = 1.0 / fact;  // constants after unrolling: no division left
+    double fk[M], hk[M];  // dt^k d_t^k of f_d and of B_d(u) D_d u (lane's direction)
+#pragma unroll
+    for (int v = 0; v < M; ++v) { fk[v] = 0.0; hk[v] = 0.0; }
+#pragma unroll
+    for (int jj = -J; jj <= J; ++jj) {
+      const double wj = alw_weight(N, k, jj);
+      if (wj == 0.0) continue;
+      double tm[N + 1];
+      tm[0] = 1.0;
+#pragma unroll
+      for (int m = 1; m <= k; ++m) tm[m] = tm[m - 1] * (jj * dt) * (1.0 / m);
+      double sh[H0], st[M];
+#pragma unroll
+      for (int kk = 0; kk < H0; ++kk) {
+        double a = c[0][kk];
+#pragma unroll
+        for (int m = 1; m <= k; ++m) a += tm[m] * c[m][kk];
+        sh[kk] = a;
       }
-      kp.alpha[e] = a;
-      if (d_alpha_out) d_alpha_out[e] = a;
+      full(sh, st);
+      double f[M];
+      Ph::flux_rd(st, d, f, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) fk[v] += wj * f[v];
+      double wc[NCD], nc[M];
+#pragma unroll
+      for (int cc = 0; cc < NCD; ++cc) {
+        double a = Dc[0][cc];
+#pragma unroll
+        for (int m = 1; m <= k; ++m) a += tm[m] * Dc[m][cc];
+        wc[cc] = a;
+      }
+      Ph::ncprod_rd(st, wc, d, nc, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) hk[v] += wj * nc[v];
+    }
+    // r_d = D_d fk / dx_d + hk through LDS, then the lane's half of r_x + r_y
+#pragma unroll
+    for (int v = 0; v < M; ++v) s_buf[le][(d * M + v) * P + pw] = fk[v];
+    __syncthreads();
+    double rd[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) acc += Drow[r] * s_buf[le][(d * M + v) * P + q * n1 + r];
+      rd[v] = hk[v] + acc * idx;
+    }
+    __syncthreads();
+    double rh[H0];
+#pragma unroll
+    for (int kk = 0; kk < H0; ++kk) {
+      double a = rd[kk], b = kk < H1 ? rd[H0 + kk] : 0.0;
+      cross_pair(a, b);
+      rh[kk] = a + b;
+    }
+    const double uw = dtk * ifact;
+#pragma unroll
+    for (int kk = 0; kk < H0; ++kk) {
+      Ua[kk] += uw * c[k][kk];
+      Ra[kk] += rh[kk] * ifact;
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) Fa[v] += fk[v] * ifact;
+    if (k < N) {
+      const double idtk = -1.0 / dtk;
+#pragma unroll
+      for (int kk = 0; kk < H0; ++kk) c[k + 1][kk] = rh[kk] * idtk;
+      nc_derivs(k + 1);
+      dtk *= dt;
     }
   }
+  stages2_tail<Ph, N, NT>(kp, L, le, p, d, e, act, Fa, Ua, Ra, c[0], rvol_g, d_alpha_out);
+}
+
+// two waves per SIMD: at N = 4 GLM-MHD then spills about 30 VGPRs, and still
+// runs faster than with one wave
+#ifndef ALW2_WAVES_PER_EU
+#define ALW2_WAVES_PER_EU 2
+#endif
+template <class Ph, int N, int EPB>
+__global__ void __launch_bounds__(stages2_threads(EPB, ipow(N + 1, 2))) __attribute__((amdgpu_waves_per_eu(ALW2_WAVES_PER_EU)))
+    k_stages_alw2(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int NT = stages2_threads(EPB, ipow(N + 1, 2));
+  __shared__ Stages2Lds<Ph, N, NT> L;
+  alw2_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // lanes per solution point of the stage kernel: two for the 2-D systems with

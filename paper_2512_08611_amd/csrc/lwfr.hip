@@ -156,6 +156,12 @@ struct TimedLaunch {
 
 // The launch sequence of one step for system Ph at degree N (Tab: the stage
 // tableau, an IMEX pair for systems with a source).
+// the approximate Lax-Wendroff stage kernel with two lanes per solution point
+// for the systems whose cRK stage kernel has two
+#ifndef LWFR_ALW2
+#define LWFR_ALW2 1
+#endif
+
 template <class Ph, int N, class Tab = Tableau<N>>
 lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
                         double* d_alpha, uint32_t* d_flags) {
@@ -173,9 +179,14 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   const int nblk_el = (E + EPB - 1) / EPB;
   constexpr int EPBS = epb_stages<Ph, N>();
   if (c->cfg.flags & LWFR_CFG_ALW) {
-    if constexpr (!Ph::SRC)
-      LWFR_LAUNCH(KID_STAGES, "k_stages_alw", (k_stages_alw<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp,
-                  u_in, u_out, d_alpha);
+    if constexpr (!Ph::SRC) {
+      if constexpr (stage_lanes<Ph>() == 2 && LWFR_ALW2)
+        LWFR_LAUNCH(KID_STAGES, "k_stages_alw", (k_stages_alw2<Ph, N, EPBS>), dim3((E + EPBS - 1) / EPBS),
+                    dim3(stages2_threads(EPBS, P)), 0, s, kp, u_in, u_out, d_alpha);
+      else
+        LWFR_LAUNCH(KID_STAGES, "k_stages_alw", (k_stages_alw<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp,
+                    u_in, u_out, d_alpha);
+    }
   } else {
     LWFR_LAUNCH(KID_STAGES, "k_stages", (k_stages<Ph, N, EPBS, Tab>), dim3((E + EPBS - 1) / EPBS),
                 dim3(stage_threads<Ph, N, EPBS>()), 0, s, kp, u_in, u_out, d_alpha);
