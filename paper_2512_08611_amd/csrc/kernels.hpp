@@ -1781,8 +1781,11 @@ template <class Ph, int N, int NT>
 struct UpdateLds {
   static constexpr int M = Ph::M, P = ipow(N + 1, Ph::DIM), EL = (NT + P - 1) / P;
   double s_u[EL][M][P];
-  double s_f[EL][M][P];     // f_d at the nodes (one direction at a time)
-  double s_left[EL][M][P];  // f^{num,+} of the subface left of each node
+  // f_d at the nodes (one direction at a time).  The node left of a subface is
+  // the only reader of its right neighbour's slot, and overwrites it with the
+  // subface flux f^{num,+} that the neighbour needs, after reading it; the
+  // slots then serve Algorithm 2's reductions
+  double s_f[EL][M][P];
   double s_red[EL][P];      // sigma_d at the nodes / reductions
   uint32_t s_fl[EL][P];
 };
@@ -1794,7 +1797,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
   auto& s_u = L.s_u;
   auto& s_f = L.s_f;
-  auto& s_left = L.s_left;
+  auto& s_left = L.s_f;  // f^{num,+} of the subface left of each node (see UpdateLds)
   auto& s_red = L.s_red;
   auto& s_fl = L.s_fl;
 
