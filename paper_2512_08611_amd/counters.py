@@ -116,7 +116,7 @@ def summarize(stats_csv, fetch_csv, write_csv, copy_bytes, match, fp64_csv=None,
 
 
 def write_md(path, title, summary, ff, fw, commands, digest):
-    lines = [f"# {title}", "", "Commands (from the repository root R on the GPU box; the counter passes are separate runs):", ""]
+    lines = [f"# {title}", "", "Commands (run from the repository root R; the counter passes are separate runs):", ""]
     lines += ["```"] + list(commands) + ["```", ""]
     lines += [f"Calibration (256 MiB device copy in the same runs): FETCH_SIZE x {ff / 1024:.3f} KiB, "
               f"WRITE_SIZE x {fw / 1024:.3f} KiB per counted KiB.", ""]
