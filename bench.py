@@ -269,8 +269,8 @@ def rotor_run(torch, lwfr, workloads, np, n=256, N=4, tend=0.15, gamma=1.4):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the step has no multi-GPU path "
-              f"in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
+              f"path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
