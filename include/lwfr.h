@@ -94,7 +94,9 @@ typedef struct {
   uint32_t abi_version;  /* LWFR_ABI_VERSION */
   int32_t equation;      /* lwfr_equation */
   int32_t degree;        /* N, 1..4 */
-  int32_t nelem[2];      /* elements per direction; nelem[1] ignored in 1-D */
+  int32_t nelem[2];      /* elements per direction; nelem[1] ignored in 1-D; at most
+                            2^26 elements in all (element, node and face-point indices
+                            stay in 32 bits), else LWFR_E_INVALID_ARG */
   double lo[2], hi[2];   /* domain box */
   double gamma;          /* GLM-MHD ratio of specific heats (5/3) */
   double gravity;        /* shallow water g (9.81) */

@@ -37,6 +37,7 @@ def test_init_validation():
     bad = [
         dict(degree=0), dict(degree=5), dict(nelem=(0, 4)), dict(blending=3), dict(alpha_max=1.5),
         dict(cfl_safety=0.0), dict(hi=(0.0, 1.0)), dict(gamma=1.0), dict(alpha_force=2.0),
+        dict(nelem=(8193, 8192)),  # one row past 2^26 elements: indices would leave 32 bits
     ]
     for kw in bad:
         args = dict(equation=lwfr.LWFR_EQ_GLMMHD2D, degree=3, nelem=(4, 4))
@@ -45,6 +46,11 @@ def test_init_validation():
         with pytest.raises(lwfr.LwfrError) as ei:
             lwfr.lwfr_init(cfg)
         assert ei.value.status in (lwfr.LWFR_E_INVALID_ARG, lwfr.LWFR_E_UNSUPPORTED)
+    # exactly 2^26 elements is accepted (the context is host-side; nothing is allocated)
+    big = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 4, (8192, 8192)))
+    assert lwfr.lwfr_state_size(big) == 9 * 8192 * 8192 * 25
+    assert lwfr.lwfr_workspace_bytes(big) > 0
+    lwfr.lwfr_destroy(big)
     cfg = lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 10)
     cfg.abi_version = 99
     with pytest.raises(lwfr.LwfrError):
