@@ -95,19 +95,14 @@ __global__ void __launch_bounds__(NT) kb_pre(const BatchArgs ba, const double* _
 // (eq. time.step.2d) unless the problem's dt is fixed
 __global__ void __launch_bounds__(256) kb_dt(const BatchArgs ba, const int* __restrict__ tile_begin,
                                              double* d_dt) {
-  __shared__ double s_max[256];
+  __shared__ double s_w[4];
   const int inst = blockIdx.x;
   const KParams& kp = ba.kps[inst];
   double m = 0.0;
   for (int i = tile_begin[inst] + threadIdx.x; i < tile_begin[inst + 1]; i += blockDim.x) m = fmax(m, ba.part[i]);
-  s_max[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
-    __syncthreads();
-  }
+  const double lam_all = block_reduce<true>(m, s_w);
   if (threadIdx.x == 0) {
-    const double lam = s_max[0];
+    const double lam = lam_all;
     const double dt = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
     kp.scal[0] = dt;
     kp.scal[1] = kp.ch_in >= 0.0 ? kp.ch_in : 0.0;

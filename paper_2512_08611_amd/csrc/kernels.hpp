@@ -265,9 +265,34 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) k_pre(const KParams
   pre_body<Ph, N, EPB, NT>(kp, L, un, b, kp.part + b);
 }
 
+// Max / min over a workgroup of whole waves: within each wave by lane
+// exchanges, then over the waves' results through LDS (one barrier).  The
+// result is valid in every thread.  Max and min are exact, so the order of the
+// reduction does not change the result.
+__device__ inline double wave_reduce_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ inline double wave_reduce_min(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+  return x;
+}
+template <bool MAX>
+__device__ inline double block_reduce(double x, double* s_w /* >= blockDim.x / 64 */) {
+  x = MAX ? wave_reduce_max(x) : wave_reduce_min(x);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_w[w] = x;
+  __syncthreads();
+  double r = s_w[0];
+  for (int k = 1; k < nw; ++k) r = MAX ? fmax(r, s_w[k]) : fmin(r, s_w[k]);
+  return r;
+}
+
 // k_dt: one block of 1024 threads; Lambda and dt
 __global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, int has_ch) {
-  __shared__ double s_max[1024];
+  __shared__ double s_w[16];
   double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
   const int n = kp.nblk_pre, st = blockDim.x;
   int i = threadIdx.x;
@@ -278,14 +303,9 @@ __global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, 
     m3 = fmax(m3, kp.part[i + 3 * st]);
   }
   for (; i < n; i += st) m0 = fmax(m0, kp.part[i]);
-  s_max[threadIdx.x] = fmax(fmax(m0, m1), fmax(m2, m3));
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) s_max[threadIdx.x] = fmax(s_max[threadIdx.x], s_max[threadIdx.x + s]);
-    __syncthreads();
-  }
+  const double lam_all = block_reduce<true>(fmax(fmax(m0, m1), fmax(m2, m3)), s_w);
   if (threadIdx.x == 0) {
-    const double lam = s_max[0];
+    const double lam = lam_all;
     const double dt = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
     kp.scal[0] = dt;
     kp.scal[2] = lam;
@@ -300,7 +320,7 @@ __global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, 
 // k_ch: GLM speed candidate of each element: the largest c with
 // wx max(c_x, c) + wy max(c_y, c) <= Lambda - (wx |v_x| + wy |v_y|)
 __global__ void __launch_bounds__(256) k_ch(const KParams kp) {
-  __shared__ double s_min[256];
+  __shared__ double s_w[4];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   double ce = INFINITY;
   if (e < kp.E) {
@@ -311,17 +331,12 @@ __global__ void __launch_bounds__(256) k_ch(const KParams kp) {
     if (lo > hi) { double t = lo; lo = hi; hi = t; t = wlo; wlo = whi; whi = t; }
     ce = (wlo + whi) * hi >= R ? (R - whi * hi) / wlo : R / (wlo + whi);
   }
-  s_min[threadIdx.x] = ce;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) kp.part2[blockIdx.x] = s_min[0];
+  const double cmin = block_reduce<false>(ce, s_w);
+  if (threadIdx.x == 0) kp.part2[blockIdx.x] = cmin;
 }
 
 __global__ void __launch_bounds__(1024) k_ch_fin(const KParams kp, double* d_dt_ch) {
-  __shared__ double s_min[1024];
+  __shared__ double s_w[16];
   double m0 = INFINITY, m1 = INFINITY;
   const int n = kp.nblk_ch, st = blockDim.x;
   int i = threadIdx.x;
@@ -330,15 +345,10 @@ __global__ void __launch_bounds__(1024) k_ch_fin(const KParams kp, double* d_dt_
     m1 = fmin(m1, kp.part2[i + st]);
   }
   for (; i < n; i += st) m0 = fmin(m0, kp.part2[i]);
-  s_min[threadIdx.x] = fmin(m0, m1);
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) s_min[threadIdx.x] = fmin(s_min[threadIdx.x], s_min[threadIdx.x + s]);
-    __syncthreads();
-  }
+  const double ch = block_reduce<false>(fmin(m0, m1), s_w);
   if (threadIdx.x == 0) {
-    kp.scal[1] = s_min[0];
-    if (d_dt_ch) { d_dt_ch[0] = kp.scal[0]; d_dt_ch[1] = s_min[0]; }
+    kp.scal[1] = ch;
+    if (d_dt_ch) { d_dt_ch[0] = kp.scal[0]; d_dt_ch[1] = ch; }
   }
 }
 
