@@ -293,17 +293,21 @@ __device__ inline double block_reduce(double x, double* s_w /* >= blockDim.x / 6
 // k_dt: one block of 1024 threads; Lambda and dt
 __global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, int has_ch) {
   __shared__ double s_w[16];
-  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
   const int n = kp.nblk_pre, st = blockDim.x;
-  int i = threadIdx.x;
-  for (; i + 3 * st < n; i += 4 * st) {
-    m0 = fmax(m0, kp.part[i]);
-    m1 = fmax(m1, kp.part[i + st]);
-    m2 = fmax(m2, kp.part[i + 2 * st]);
-    m3 = fmax(m3, kp.part[i + 3 * st]);
+  // 16 loads in flight per thread (up to 16384 partials in one round trip); an
+  // index past the end reads the thread's first one again, which leaves the max
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 16 * st) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int idx = i + k * st;
+      v[k] = kp.part[idx < n ? idx : i];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m = fmax(m, v[k]);
   }
-  for (; i < n; i += st) m0 = fmax(m0, kp.part[i]);
-  const double lam_all = block_reduce<true>(fmax(fmax(m0, m1), fmax(m2, m3)), s_w);
+  const double lam_all = block_reduce<true>(m, s_w);
   if (threadIdx.x == 0) {
     const double lam = lam_all;
     const double dt = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
