@@ -124,10 +124,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) kb
     const double* un = u_in + ba.uoff[inst];
     double* rv = u_out + ba.uoff[inst];
     switch (kp.N) {
-      case 1: stage_body<Ph, 1, batch_epb_stages<Ph, 1, NT>(), NT>(kp, L.n1, un, rv, nullptr, blk); break;
-      case 2: stage_body<Ph, 2, batch_epb_stages<Ph, 2, NT>(), NT>(kp, L.n2, un, rv, nullptr, blk); break;
-      case 3: stage_body<Ph, 3, batch_epb_stages<Ph, 3, NT>(), NT>(kp, L.n3, un, rv, nullptr, blk); break;
-      default: stage_body<Ph, 4, batch_epb_stages<Ph, 4, NT>(), NT>(kp, L.n4, un, rv, nullptr, blk); break;
+      case 1: stage_body<Ph, 1, batch_epb_stages<Ph, 1, NT>(), NT, Tableau<1>, true>(kp, L.n1, un, rv, nullptr, blk); break;
+      case 2: stage_body<Ph, 2, batch_epb_stages<Ph, 2, NT>(), NT, Tableau<2>, true>(kp, L.n2, un, rv, nullptr, blk); break;
+      case 3: stage_body<Ph, 3, batch_epb_stages<Ph, 3, NT>(), NT, Tableau<3>, true>(kp, L.n3, un, rv, nullptr, blk); break;
+      default: stage_body<Ph, 4, batch_epb_stages<Ph, 4, NT>(), NT, Tableau<4>, true>(kp, L.n4, un, rv, nullptr, blk); break;
     }
     __syncthreads();
   }
@@ -165,10 +165,10 @@ __global__ void __launch_bounds__(NT) kb_update(const BatchArgs ba, const double
     const double* un = u_in + ba.uoff[inst];
     double* o = io + ba.uoff[inst];
     switch (kp.N) {
-      case 1: update_body<Ph, 1, batch_epb<1, NT>(DIM), NT>(kp, L.n1, un, o, nullptr, blk); break;
-      case 2: update_body<Ph, 2, batch_epb<2, NT>(DIM), NT>(kp, L.n2, un, o, nullptr, blk); break;
-      case 3: update_body<Ph, 3, batch_epb<3, NT>(DIM), NT>(kp, L.n3, un, o, nullptr, blk); break;
-      default: update_body<Ph, 4, batch_epb<4, NT>(DIM), NT>(kp, L.n4, un, o, nullptr, blk); break;
+      case 1: update_body<Ph, 1, batch_epb<1, NT>(DIM), NT, true>(kp, L.n1, un, o, nullptr, blk); break;
+      case 2: update_body<Ph, 2, batch_epb<2, NT>(DIM), NT, true>(kp, L.n2, un, o, nullptr, blk); break;
+      case 3: update_body<Ph, 3, batch_epb<3, NT>(DIM), NT, true>(kp, L.n3, un, o, nullptr, blk); break;
+      default: update_body<Ph, 4, batch_epb<4, NT>(DIM), NT, true>(kp, L.n4, un, o, nullptr, blk); break;
     }
     __syncthreads();
   }

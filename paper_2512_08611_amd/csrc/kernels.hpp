@@ -25,6 +25,24 @@ namespace lwfr {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// The thread's index in the workgroup, hidden from the optimiser by an empty asm
+// statement (no instruction is emitted).  The batched kernels run the per-element
+// bodies below once per tile in a loop; without this, everything the bodies
+// derive from the thread index (node coordinates, LDS offsets) is hoisted out of
+// that loop for every degree's body and held in registers throughout.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+// OT: the body runs inside a batched tile loop (single-problem kernels keep the
+// plain index, whose known range gives shorter index arithmetic)
+template <bool OT>
+__device__ __forceinline__ int body_tid() {
+  if constexpr (OT) return opaque_tid();
+  else return threadIdx.x;
+}
+
 // Workgroups of a launch go to the eight XCDs in turn, and each XCD has its own
 // L2.  Neighbouring workgroups share cache lines at their edges (the face data of
 // adjacent elements, the node rows either side of a y face), so the block index a
@@ -463,7 +481,7 @@ __device__ __forceinline__ void stage_outputs(const KParams& kp, double (&sb)[NB
 // IMEX pair (the source enters each stage through the implicit part, eq.
 // crkfr.inner, and its b-weighted average, eq. avg.source, is subtracted from
 // the volume residual).
-template <class Ph, int N, int EPB, int NT, class Tab = Tableau<N>>
+template <class Ph, int N, int EPB, int NT, class Tab = Tableau<N>, bool OT = false>
 __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, NT>& L,
                                             const double* __restrict__ un_g, double* __restrict__ rvol_g,
                                             double* d_alpha_out, int blk) {
@@ -472,7 +490,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
   constexpr int S = Tab::S;
   auto& s_buf = L.s_buf;
 
-  const int tid = threadIdx.x;
+  const int tid = body_tid<OT>();
   const int le = tid / P, p = tid - le * P;
   const int e = blk * EPB + le;
   const bool act = le < EPB && e < kp.E;
@@ -889,7 +907,7 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
   }
 }
 
-template <class Ph, int N, int EPB, int NT>
+template <class Ph, int N, int EPB, int NT, bool OT = false>
 __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N, NT>& L,
                                              const double* __restrict__ un_g, double* __restrict__ rvol_g,
                                              double* d_alpha_out, int blk) {
@@ -900,7 +918,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
   constexpr int S = Tab::S;
   auto& s_buf = L.s_buf;
 
-  const int tid = threadIdx.x;
+  const int tid = body_tid<OT>();
   const int d = (tid >> 5) & 1, np = ((tid >> 6) << 5) | (tid & 31);
   const int le = np / P, p = np - le * P;
   const int e = blk * EPB + le;
@@ -1194,12 +1212,12 @@ constexpr int stage_lanes() {
 template <class Ph, int N, int NT>
 using StageLdsT = typename std::conditional<stage_lanes<Ph>() == 2, Stages2Lds<Ph, N, NT>, StagesLds<Ph, N, NT>>::type;
 
-template <class Ph, int N, int EPB, int NT, class Tab = Tableau<N>>
+template <class Ph, int N, int EPB, int NT, class Tab = Tableau<N>, bool OT = false>
 __device__ __forceinline__ void stage_body(const KParams& kp, StageLdsT<Ph, N, NT>& L, const double* __restrict__ un_g,
                                            double* __restrict__ rvol_g, double* d_alpha_out, int blk) {
   static_assert(stage_lanes<Ph>() == 1 || std::is_same<Tab, Tableau<N>>::value, "IMEX pairs use the one-lane kernel");
-  if constexpr (stage_lanes<Ph>() == 2) stages2_body<Ph, N, EPB, NT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
-  else stages_body<Ph, N, EPB, NT, Tab>(kp, L, un_g, rvol_g, d_alpha_out, blk);
+  if constexpr (stage_lanes<Ph>() == 2) stages2_body<Ph, N, EPB, NT, OT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
+  else stages_body<Ph, N, EPB, NT, Tab, OT>(kp, L, un_g, rvol_g, d_alpha_out, blk);
 }
 
 // threads of a stage workgroup of EPB elements
@@ -1804,7 +1822,7 @@ struct UpdateLds {
   uint32_t s_fl[EL][P];
 };
 
-template <class Ph, int N, int EPB, int NT>
+template <class Ph, int N, int EPB, int NT, bool OT = false>
 __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, NT>& L,
                                             const double* __restrict__ un_g, double* __restrict__ io,
                                             uint32_t* d_flags, int blk) {
@@ -1815,7 +1833,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   auto& s_red = L.s_red;
   auto& s_fl = L.s_fl;
 
-  const int tid = threadIdx.x;
+  const int tid = body_tid<OT>();
   const int le = tid / P, p = tid - le * P;
   const int e = blk * EPB + le;
   const bool act = le < EPB && e < kp.E;
