@@ -58,9 +58,50 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-problem measurement")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the rotor run and the variants (GLL, approximate LW, Jin-Xin IMEX): profiling runs")
+    ap.add_argument("--no-references", action="store_true",
+                    help="skip the measured device references (a 1 GiB copy and an FP64 matrix product; "
+                         "also skipped with --no-extras or --copy-calibration)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device copy of 256 MiB (reference kernel for the HBM byte counters)")
     return ap.parse_args()
+
+
+def device_references(torch, reps=5):
+    """What this GPU reaches on plain reference work, beside the published peaks the
+    roofline uses: a 1 GiB device-to-device copy (read + write bytes per second) and
+    an 8192^3 FP64 matrix product through the ROCm BLAS library (dense FP64 flops per
+    second).  Each is timed with events on the current stream, best of `reps`."""
+    dev = torch.device("cuda:0")
+    res = {}
+    a = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    res["copy_GBs"] = 2 * a.numel() * 8 / min(ts) / 1e9
+    del a, b
+    n = 8192
+    A = torch.rand((n, n), dtype=torch.float64, device=dev)
+    B = torch.rand((n, n), dtype=torch.float64, device=dev)
+    C = torch.matmul(A, B)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.matmul(A, B, out=C)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    res["fp64_gemm_TFLOPs"] = 2.0 * n ** 3 / min(ts) / 1e12
+    res["note"] = ("measured on this GPU for context; the roofline fractions use the published peaks "
+                   "(8 TB/s HBM, 78.6 TFLOP/s FP64 vector)")
+    return res
 
 
 def cpu_baseline(u0, n, N, steps):
@@ -411,6 +452,9 @@ def main():
         out["alw"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_ALW, K,
                                     "approximate Lax-Wendroff time averages in place of the cRK stages")
         out["imex_jinxin"] = jinxin_timing(torch, lwfr, workloads, np, K)
+    if not (args.no_references or args.no_extras or args.copy_calibration):
+        # not in profiling runs: the counter calibration takes the largest copy
+        out["device_references"] = device_references(torch)
     if args.copy_calibration:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
