@@ -260,3 +260,33 @@ def count_ops(c, u, dt, ch):
     assert lib().ora_count_ops(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch),
                                _p(counts, ctypes.c_uint64)) == 0
     return counts.reshape(4, 5)
+
+
+def step_parts(c, u, dt=0.0, ch=-1.0):
+    """u^{n+1}, the lower order update u^L and the blend u* before Algorithm 2, the
+    Algorithm 2 theta product per element and the flags, for one step as `step`."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    E = c.nx * c.ny
+    out = {"u": np.zeros_like(u), "uL": np.zeros_like(u), "ustar": np.zeros_like(u), "theta_elem": np.ones(E),
+           "flags": np.zeros(E, dtype=np.uint32)}
+    rc = lib().ora_step_parts(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch), _p(out["u"]),
+                              _p(out["uL"]), _p(out["ustar"]), _p(out["theta_elem"]),
+                              _p(out["flags"], ctypes.c_uint32))
+    assert rc == 0, rc
+    return out
+
+
+def face(c, d, side_m, side_p, af, dt, ch=0.0):
+    """One face (Algorithm 1 with cfg blending = 2) from side data [a, F, U, s, si]
+    (each M values: face u^n, traces of F_d and U, u^n at the node next to the face
+    and the one after it).  Returns (F^-, F^+, theta product, guard)."""
+    M = NVARS[c.eq]
+    sm = np.ascontiguousarray(side_m, dtype=np.float64).reshape(5 * M)
+    sp = np.ascontiguousarray(side_p, dtype=np.float64).reshape(5 * M)
+    Fm, Fp = np.zeros(M), np.zeros(M)
+    th = ctypes.c_double(1.0)
+    g = ctypes.c_uint8(0)
+    rc = lib().ora_face(ctypes.byref(c), d, _p(sm), _p(sp), ctypes.c_double(af), ctypes.c_double(dt),
+                        ctypes.c_double(ch), _p(Fm), _p(Fp), ctypes.byref(th), ctypes.byref(g))
+    assert rc == 0, rc
+    return Fm, Fp, th.value, g.value

@@ -204,6 +204,48 @@ int ora_step(const ora_cfg* c, const double* u, double* unew, double dt_in, doub
   });
 }
 
+// The pre-Algorithm-2 parts of one step with dt, c_h and alpha as ora_step
+// computes them: u^L (lower order subcell update) and u* = (1 - alpha) u^H +
+// alpha u^L, plus u^{n+1} and theta_elem (product of the Algorithm 2 thetas).
+int ora_step_parts(const ora_cfg* c, const double* u, double dt_in, double ch_in, double* unew, double* uL,
+                   double* ustar, double* theta_elem, uint32_t* flags) {
+  return dispatch(c, [&](auto& s) {
+    double dt, ch;
+    s.dt_ch(u, dt, ch);
+    if (dt_in > 0) dt = dt_in;
+    if (ch_in >= 0) ch = ch_in;
+    std::vector<double> araw, alpha;
+    std::vector<uint8_t> t;
+    s.indicator(u, araw, alpha, t);
+    s.template step<double>(u, unew, dt, ch, alpha, flags, nullptr, theta_elem, uL, ustar);
+  });
+}
+
+// One face in direction d (Algorithm 1 included when cfg blending = 2) from the
+// data of its two sides.  side_m, side_p: 5 M values each, [a | F | U | s | si]
+// = face value of u^n, traces of F_d and U, u^n at the node next to the face
+// and at the node after it.  af: alpha of the face.  Out: F^- (Fm), F^+ (Fp),
+// the product of the Algorithm 1 thetas and the guard bit.
+int ora_face(const ora_cfg* c, int d, const double* side_m, const double* side_p, double af, double dt, double ch,
+             double* Fm, double* Fp, double* theta, uint8_t* guard) {
+  return dispatch(c, [&](auto& s) {
+    using S = std::decay_t<decltype(s)>;
+    constexpr int M = S::M;
+    typename S::template Side<double> mi, pl;
+    for (int v = 0; v < M; ++v) {
+      mi.a[v] = side_m[v]; mi.F[v] = side_m[M + v]; mi.U[v] = side_m[2 * M + v];
+      mi.s[v] = side_m[3 * M + v]; mi.si[v] = side_m[4 * M + v];
+      pl.a[v] = side_p[v]; pl.F[v] = side_p[M + v]; pl.U[v] = side_p[2 * M + v];
+      pl.s[v] = side_p[3 * M + v]; pl.si[v] = side_p[4 * M + v];
+    }
+    double th = 1.0;
+    uint8_t g = 0;
+    s.face(d, mi, pl, af, true, true, dt, ch, Fm, Fp, th, g);
+    *theta = th;
+    *guard = g;
+  }, false);
+}
+
 // Element-local time averages of one step (the stages, or the approximate LW
 // procedure with cfg alw): F [d][v][e][p], U [v][e][p], B^loc [v][e][p].
 int ora_time_averages(const ora_cfg* c, const double* u, double dt, double ch, double* F, double* U, double* Bl) {

@@ -715,9 +715,12 @@ struct Scheme {
   }
 
   // ------------------------------------------------ 5. element update -----
+  // uL_out, ustar_out (nullable, [v][e][p]): the lower order update u^L and the
+  // blend (1 - alpha_e) u^H + alpha_e u^L before Algorithm 2 (test inspection).
   template <class T>
   void update(const T* un, const Local<T>& L, const Faces<T>& Fc, const std::vector<double>& alpha,
-              double dt, double ch, T* unew, uint32_t* flags, double* theta_elem) const {
+              double dt, double ch, T* unew, uint32_t* flags, double* theta_elem, T* uL_out = nullptr,
+              T* ustar_out = nullptr) const {
     std::vector<T> uH((size_t)M * P), uL((size_t)M * P), us((size_t)M * P);
     T x0[M], x1[M], fm[M], fp[M], tmp[M];
     for (int e = 0; e < E; ++e) {
@@ -793,6 +796,11 @@ struct Scheme {
         // blend (eq. blended.scheme)
         double al = alpha[e];
         for (size_t i = 0; i < us.size(); ++i) us[i] = T(1.0 - al) * uH[i] + T(al) * uL[i];
+        for (int v = 0; v < M; ++v)
+          for (int p = 0; p < P; ++p) {
+            if (uL_out) uL_out[idx(v, e, p)] = uL[(size_t)v * P + p];
+            if (ustar_out) ustar_out[idx(v, e, p)] = us[(size_t)v * P + p];
+          }
         // Algorithm 2
         double Theta = 1.0;
         T z[M];
@@ -832,7 +840,7 @@ struct Scheme {
   // full step for scalar type T with dt, c_h and alpha given (frozen)
   template <class T>
   void step(const T* un, T* unew, double dt, double ch, const std::vector<double>& alpha, uint32_t* flags,
-            double* theta_face, double* theta_elem) const {
+            double* theta_face, double* theta_elem, T* uL_out = nullptr, T* ustar_out = nullptr) const {
     Local<T> L;
     Faces<T> Fc;
     if (cfg.alw) stages_alw(un, dt, ch, L);
@@ -840,7 +848,7 @@ struct Scheme {
     face_traces(un, L);
     faces(un, L, alpha, dt, ch, Fc);
     if (theta_face) std::copy(Fc.theta.begin(), Fc.theta.end(), theta_face);
-    update(un, L, Fc, alpha, dt, ch, unew, flags, theta_elem);
+    update(un, L, Fc, alpha, dt, ch, unew, flags, theta_elem, uL_out, ustar_out);
   }
 };
 
