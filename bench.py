@@ -1,11 +1,13 @@
 """Throughput of the time step on one MI355X, with roofline and CPU-oracle baseline.
 
-Workload (the metric's 1-GPU configuration): 2-D ideal GLM-MHD, Orszag-Tang
-vortex plus seeded Fourier perturbations of amplitude 1e-2 (seed 0), periodic
-256 x 256 elements, N = 4 (25 Gauss-Legendre points per element, 1,638,400
-solution points), FP64, C_s = 0.9 with CFL(N) from the library's Fourier
-analysis, subcell blending with Algorithms 1 and 2, dt computed on the device
-every step.
+Workload of the headline line (the largest single-problem configuration):
+2-D ideal GLM-MHD on 512 x 512 periodic elements, N = 3 (16 Gauss-Legendre
+points per element, 4,194,304 solution points), blocky data (16 x 16 constant
+blocks with density and pressure ratios up to 10 and 100 and random fields,
+at rest, jumps inside elements; seed 0), FP64, C_s = 0.9 with CFL(N) from the
+library's Fourier analysis, subcell blending with Algorithms 1 and 2 active,
+dt computed on the device every step.  The secondary line is the smooth
+Orszag-Tang workload (256 x 256, N = 4).
 
 One "step" is one full time step (means/indicator, dt and c_h, element stages,
 faces, update).  The state is resident in HBM before the timed region.  The
@@ -43,6 +45,12 @@ STAGE_LOOP_FLOPS_PER_DOF = {
     ("GLMMHD2D", 4): 3561,
     ("GLMMHD2D", 3): 2153,
 }
+# Algorithmic floating point operations per solution point of a whole step
+# (means, indicator, dt and c_h; stage loop; face traces; faces with Algorithm
+# 1; update with the subcell scheme and Algorithm 2), counted by the oracle's
+# counting scalar on a 16x16-element sample of the workload's recipe (the
+# limiters' work depends on the data).  tests/test_bench_contract.py re-counts.
+STEP_FLOPS_PER_DOF = {}
 
 
 def parse():
@@ -50,10 +58,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--nelem", type=int, default=256)
-    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--workload", default="mhd512_n3_blocky", choices=sorted(WORKLOADS),
+                    help="the timed workload (the other one is measured as the secondary line)")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workload's line")
+    ap.add_argument("--graph-trace", action="store_true",
+                    help="profiling runs: only the warm-up and the graph-replayed steps run (no event-timed pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps of the CPU baseline sample")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps of the CPU baseline sample")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-problem measurement")
     ap.add_argument("--no-extras", action="store_true",
@@ -124,6 +135,7 @@ def cpu_baseline(u0, n, N, steps):
         "kind": "oracle",
         "sample": f"{steps} steps of the full {n}x{n} N={N} GLM-MHD workload, single-threaded C++ oracle "
                   f"({dt:.1f} s)",
+        "host": host_info(),
     }
 
 
@@ -307,51 +319,77 @@ def rotor_run(torch, lwfr, workloads, np, n=256, N=4, tend=0.15, gamma=1.4):
             "unit": "DOF-updates/s", "step_status": int(status), "flags_or": int(flags)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
-              f"path", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
+def host_info():
+    """The host CPU model and the cores this process may use (the oracle's baseline runs on them)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
 
-    from paper_2512_08611_amd import lwfr, workloads
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    lwfr.lib()  # raises if the HIP library is not built
-    n, N, K, Wm = args.nelem, args.degree, args.steps, args.warmup
+WORKLOADS = {
+    # name: (elements per direction, degree, data)
+    "mhd512_n3_blocky": (512, 3, "blocky"),
+    "mhd256_n4_smooth": (256, 4, "smooth"),
+}
+
+
+def workload_state(workloads, np, xi, n, data):
+    if data == "blocky":
+        return workloads.mhd_blocky(np.array(xi), n, n, seed=0)
+    return workloads.mhd_smooth(np.array(xi), n, n, seed=0)
+
+
+def workload_text(n, N, data):
+    dofs = n * n * (N + 1) ** 2
+    if data == "blocky":
+        return (f"2-D GLM-MHD, 16x16 piecewise-constant blocks (rho 10^U(-1,0), p 10^U(-2,0), B 0.5 U(-1,1), "
+                f"at rest; jumps inside elements; seed 0), {n}x{n} periodic elements, N={N} Gauss-Legendre "
+                f"({dofs} DOF, 9 variables), blending + Algorithms 1-2, C_s=0.9")
+    return (f"2-D GLM-MHD Orszag-Tang + 1e-2 seeded Fourier perturbations, {n}x{n} periodic elements, "
+            f"N={N} Gauss-Legendre ({dofs} DOF, 9 variables), blending + Algorithms 1-2, C_s=0.9")
+
+
+def measure(torch, np, lwfr, workloads, counters, n, N, data, K, Wm, graph_trace=False):
+    """One workload: Wm warm-up steps, K steps launched one by one with HIP events
+    around every kernel (per-kernel durations, ms_per_step_eager), then the timed
+    region: the same K steps as one HIP graph replayed once after an untimed replay."""
     dev = torch.device("cuda:0")
     cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), cfl_safety=0.9, blending=2)
     stream = torch.cuda.Stream(dev)  # graph capture needs a non-default stream
     st = lwfr.Stepper(cfg, dev, stream=stream)
-    u0 = workloads.mhd_smooth(np.array(st.xi), n, n, seed=0)
+    u0 = workload_state(workloads, np, st.xi, n, data)
     ua = torch.tensor(u0, dtype=torch.float64, device=dev)
     ub = torch.empty_like(ua)
     dtch = torch.zeros(2, dtype=torch.float64, device=dev)
     E, P = n * n, (N + 1) ** 2
     dofs = E * P
-
     for _ in range(Wm):
         st.step(ua, ub, 0.0, dtch)
         ua, ub = ub, ua
     torch.cuda.synchronize()
-    status, _ = st.query()
-
-    # K steps launched one by one, HIP events around every kernel: per-kernel durations
-    lwfr.lwfr_timing_begin(st.ctx, 8 * K)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(K):
-        st.step(ua, ub, 0.0, dtch)
-        ua, ub = ub, ua
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = lwfr.lwfr_timing_end(st.ctx)
-    wall_eager = t1 - t0
-    # timed region: the same K steps as one HIP graph (one untimed replay uploads it)
+    per_kernel, wall_eager = {}, None
+    if not graph_trace:
+        lwfr.lwfr_timing_begin(st.ctx, 8 * K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            st.step(ua, ub, 0.0, dtch)
+            ua, ub = ub, ua
+        torch.cuda.synchronize()
+        wall_eager = time.perf_counter() - t0
+        kern = lwfr.lwfr_timing_end(st.ctx)
+        per_kernel = {k: {"ms_per_launch": (ms / cnt if cnt else None), "launches": cnt, "ms_total": ms}
+                      for k, (ms, cnt) in kern.items() if cnt}
     ga, gb = ua.clone(), torch.empty_like(ua)
     torch.cuda.synchronize()
     st.graph_capture(ga, gb, K)
@@ -362,22 +400,25 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t2
     status, flags = st.query()
-    value = dofs * K / wall
-    per_kernel = {k: {"ms_per_launch": (ms / cnt if cnt else None), "launches": cnt, "ms_total": ms}
-                  for k, (ms, cnt) in kern.items() if cnt}
+    res = {
+        "value": dofs * K / wall,
+        "ms_per_step": wall / K * 1e3,
+        "ms_per_step_eager": wall_eager / K * 1e3 if wall_eager else None,
+        "workload": workload_text(n, N, data),
+        "elements": E, "degree": N, "dof": dofs,
+        "per_kernel": per_kernel,
+        "step_status": int(status), "flags_or": int(flags),
+        "u0": u0,
+    }
+    if graph_trace:
+        return res
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
     avg_ms = per_kernel["k_stages"]["ms_per_launch"]
     flops = STAGE_LOOP_FLOPS_PER_DOF.get(("GLMMHD2D", N))
     achieved = flops * dofs / (avg_ms * 1e-3) / 1e12 if flops else None
-    # HBM bytes per launch of the stage kernel from the committed counter summary
-    # of this workload, only while it was taken on the current kernel sources
-    from paper_2512_08611_amd import counters
-
-    traffic, traffic_us = (None, None)
-    if (n, N) == (256, 4):
-        traffic, traffic_us = counters.read_traffic(os.path.join(ROOT, "profiles", "counters_mhd256_n4.md"),
-                                                    f"k_stages<MHD2D, {N},")
-    roofline = {
+    summary = os.path.join(ROOT, "profiles", f"counters_mhd{n}_n{N}.md")
+    traffic, traffic_us = counters.read_traffic(summary, f"k_stages<MHD2D, {N},")
+    res["roofline"] = {
         "kernel": "k_stages",
         "bound": "alu",
         "achieved": achieved,
@@ -390,66 +431,118 @@ def main():
         "algorithmic_flops_per_launch": flops * dofs if flops else None,
         "dominant_kernel_by_time": dom,
     }
-    # every kernel of the step against both rooflines: HBM bytes and hardware FP64
-    # operations per launch from the committed counter summary (while it matches
-    # the sources), durations measured live above
+    # every kernel of the step against both rooflines (counter figures from the
+    # committed summary while it matches the sources, durations measured live)
+    table = counters.read_table(summary)
     by_kernel = None
-    if (n, N) == (256, 4):
-        table = counters.read_table(os.path.join(ROOT, "profiles", "counters_mhd256_n4.md"))
-        if table:
-            by_kernel = {}
-            for name, row in table.items():
-                base = name.split("<")[0]
-                key = next((k for k in per_kernel if base == k or base.startswith(k + "2")), None)
-                if key is None or not per_kernel[key]["ms_per_launch"]:
-                    continue
-                sec = per_kernel[key]["ms_per_launch"] * 1e-3
-                ent = {"counted_kernel": name, "ms_per_launch": per_kernel[key]["ms_per_launch"]}
-                if "bytes" in row:
-                    gbs = row["bytes"] / sec / 1e9
-                    ent.update(hbm_bytes=row["bytes"], hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
-                if "fp64_ops" in row:
-                    tf = row["fp64_ops"] / sec / 1e12
-                    ent.update(fp64_hw_ops=row["fp64_ops"], fp64_TFLOPs=tf, fp64_frac=tf / FP64_VECTOR_PEAK_TFLOPS)
-                by_kernel[key] = ent
+    step_bytes = None
+    if table:
+        by_kernel, step_bytes = {}, 0.0
+        for name, row in table.items():
+            base = name.split("<")[0]
+            key = next((k for k in per_kernel if base == k or base.startswith(k + "2")), None)
+            if key is None or not per_kernel[key]["ms_per_launch"]:
+                continue
+            sec = per_kernel[key]["ms_per_launch"] * 1e-3
+            ent = {"counted_kernel": name, "ms_per_launch": per_kernel[key]["ms_per_launch"]}
+            if "bytes" in row:
+                gbs = row["bytes"] / sec / 1e9
+                ent.update(hbm_bytes=row["bytes"], hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+                step_bytes += row["bytes"] * per_kernel[key]["launches"] / K
+            if "fp64_ops" in row:
+                tf = row["fp64_ops"] / sec / 1e12
+                ent.update(fp64_hw_ops=row["fp64_ops"], fp64_TFLOPs=tf, fp64_frac=tf / FP64_VECTOR_PEAK_TFLOPS)
+            by_kernel[key] = ent
+    res["rooflines_by_kernel"] = by_kernel
+    # the whole step (graph-replayed) against both rooflines: algorithmic FP64
+    # operations of every phase (oracle counts per solution point) and the HBM
+    # bytes of every kernel of a step (counter summary)
+    sec = wall / K
+    step_flops = STEP_FLOPS_PER_DOF.get((N, data))
+    res["step_roofline"] = {
+        "seconds_per_step": sec,
+        "fp64": None if step_flops is None else {
+            "flops_per_dof": step_flops, "flops_per_step": step_flops * dofs,
+            "achieved_TFLOPs": step_flops * dofs / sec / 1e12,
+            "frac": step_flops * dofs / sec / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
+        "hbm": None if not step_bytes else {
+            "bytes_per_step": step_bytes, "achieved_GBs": step_bytes / sec / 1e9,
+            "frac": step_bytes / sec / 1e9 / HBM_PEAK_GBS,
+            "state_min_bytes_per_step": 2 * 9 * 8 * dofs,
+            "bytes_over_state_min": step_bytes / (2 * 9 * 8 * dofs)},
+    }
+    res["kernels_ms_per_launch"] = {k: v["ms_per_launch"] for k, v in per_kernel.items()}
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU "
+              f"path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2512_08611_amd import counters, lwfr, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lwfr.lib()  # raises if the HIP library is not built
+    n, N, data = WORKLOADS[args.workload]
+    K, Wm = args.steps, args.warmup
+    dev = torch.device("cuda:0")
+    main_line = measure(torch, np, lwfr, workloads, counters, n, N, data, K, Wm, args.graph_trace)
+    u0 = main_line.pop("u0")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_line["value"],
         "unit": "DOF-updates/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": Wm,
-        "ms_per_step": wall / K * 1e3,
-        "ms_per_step_eager": wall_eager / K * 1e3,
+        "ms_per_step": main_line["ms_per_step"],
+        "ms_per_step_eager": main_line["ms_per_step_eager"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": f"2-D GLM-MHD Orszag-Tang + 1e-2 seeded Fourier perturbations, {n}x{n} periodic elements, "
-                        f"N={N} Gauss-Legendre ({dofs} DOF, 9 variables), blending + Algorithms 1-2, C_s=0.9",
-            "elements": E,
-            "degree": N,
-            "dof": dofs,
-        },
-        "roofline": roofline,
-        "rooflines_by_kernel": by_kernel,
-        "kernels_ms_per_launch": {k: v["ms_per_launch"] for k, v in per_kernel.items()},
-        "step_status": int(status),
-        "flags_or": int(flags),
+        "config": {"workload": main_line["workload"], "name": args.workload, "elements": main_line["elements"],
+                   "degree": N, "dof": main_line["dof"]},
+        "roofline": main_line.get("roofline"),
+        "step_roofline": main_line.get("step_roofline"),
+        "rooflines_by_kernel": main_line.get("rooflines_by_kernel"),
+        "kernels_ms_per_launch": main_line.get("kernels_ms_per_launch"),
+        "step_status": main_line["step_status"],
+        "flags_or": main_line["flags_or"],
+        "secondary": None,
         "adjoint_over_forward": None,
         "batched": None,
     }
+    if args.graph_trace:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_secondary:
+        for name in WORKLOADS:
+            if name == args.workload:
+                continue
+            sn, sN, sdata = WORKLOADS[name]
+            sec = measure(torch, np, lwfr, workloads, counters, sn, sN, sdata, K, Wm)
+            sec.pop("u0")
+            sec.pop("per_kernel")
+            sec["name"] = name
+            out["secondary"] = sec
     if not args.no_adjoint:
         out["adjoint_over_forward"] = adjoint_over_forward(torch, lwfr, workloads, np)
     if not args.no_batch:
         out["batched"] = batched(torch, lwfr, workloads, np)
     if not args.no_extras:
         out["rotor"] = rotor_run(torch, lwfr, workloads, np)
-        out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_GLL, K,
+        out["gll_g2"] = variant_timing(torch, lwfr, workloads, np, 256, 4, lwfr.LWFR_CFG_GLL, K,
                                        "Gauss-Lobatto-Legendre points with the g_2 correction")
-        out["alw"] = variant_timing(torch, lwfr, workloads, np, n, N, lwfr.LWFR_CFG_ALW, K,
+        out["alw"] = variant_timing(torch, lwfr, workloads, np, 256, 4, lwfr.LWFR_CFG_ALW, K,
                                     "approximate Lax-Wendroff time averages in place of the cRK stages")
         out["imex_jinxin"] = jinxin_timing(torch, lwfr, workloads, np, K)
     if not (args.no_references or args.no_extras or args.copy_calibration):

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define LWFR_ABI_VERSION 2u
+#define LWFR_ABI_VERSION 3u
 
 typedef struct lwfr_ctx lwfr_ctx;
 
@@ -143,6 +143,28 @@ typedef struct {
  * (LWFR_E_UNSUPPORTED). */
 #define LWFR_CFG_ALW 16u
 
+/* Statistics of one step (filled on the device by lwfr_step when d_stats is
+ * not NULL; the caller owns the device buffer of sizeof(lwfr_stats) bytes,
+ * 8-byte aligned).  The paper's diagnostics are the time step (§5 eq.
+ * time.step.2d), conservation of the variables whose non-conservative row is
+ * zero (§4 after eq. numflux.args), the blending coefficients (§4 eq.
+ * blended.scheme) and the positivity of the constraints of the admissible set
+ * (§2 eq. uad.form, §4.1).  Reductions run in a fixed order: the same step
+ * gives the same bits. */
+typedef struct lwfr_stats {
+  double dt;                  /* the step's time step */
+  double ch;                  /* its GLM cleaning speed (0 without GLM) */
+  double mass[9];             /* sum_e sum_p w_p |Omega_e| u^{n+1}_{v,e,p} per variable v (first M used) */
+  double min_constraint[2];   /* min over nodes of P_k(u^{n+1}) (first K used: depth; density, pressure) */
+  uint32_t alpha_hist[11];    /* elements by alpha_e: [0] alpha = 0, [k] alpha in ((k-1)/10, k/10] */
+  uint32_t n_alg1;            /* elements with LWFR_FLAG_ALG1 */
+  uint32_t n_alg2;            /* elements with LWFR_FLAG_ALG2 */
+  uint32_t n_low_inadm;       /* elements with LWFR_FLAG_LOW_INADM */
+  uint32_t n_nonfinite;       /* elements with LWFR_FLAG_NONFINITE */
+  uint32_t n_alg1_guard;      /* elements with LWFR_FLAG_ALG1_GUARD */
+  uint32_t reserved;
+} lwfr_stats;
+
 /* Validates cfg and builds the reference element, tableau and launch shapes on
  * the host.  No device work.  *out receives a context owned by the caller
  * until lwfr_destroy.  Errors: LWFR_E_INVALID_ARG (bad value, null pointer,
@@ -197,11 +219,12 @@ lwfr_status lwfr_bind(lwfr_ctx* ctx, void* d_workspace, size_t bytes, void* stre
  *   d_dt_ch  nullable; receives {dt, c_h} (c_h = GLM cleaning speed, 0 otherwise)
  *   d_alpha  nullable; receives the blending coefficient alpha_e of each element
  *   d_flags  nullable; receives LWFR_FLAG_* bits of each element
+ *   d_stats  nullable; receives the step's lwfr_stats (two extra launches)
  * Asynchronous on the bound stream; LWFR_E_STATE if not bound, or if the
  * context has a Dirichlet side without data; LWFR_E_INVALID_ARG for dt <= 0
- * with a Dirichlet side. */
+ * with a Dirichlet side, or a d_stats not 8-byte aligned. */
 lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
-                      double* d_alpha, uint32_t* d_flags);
+                      double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats);
 
 /* One time step with both dt > 0 and the GLM cleaning speed ch >= 0 given
  * (ignored by systems without GLM), e.g. to replay a step sequence with the
@@ -209,7 +232,11 @@ lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, doub
 lwfr_status lwfr_step_fixed(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double ch,
                             double* d_alpha, uint32_t* d_flags);
 
-/* Residual R = (u^n - u^{n+1})/dt of one step with the given dt > 0.
+/* Residual R = (u^n - u^{n+1})/dt of one step with the given dt > 0: the
+ * right-hand side of the final update of §3 eq. crkfr.non.cons.final (the
+ * divergence of the time-averaged flux, the averaged non-conservative term and
+ * the correction-function terms), blended with the subcell residual of §4
+ * eq. low.order.update as the mode says.
  * mode 0: high order only (alpha = 0, no limiting); 1: lower order subcell
  * scheme only (alpha = 1, no limiting); 2: as configured.  d_R must not alias d_u. */
 lwfr_status lwfr_residual(lwfr_ctx* ctx, const double* d_u, double dt, int32_t mode, double* d_R);
@@ -236,8 +263,9 @@ lwfr_status lwfr_step_taped(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out
 lwfr_status lwfr_adjoint_step(lwfr_ctx* ctx, const double* d_u_n, double dt, const double* d_lam_np1,
                               double* d_lam_n, const void* d_tape);
 
-/* Synchronises the bound stream and returns the OR of the flags of every step
- * since the previous query (then clears it): LWFR_E_NONFINITE if a non-finite
+/* Synchronises the bound stream and returns the OR of the flags of every
+ * element of every step since the previous query (then clears it; all
+ * LWFR_FLAG_* bits, so limiter activity shows too): LWFR_E_NONFINITE if a non-finite
  * value appeared, LWFR_E_INADMISSIBLE if a lower order update was inadmissible,
  * LWFR_OK otherwise.  flags_or (nullable) receives the raw OR. */
 lwfr_status lwfr_query(lwfr_ctx* ctx, uint32_t* flags_or);

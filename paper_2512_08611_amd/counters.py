@@ -188,7 +188,54 @@ def read_table(path, digest=None):
     return out
 
 
+def trace_summary(trace_csv, steps, match="lwfr::"):
+    """Per-kernel durations of the last `steps` steps of a --kernel-trace run whose last
+    launches are one graph replay of `steps` steps (bench.py --graph-trace), the
+    span from the first start to the last end of those launches, and the summed
+    kernel time: {kernel: [durations ns]}, span_ns, busy_ns."""
+    rows = [r for r in csv.DictReader(open(trace_csv)) if match in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    # launches per step: the kernels between two consecutive launches of k_pre (a step's first kernel)
+    names = [_short(r["Kernel_Name"]) for r in rows]
+    starts = [i for i, n in enumerate(names) if n.startswith("k_pre<")]
+    per_step = starts[-1] - starts[-2] if len(starts) >= 2 else len(rows)
+    last = rows[-per_step * steps:]
+    out = {}
+    for r in last:
+        out.setdefault(_short(r["Kernel_Name"]), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    span = int(last[-1]["End_Timestamp"]) - int(last[0]["Start_Timestamp"])
+    busy = sum(sum(v) for v in out.values())
+    return out, span, busy
+
+
+def write_trace_md(path, title, trace_csv, steps, commands, ms_per_step):
+    ker, span, busy = trace_summary(trace_csv, steps)
+    lines = [f"# {title}", "", "Command (run from the repository root R):", "", "```"] + list(commands) + ["```", ""]
+    lines += [f"The last {steps} steps of the run are one replay of the HIP graph that bench.py times "
+              f"(the timed region).  Per step: kernel span {span / steps / 1e3:.1f} us, summed kernel time "
+              f"{busy / steps / 1e3:.1f} us; the same run's bench line: {ms_per_step * 1e3:.1f} us per step.", ""]
+    lines += ["| kernel | launches | mean (us) | min (us) | max (us) | us per step | % of step |",
+              "|---|---|---|---|---|---|---|"]
+    for k, v in sorted(ker.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {min(v) / 1e3:.1f} | {max(v) / 1e3:.1f} | "
+                     f"{sum(v) / steps / 1e3:.1f} | {100 * sum(v) / busy:.1f} |")
+    lines += ["", f"kernel sources sha256: {sources_digest()}", ""]
+    open(path, "w").write("\n".join(lines) + "\n")
+
+
 def main():
+    if len(os.sys.argv) > 1 and os.sys.argv[1] == "trace":
+        tp = argparse.ArgumentParser(description="summary of a graph-replay kernel trace")
+        tp.add_argument("cmd")
+        tp.add_argument("--trace", required=True, help="rocprofv3 --kernel-trace kernel_trace.csv")
+        tp.add_argument("--steps", type=int, required=True)
+        tp.add_argument("--ms-per-step", type=float, required=True, help="ms_per_step of the same run's bench line")
+        tp.add_argument("--title", default="Kernel trace of the graph-replayed steps")
+        tp.add_argument("--command", action="append", default=[])
+        tp.add_argument("--out", required=True)
+        a = tp.parse_args()
+        write_trace_md(a.out, a.title, a.trace, a.steps, a.command, a.ms_per_step)
+        return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--stats", required=True, help="rocprofv3 --stats kernel_stats.csv")
     ap.add_argument("--fetch", required=True, help="counter_collection.csv of the FETCH_SIZE run")

@@ -101,6 +101,8 @@ struct KParams {
   uint32_t* guard_face;       // [d][E*nfp]
   uint32_t* flag_or;          // [1] OR of every element flag since the last query
   double* theta_elem;         // [E] product of Algorithm 2 thetas
+  uint32_t* eflags;           // [E] element flags of the last step with statistics
+  double* stats_rows;         // per-block rows of the step statistics
   // boundaries: kind of side (d, s), 0 periodic, 1 outflow, 2 wall, 3 Dirichlet
   int bc[2][2];
   const double* ghost;        // Dirichlet face data, per side 2d+s: [3][M][lines_d*nfp]
@@ -2031,7 +2033,12 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
     for (int r = 0; r < P; ++r) f |= s_fl[le][r];
     if (d_flags) d_flags[e] = f;
-    if (f & 10u) atomicOr(kp.flag_or, f);
+    // every flag reaches the context's word; the atomic is skipped once its
+    // bits are set (a stale read only costs an extra atomic)
+    if (f) {
+      const uint32_t seen = __hip_atomic_load(kp.flag_or, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((seen | f) != seen) atomicOr(kp.flag_or, f);
+    }
   }
 }
 
@@ -2041,6 +2048,123 @@ __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
   constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
   __shared__ UpdateLds<Ph, N, NT> L;
   update_body<Ph, N, EPB, NT>(kp, L, un_g, io, d_flags, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// ------------------------------------------------------------------------
+// k_stats / k_stats_fin: statistics of one step (lwfr_stats).  One thread per
+// element forms sum_p w_p |Omega_e| u_{v,e,p}, min_p P_k(u_{e,p}) and counts
+// its flags and alpha_e bin; each block reduces its elements (lane exchanges
+// in a fixed pattern, then the waves in order) into one row of partials; one
+// block reduces the rows in a fixed order.  The bits of the result therefore
+// do not depend on scheduling.
+// Row layout (doubles): [0, 9) sums per variable, [9, 11) minima, [11, 16)
+// counts ALG1, ALG2, LOW_INADM, NONFINITE, ALG1_GUARD, [16, 27) alpha bins.
+constexpr int kStatsSums = 9, kStatsMins = 2, kStatsCounts = 5, kStatsBins = 11;
+constexpr int kStatsRow = kStatsSums + kStatsMins + kStatsCounts + kStatsBins;
+constexpr int kStatsMin0 = kStatsSums, kStatsCnt0 = kStatsMin0 + kStatsMins, kStatsBin0 = kStatsCnt0 + kStatsCounts;
+
+__device__ inline double wave_reduce_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+// alpha bin: 0 for alpha = 0, k for alpha in ((k-1)/10, k/10]
+__device__ inline int alpha_bin(double a) {
+  if (!(a > 0.0)) return 0;
+  int k = (int)ceil(a * 10.0);
+  return k < 1 ? 1 : (k > 10 ? 10 : k);
+}
+
+template <class Ph, int N>
+__global__ void __launch_bounds__(256) k_stats(const KParams kp, const double* __restrict__ u,
+                                               const uint32_t* __restrict__ eflags, double* __restrict__ rows) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, K = Ph::K, P = ipow(n1, DIM);
+  static_assert(M <= kStatsSums && K <= kStatsMins, "stats row");
+  __shared__ double s_w[kStatsRow][4];
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const bool act = e < kp.E;
+  const PhysParams pp = phys_params(kp, 0.0);
+  double val[kStatsRow];
+#pragma unroll
+  for (int i = 0; i < kStatsRow; ++i) val[i] = 0.0;
+  val[kStatsMin0] = val[kStatsMin0 + 1] = INFINITY;
+  if (act) {
+    const double vol = kp.dx[0] * (DIM == 2 ? kp.dx[1] : 1.0);
+    for (int p = 0; p < P; ++p) {
+      double x[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) x[v] = u[((size_t)v * kp.E + e) * P + p];
+      const double wp = DIM == 1 ? kp.w[p] : kp.w[p % n1] * kp.w[p / n1];
+#pragma unroll
+      for (int v = 0; v < M; ++v) val[v] += wp * x[v];
+#pragma unroll
+      for (int k = 0; k < K; ++k) val[kStatsMin0 + k] = fmin(val[kStatsMin0 + k], Ph::constraint(k, x, pp));
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) val[v] *= vol;
+    const uint32_t f = eflags[e];
+    val[kStatsCnt0 + 0] = (f & 4u) ? 1.0 : 0.0;
+    val[kStatsCnt0 + 1] = (f & 1u) ? 1.0 : 0.0;
+    val[kStatsCnt0 + 2] = (f & 2u) ? 1.0 : 0.0;
+    val[kStatsCnt0 + 3] = (f & 8u) ? 1.0 : 0.0;
+    val[kStatsCnt0 + 4] = (f & 16u) ? 1.0 : 0.0;
+    val[kStatsBin0 + alpha_bin(kp.alpha[e])] = 1.0;
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kStatsRow; ++i) {
+    double r;
+    if (i >= kStatsMin0 && i < kStatsCnt0) r = wave_reduce_min(val[i]);
+    else r = wave_reduce_sum(val[i]);
+    if ((threadIdx.x & 63) == 0) s_w[i][w] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < kStatsRow) {
+    const int i = threadIdx.x;
+    double r = s_w[i][0];
+    for (int k = 1; k < 4; ++k) r = (i >= kStatsMin0 && i < kStatsCnt0) ? fmin(r, s_w[i][k]) : r + s_w[i][k];
+    rows[(size_t)blockIdx.x * kStatsRow + i] = r;
+  }
+}
+
+template <class Stats>
+__global__ void __launch_bounds__(256) k_stats_fin(const KParams kp, const double* __restrict__ rows, int nrows,
+                                                   Stats* __restrict__ out) {
+  __shared__ double s_w[kStatsRow][4];
+  const int w = threadIdx.x >> 6;
+  for (int i = 0; i < kStatsRow; ++i) {
+    const bool mn = i >= kStatsMin0 && i < kStatsCnt0;
+    double r = mn ? INFINITY : 0.0;
+    for (int b = threadIdx.x; b < nrows; b += 256) {
+      const double x = rows[(size_t)b * kStatsRow + i];
+      r = mn ? fmin(r, x) : r + x;
+    }
+    r = mn ? wave_reduce_min(r) : wave_reduce_sum(r);
+    if ((threadIdx.x & 63) == 0) s_w[i][w] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[kStatsRow];
+    for (int i = 0; i < kStatsRow; ++i) {
+      const bool mn = i >= kStatsMin0 && i < kStatsCnt0;
+      double r = s_w[i][0];
+      for (int k = 1; k < 4; ++k) r = mn ? fmin(r, s_w[i][k]) : r + s_w[i][k];
+      t[i] = r;
+    }
+    Stats st;
+    st.dt = kp.scal[0];
+    st.ch = kp.scal[1];
+    for (int v = 0; v < kStatsSums; ++v) st.mass[v] = t[v];
+    for (int k = 0; k < kStatsMins; ++k) st.min_constraint[k] = t[kStatsMin0 + k];
+    for (int b = 0; b < kStatsBins; ++b) st.alpha_hist[b] = (uint32_t)t[kStatsBin0 + b];
+    st.n_alg1 = (uint32_t)t[kStatsCnt0 + 0];
+    st.n_alg2 = (uint32_t)t[kStatsCnt0 + 1];
+    st.n_low_inadm = (uint32_t)t[kStatsCnt0 + 2];
+    st.n_nonfinite = (uint32_t)t[kStatsCnt0 + 3];
+    st.n_alg1_guard = (uint32_t)t[kStatsCnt0 + 4];
+    st.reserved = 0;
+    *out = st;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ u, double* __restrict__ R, size_t n,

@@ -44,7 +44,9 @@ struct lwfr_ctx {
   KParams kp;
   // workspace carving (byte offsets)
   size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr, off_untr,
-      off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, ws_bytes;
+      off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, off_eflags, off_srows,
+      ws_bytes;
+  int nblk_stats = 0;
   // non-periodic sides: k_bfaces threads (0: periodic mesh); Dirichlet sides
   int bface_threads = 0;
   bool dirichlet = false;
@@ -164,7 +166,7 @@ struct TimedLaunch {
 
 template <class Ph, int N, class Tab = Tableau<N>>
 lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
-                        double* d_alpha, uint32_t* d_flags) {
+                        double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats) {
   constexpr int DIM = Ph::DIM, P = ipow(N + 1, DIM), NFP = DIM == 1 ? 1 : N + 1;
   constexpr int EPB = epb_for<N>(DIM, Ph::M);
   const int E = c->E;
@@ -199,8 +201,19 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   if (c->bface_threads > 0)
     LWFR_LAUNCH(KID_BFACES, "k_bfaces", (k_bfaces<Ph, N>), dim3((c->bface_threads + 63) / 64), dim3(64), 0, s, kp,
                 u_in);
+  // statistics need the element flags: the context's own array when the caller takes none
+  uint32_t* eflags = d_stats && !d_flags ? kp.eflags : d_flags;
   LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
-              d_flags);
+              eflags);
+  if (d_stats) {
+    double* rows = kp.stats_rows;
+    hipLaunchKernelGGL((k_stats<Ph, N>), dim3(c->nblk_stats), dim3(256), 0, s, kp, (const double*)u_out,
+                       (const uint32_t*)eflags, rows);
+    LWFR_CHECK_LAUNCH("k_stats");
+    hipLaunchKernelGGL((k_stats_fin<lwfr_stats>), dim3(1), dim3(256), 0, s, kp, (const double*)rows, c->nblk_stats,
+                       d_stats);
+    LWFR_CHECK_LAUNCH("k_stats_fin");
+  }
   return LWFR_OK;
 }
 
@@ -262,40 +275,40 @@ lwfr_status dispatch_adjoint(lwfr_ctx* c, const KParams& kp, const double* u_n, 
 
 template <class Ph>
 lwfr_status launch_step_n(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
-                          double* d_alpha, uint32_t* d_flags) {
+                          double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats) {
   if constexpr (Ph::SRC) {
     const bool ht = (c->cfg.flags & LWFR_CFG_IMEX_HT112) != 0;
     switch (c->N) {
-      case 1: return ht ? launch_step<Ph, 1, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
-                        : launch_step<Ph, 1, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-      case 2: return ht ? launch_step<Ph, 2, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
-                        : launch_step<Ph, 2, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-      case 3: return ht ? launch_step<Ph, 3, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
-                        : launch_step<Ph, 3, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-      case 4: return ht ? launch_step<Ph, 4, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags)
-                        : launch_step<Ph, 4, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 1: return ht ? launch_step<Ph, 1, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
+                        : launch_step<Ph, 1, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 2: return ht ? launch_step<Ph, 2, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
+                        : launch_step<Ph, 2, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 3: return ht ? launch_step<Ph, 3, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
+                        : launch_step<Ph, 3, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 4: return ht ? launch_step<Ph, 4, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
+                        : launch_step<Ph, 4, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
     }
     return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
   } else {
     switch (c->N) {
-      case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-      case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-      case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-      case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+      case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
     }
     return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
   }
 }
 
 lwfr_status dispatch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
-                          double* d_alpha, uint32_t* d_flags) {
+                          double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats = nullptr) {
   switch (c->cfg.equation) {
-    case LWFR_EQ_SW1D: return launch_step_n<SW1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case LWFR_EQ_SW2D: return launch_step_n<SW2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case LWFR_EQ_GLMMHD2D: return launch_step_n<MHD2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case LWFR_EQ_LINADV1D: return launch_step_n<LinAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case LWFR_EQ_VARADV1D: return launch_step_n<VarAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
-    case LWFR_EQ_JINXIN1D: return launch_step_n<JinXin1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags);
+    case LWFR_EQ_SW1D: return launch_step_n<SW1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+    case LWFR_EQ_SW2D: return launch_step_n<SW2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+    case LWFR_EQ_GLMMHD2D: return launch_step_n<MHD2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+    case LWFR_EQ_LINADV1D: return launch_step_n<LinAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+    case LWFR_EQ_VARADV1D: return launch_step_n<VarAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+    case LWFR_EQ_JINXIN1D: return launch_step_n<JinXin1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
   }
   return fail(LWFR_E_UNSUPPORTED, "unknown equation");
 }
@@ -408,6 +421,8 @@ void carve(lwfr_ctx* c, char* b) {
   kp.theta_left = reinterpret_cast<double*>(b + c->off_thl);
   kp.guard_left = reinterpret_cast<uint32_t*>(b + c->off_gul);
   kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
+  kp.eflags = reinterpret_cast<uint32_t*>(b + c->off_eflags);
+  kp.stats_rows = reinterpret_cast<double*>(b + c->off_srows);
   if (c->adjoint) {
     AdjParams& ap = c->ap;
     ap.g_rvol = reinterpret_cast<double*>(b + c->off_grvol);
@@ -740,6 +755,9 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     c->off_gul = take(nbl * sizeof(uint32_t));
   }
   c->off_flag = take(sizeof(uint32_t));
+  c->nblk_stats = (c->E + 255) / 256;
+  c->off_eflags = take((size_t)c->E * sizeof(uint32_t));
+  c->off_srows = take((size_t)c->nblk_stats * kStatsRow * sizeof(double));
   c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
   if (c->adjoint) {
     const size_t nst = (size_t)c->M * c->E * c->P * sizeof(double);
@@ -820,7 +838,7 @@ lwfr_status lwfr_bind(lwfr_ctx* c, void* d_ws, size_t bytes, void* stream) {
 }
 
 lwfr_status lwfr_step(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
-                      double* d_alpha, uint32_t* d_flags) {
+                      double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats) {
   if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
   if (!c->bound) return fail(LWFR_E_STATE, "lwfr_bind has not been called");
   if (!d_u_in || !d_u_out) return fail(LWFR_E_INVALID_ARG, "null state pointer");
@@ -828,10 +846,11 @@ lwfr_status lwfr_step(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double
   if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
   if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
   if (lwfr_status st = dirichlet_ready(c, dt); st != LWFR_OK) return st;
+  if (reinterpret_cast<uintptr_t>(d_stats) % 8 != 0) return fail(LWFR_E_INVALID_ARG, "d_stats not 8-byte aligned");
   KParams kp = c->kp;
   kp.dt_in = dt > 0.0 ? dt : 0.0;
   kp.ch_in = -1.0;
-  return dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, d_alpha, d_flags);
+  return dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, d_alpha, d_flags, d_stats);
 }
 
 lwfr_status lwfr_step_fixed(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double ch,

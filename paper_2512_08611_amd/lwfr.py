@@ -11,7 +11,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # LWFR_LIBRARY selects another build of the same library (e.g. a tuning variant)
 LIBPATH = os.environ.get("LWFR_LIBRARY", os.path.join(_HERE, "liblwfr.so"))
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 LWFR_OK, LWFR_E_INVALID_ARG, LWFR_E_UNSUPPORTED, LWFR_E_HIP = 0, 1, 2, 3
 LWFR_E_INADMISSIBLE, LWFR_E_NONFINITE, LWFR_E_WORKSPACE, LWFR_E_STATE = 4, 5, 6, 7
@@ -56,6 +56,44 @@ class lwfr_config(ctypes.Structure):
     ]
 
 
+class lwfr_stats(ctypes.Structure):
+    """Mirror of lwfr_stats (include/lwfr.h): statistics of one step."""
+    _fields_ = [
+        ("dt", ctypes.c_double),
+        ("ch", ctypes.c_double),
+        ("mass", ctypes.c_double * 9),
+        ("min_constraint", ctypes.c_double * 2),
+        ("alpha_hist", ctypes.c_uint32 * 11),
+        ("n_alg1", ctypes.c_uint32),
+        ("n_alg2", ctypes.c_uint32),
+        ("n_low_inadm", ctypes.c_uint32),
+        ("n_nonfinite", ctypes.c_uint32),
+        ("n_alg1_guard", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+STATS_BYTES = ctypes.sizeof(lwfr_stats)
+
+
+def stats_buffer(device="cuda:0"):
+    """A device buffer for one lwfr_stats (uint8 tensor, 8-byte aligned by the allocator)."""
+    import torch
+
+    return torch.zeros(STATS_BYTES, dtype=torch.uint8, device=device)
+
+
+def read_stats(buf):
+    """Host dict of an lwfr_stats held in the device tensor buf (synchronising copy)."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    st = lwfr_stats.from_buffer_copy(raw)
+    return {
+        "dt": st.dt, "ch": st.ch, "mass": list(st.mass), "min_constraint": list(st.min_constraint),
+        "alpha_hist": list(st.alpha_hist), "n_alg1": st.n_alg1, "n_alg2": st.n_alg2,
+        "n_low_inadm": st.n_low_inadm, "n_nonfinite": st.n_nonfinite, "n_alg1_guard": st.n_alg1_guard,
+    }
+
+
 _lib = None
 _SIGS = {
     "lwfr_init": [ctypes.POINTER(lwfr_config), ctypes.POINTER(ctypes.c_void_p)],
@@ -68,7 +106,7 @@ _SIGS = {
     "lwfr_boundary_data_size": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
     "lwfr_set_boundary_data": [ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
-                  ctypes.c_void_p, ctypes.c_void_p],
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_step_fixed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                         ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_residual": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p],
@@ -211,8 +249,10 @@ def lwfr_set_boundary_data(ctx, ghost):
     _check(lib().lwfr_set_boundary_data(ctx, _ptr(ghost)))
 
 
-def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
-    _check(lib().lwfr_step(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(alpha), _ptr(flags)))
+def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None, stats=None):
+    """stats: nullable device buffer of STATS_BYTES (stats_buffer()); read it with read_stats."""
+    _check(lib().lwfr_step(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(alpha), _ptr(flags),
+                           _ptr(stats)))
 
 
 def lwfr_step_fixed(ctx, u_in, u_out, dt, ch, alpha=None, flags=None):
@@ -312,8 +352,8 @@ class Stepper:
         self.ghost = ghost  # the library reads it at every step
         lwfr_set_boundary_data(self.ctx, ghost)
 
-    def step(self, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None):
-        lwfr_step(self.ctx, u_in, u_out, dt, dt_ch, alpha, flags)
+    def step(self, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None, stats=None):
+        lwfr_step(self.ctx, u_in, u_out, dt, dt_ch, alpha, flags, stats)
 
     def step_fixed(self, u_in, u_out, dt, ch, alpha=None, flags=None):
         lwfr_step_fixed(self.ctx, u_in, u_out, dt, ch, alpha, flags)

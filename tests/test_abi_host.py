@@ -62,7 +62,7 @@ def test_init_validation():
 
 def test_step_before_bind_is_a_state_error():
     ctx = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 10))
-    st = lwfr.lib().lwfr_step(ctx, ctypes.c_void_p(256), ctypes.c_void_p(4096), 0.0, None, None, None)
+    st = lwfr.lib().lwfr_step(ctx, ctypes.c_void_p(256), ctypes.c_void_p(4096), 0.0, None, None, None, None)
     assert st == lwfr.LWFR_E_STATE
     assert "bind" in lwfr.lwfr_last_error()
     st = lwfr.lib().lwfr_bind(ctx, None, 0, None)
@@ -224,3 +224,21 @@ def test_alw_validation():
     assert lwfr.lib().lwfr_batch_init(arr, 1, ctypes.byref(h)) == lwfr.LWFR_E_UNSUPPORTED
     # the same Fourier limit as the cRK stages
     assert lwfr.lwfr_cfl_number(3, A) == lwfr.lwfr_cfl_number(3)
+
+
+def test_stats_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of lwfr_stats has the header's size and field offsets
+    (a C program compiled against include/lwfr.h prints them)."""
+    import subprocess
+
+    fields = [f[0] for f in lwfr.lwfr_stats._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("%zu\\n", offsetof(lwfr_stats, {f}));\n' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lwfr.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(lwfr_stats));\n' + body + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(lwfr.lwfr_stats)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(lwfr.lwfr_stats, f).offset == off, f
