@@ -50,6 +50,7 @@ class OraCfg(ctypes.Structure):
         ("relax_a", ctypes.c_double), ("relax_eps", ctypes.c_double),
         ("relax_l", ctypes.c_double), ("relax_q", ctypes.c_double),
         ("alw", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
     ]
 
 
@@ -71,7 +72,7 @@ BC_PERIODIC, BC_OUTFLOW, BC_WALL, BC_DIRICHLET = 0, 1, 2, 3
 
 def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gravity=9.81, cs=0.9,
              cfl=None, blending=2, alpha_max=0.5, alpha_min=1e-3, alpha_force=-1.0, gll=False,
-             bc=(0, 0, 0, 0), imex=0, relax=(3.0, 1e-2, 0.0, 1.0), alw=False):
+             bc=(0, 0, 0, 0), imex=0, relax=(3.0, 1e-2, 0.0, 1.0), alw=False, threads=1):
     """gll: Gauss-Lobatto-Legendre solution points with the g_2 correction (App. B)
     instead of Gauss-Legendre points with the Radau correction.
     bc: boundary kinds of the sides (x lo, x hi, y lo, y hi), BC_* (periodic by
@@ -81,7 +82,9 @@ def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gra
     f(u) = l u + q u^2/2 (Burgers by default).
     alw: time averages by the approximate Lax-Wendroff procedure (finite
     differences in time along Taylor states) instead of the cRK stages.
-    cfl=None takes the Fourier limit of the scheme these select."""
+    cfl=None takes the Fourier limit of the scheme these select.
+    threads: OpenMP threads of the element and face loops (the results are the
+    same bits for any count)."""
     c = OraCfg()
     c.eq, c.N, c.nx, c.ny = eq, N, nx, (ny if DIMS[eq] == 2 else 1)
     c.lo[0], c.lo[1] = lo
@@ -96,6 +99,7 @@ def make_cfg(eq, N, nx, ny=1, lo=(0.0, 0.0), hi=(1.0, 1.0), gamma=5.0 / 3.0, gra
     c.imex = imex
     c.relax_a, c.relax_eps, c.relax_l, c.relax_q = relax
     c.alw = 1 if alw else 0
+    c.threads = threads
     return c
 
 
@@ -290,3 +294,30 @@ def face(c, d, side_m, side_p, af, dt, ch=0.0):
                         ctypes.c_double(ch), _p(Fm), _p(Fp), ctypes.byref(th), ctypes.byref(g))
     assert rc == 0, rc
     return Fm, Fp, th.value, g.value
+
+
+def vjp(c, u, lam, dt, ch, threads=0):
+    """J^T lam of the step with dt, c_h, alpha and every theta frozen at their values at u
+    (reverse mode, oracle/reverse.hpp); threads <= 0: the OpenMP default."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
+    lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(shape(c))
+    mu = np.zeros_like(u)
+    rc = lib().ora_vjp(ctypes.byref(c), _p(u), _p(lam), ctypes.c_double(dt), ctypes.c_double(ch), _p(mu),
+                       ctypes.c_int(threads))
+    assert rc == 0, rc
+    return mu
+
+
+def run(c, u0, nsteps, save_at=()):
+    """The oracle's own run of nsteps steps from u0 (dt from eq. time.step.2d each step):
+    {k: state before step k for k in save_at (k = nsteps: the final state)}, and the
+    (nsteps, 2) array of each step's (dt, c_h)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(shape(c))
+    save_at = sorted(set(int(k) for k in save_at))
+    saved = np.zeros((len(save_at),) + u0.shape)
+    at = np.array(save_at, dtype=np.int32)
+    dtch = np.zeros((nsteps, 2))
+    rc = lib().ora_run(ctypes.byref(c), _p(u0), int(nsteps), len(save_at), _p(at, ctypes.c_int32), _p(saved),
+                       _p(dtch))
+    assert rc == 0, rc
+    return {k: saved[i] for i, k in enumerate(save_at)}, dtch

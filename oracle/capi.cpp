@@ -5,6 +5,7 @@
 #include <cstring>
 #include <vector>
 
+#include "reverse.hpp"
 #include "scheme.hpp"
 
 using namespace ora;
@@ -22,6 +23,7 @@ struct ora_cfg {
   int32_t imex;         // IMEX pair of a system with a source: 1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)
   double relax_a, relax_eps, relax_l, relax_q;  // Jin-Xin a, eps and f(u) = l u + q u^2/2
   int32_t alw;          // 1: approximate Lax-Wendroff time averages
+  int32_t threads;      // threads of the element and face loops (results do not depend on it)
 };
 
 static Config to_cfg(const ora_cfg* c) {
@@ -40,6 +42,7 @@ static Config to_cfg(const ora_cfg* c) {
   k.relax_l = c->relax_l;
   k.relax_q = c->relax_q;
   k.alw = c->alw;
+  k.threads = c->threads;
   return k;
 }
 
@@ -246,6 +249,39 @@ int ora_face(const ora_cfg* c, int d, const double* side_m, const double* side_p
   }, false);
 }
 
+// nsteps steps from u0 with dt from eq. time.step.2d each step (the oracle's own
+// run); the state before step k is written to saved[i] for save_at[i] == k
+// (k = nsteps: the final state), and each step's {dt, c_h} to dt_ch (nsteps x 2,
+// nullable).  The step buffers are kept over the run.
+int ora_run(const ora_cfg* c, const double* u0, int nsteps, int nsave, const int* save_at, double* saved,
+            double* dt_ch) {
+  if (nsteps < 0 || nsave < 0) return 1;
+  return dispatch(c, [&](auto& s) {
+    using S = std::decay_t<decltype(s)>;
+    const size_t n = (size_t)s.M * s.E * s.P;
+    std::vector<double> a(u0, u0 + n), b(n);
+    typename S::template Local<double> L;
+    typename S::template Faces<double> Fc;
+    auto save = [&](int k) {
+      for (int i = 0; i < nsave; ++i)
+        if (save_at[i] == k) std::memcpy(saved + (size_t)i * n, a.data(), n * sizeof(double));
+    };
+    for (int k = 0; k < nsteps; ++k) {
+      save(k);
+      double dt, ch;
+      s.dt_ch(a.data(), dt, ch);
+      std::vector<double> araw, alpha;
+      std::vector<uint8_t> t;
+      s.indicator(a.data(), araw, alpha, t);
+      s.template step<double>(a.data(), b.data(), dt, ch, alpha, nullptr, nullptr, nullptr, nullptr, nullptr, &L,
+                              &Fc);
+      if (dt_ch) { dt_ch[2 * k] = dt; dt_ch[2 * k + 1] = ch; }
+      std::swap(a, b);
+    }
+    save(nsteps);
+  });
+}
+
 // Element-local time averages of one step (the stages, or the approximate LW
 // procedure with cfg alw): F [d][v][e][p], U [v][e][p], B^loc [v][e][p].
 int ora_time_averages(const ora_cfg* c, const double* u, double dt, double ch, double* F, double* U, double* Bl) {
@@ -292,6 +328,24 @@ int ora_jvp(const ora_cfg* c, const double* u, const double* v, double dt, doubl
     for (size_t i = 0; i < n; ++i) x[i] = Dual(u[i], v[i]);
     s.template step<Dual>(x.data(), y.data(), dt, ch, alpha, nullptr, nullptr, nullptr);
     for (size_t i = 0; i < n; ++i) { if (unew) unew[i] = y[i].v; Jv[i] = y[i].d; }
+  });
+}
+
+// Reverse-mode derivative of the step (oracle/reverse.hpp): mu = J^T lam with
+// dt, c_h, every alpha_e and every theta held at their values at u (frozen
+// switches, as ora_jvp).  nthreads <= 0: the default OpenMP thread count.
+// Periodic meshes, systems without a source, the cRK stages (returns 4 otherwise).
+int ora_vjp(const ora_cfg* c, const double* u, const double* lam, double dt, double ch, double* mu, int nthreads) {
+  if (c->alw || c->eq == EQ_JINXIN1D) return 4;
+  for (int i = 0; i < 4; ++i)
+    if (c->bc[i] != BC_PERIODIC) return 4;
+  return dispatch(c, [&](auto& s) {
+    using Phys = std::decay_t<decltype(s.ph)>;
+    std::vector<double> araw, alpha;
+    std::vector<uint8_t> t;
+    s.indicator(u, araw, alpha, t);
+    StepAdjoint<Phys> adj(s);
+    adj.vjp(u, dt, ch, alpha, lam, mu, nthreads);
   });
 }
 

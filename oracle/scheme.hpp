@@ -45,6 +45,10 @@ struct Config {
   int gll = 0;         // 1: Gauss-Lobatto-Legendre solution points with g_2 correction (App. B)
   int imex = 0;        // IMEX pair of a system with a source (tableau.hpp): 1 HT(1,1,2), 2 SSP3-IMEX(4,3,3)
   int alw = 0;         // 1: time averages by the approximate Lax-Wendroff procedure (stages_alw)
+  // threads of the element and face loops (OpenMP; 1 = serial).  Every element's
+  // and face's arithmetic is the same for any count, and each writes only its
+  // own entries, so results are bit for bit the same.
+  int threads = 1;
   // Jin-Xin characteristic speed a, relaxation time eps, f(u) = l u + q u^2/2
   double relax_a = 3.0, relax_eps = 1e-2, relax_l = 0.0, relax_q = 1.0;
   // boundary condition of side (d, s): BC_PERIODIC, BC_OUTFLOW (the ghost copies
@@ -98,6 +102,8 @@ struct Scheme {
     dx[1] = DIM == 1 ? 1.0 : (c.hi[1] - c.lo[1]) / ny;
   }
 
+  int nthreads() const { return cfg.threads > 0 ? cfg.threads : 1; }
+
   // ---------------------------------------------------------------- mesh ---
   size_t idx(int v, int e, int p) const { return ((size_t)v * E + e) * P + p; }
   // neighbour across the upper (side=1) or lower (side=0) face in direction d
@@ -136,14 +142,15 @@ struct Scheme {
   // speeds; dt = C_s CFL(N) / Lambda (eq. time.step.2d).  For GLM-MHD c_h is the
   // largest value whose waves |v_d| + max(c_f, c_h) leave Lambda unchanged.
   void dt_ch(const double* u, double& dt, double& ch) const {
-    std::vector<double> ub(M);
     double Lam = 0;
+#pragma omp parallel for num_threads(nthreads()) schedule(static) reduction(max : Lam)
     for (int e = 0; e < E; ++e) {
-      mean(u, e, ub.data());
+      double ub[M];
+      mean(u, e, ub);
       double s = 0;
       for (int d = 0; d < DIM; ++d) {
         double av, c;
-        ph.speeds(d, ub.data(), av, c);
+        ph.speeds(d, ub, av, c);
         s += (av + c) / dx[d];
       }
       Lam = std::max(Lam, s);
@@ -152,10 +159,12 @@ struct Scheme {
     ch = 0.0;
     if (cfg.eq == EQ_MHD2D) {
       double best = INFINITY;
+#pragma omp parallel for num_threads(nthreads()) schedule(static) reduction(min : best)
       for (int e = 0; e < E; ++e) {
-        mean(u, e, ub.data());
+        double ub[M];
+        mean(u, e, ub);
         double av[2], c[2];
-        for (int d = 0; d < 2; ++d) ph.speeds(d, ub.data(), av[d], c[d]);
+        for (int d = 0; d < 2; ++d) ph.speeds(d, ub, av[d], c[d]);
         double wx = 1.0 / dx[0], wy = 1.0 / dx[1];
         double R = Lam - (av[0] * wx + av[1] * wy);
         // largest c with wx max(c_x, c) + wy max(c_y, c) <= R
@@ -181,8 +190,9 @@ struct Scheme {
     if (cfg.blending == 0 || N == 0) return;
     const double T = 0.5 * std::pow(10.0, -1.8 * std::pow(N + 1.0, 0.25));
     const double s = std::log(9999.0);
-    std::vector<double> q(P), mode(P), ue(M);
+#pragma omp parallel for num_threads(nthreads()) schedule(static)
     for (int e = 0; e < E; ++e) {
+      std::vector<double> q(P), ue(M);
       for (int p = 0; p < P; ++p) {
         for (int v = 0; v < M; ++v) ue[v] = u[idx(v, e, p)];
         q[p] = ph.indicator(ue.data());
@@ -241,21 +251,60 @@ struct Scheme {
     return ((((size_t)d * 2 + side) * M + v) * E + e) * nfp + q;
   }
 
+  // the arrays of the element-local phase, zero
+  // (the stage loop zeroes each element's entries before it accumulates them;
+  // every trace entry is written by the face traces)
+  template <class T>
+  void alloc_local(Local<T>& L) const {
+    L.F.resize((size_t)DIM * M * E * P);
+    L.U.resize((size_t)M * E * P);
+    L.Bl.resize((size_t)M * E * P);
+    L.Fnc.resize((size_t)DIM * 2 * M * E * nfp);
+    L.Ftr.resize(L.Fnc.size());
+    L.Utr.resize(L.Fnc.size());
+    L.untr.resize(L.Fnc.size());
+    L.S.resize(Phys::SRC ? (size_t)M * E * P : 0);
+  }
+  // scratch of the stage loop of one element
+  template <class T>
+  struct StageScratch {
+    std::vector<T> Lst, uj, f, Sst, a, fo, w, o, du, nc;
+    explicit StageScratch(const Scheme& S)
+        : Lst((size_t)S.tb.s * M * S.P), uj((size_t)M * S.P), f((size_t)DIM * M * S.P),
+          Sst(Phys::SRC ? (size_t)S.tb.s * M * S.P : 0), a(M), fo(M), w(M), o(M), du(M), nc(M) {}
+  };
+
   template <class T>
   void stages(const T* un, double dt, double ch, Local<T>& L) const {
+    alloc_local(L);
+#pragma omp parallel num_threads(nthreads())
+    {
+      StageScratch<T> W(*this);
+#pragma omp for schedule(static)
+      for (int e = 0; e < E; ++e) stages_elem(un, dt, ch, L, e, W);
+    }
+  }
+
+  // the stages and time averages of element e (L's entries of e accumulate from zero)
+  template <class T>
+  void stages_elem(const T* un, double dt, double ch, Local<T>& L, int e, StageScratch<T>& W) const {
     const int s = tb.s;
-    L.F.assign((size_t)DIM * M * E * P, T(0.0));
-    L.U.assign((size_t)M * E * P, T(0.0));
-    L.Bl.assign((size_t)M * E * P, T(0.0));
-    L.Fnc.assign((size_t)DIM * 2 * M * E * nfp, T(0.0));
-    L.Ftr.assign(L.Fnc.size(), T(0.0));
-    L.Utr.assign(L.Fnc.size(), T(0.0));
-    L.untr.assign(L.Fnc.size(), T(0.0));
-    L.S.assign(Phys::SRC ? (size_t)M * E * P : 0, T(0.0));
-    std::vector<T> Lst((size_t)s * M * P), uj((size_t)M * P), f((size_t)DIM * M * P);
-    std::vector<T> Sst(Phys::SRC ? (size_t)s * M * P : 0);
-    std::vector<T> a(M), fo(M), w(M), o(M), du(M), nc(M);
-    for (int e = 0; e < E; ++e) {
+    std::vector<T>& Lst = W.Lst;
+    std::vector<T>& uj = W.uj;
+    std::vector<T>& f = W.f;
+    std::vector<T>& Sst = W.Sst;
+    std::vector<T>& a = W.a;
+    std::vector<T>& fo = W.fo;
+    std::vector<T>& du = W.du;
+    std::vector<T>& nc = W.nc;
+    for (int v = 0; v < M; ++v)
+      for (int p = 0; p < P; ++p) {
+        L.U[idx(v, e, p)] = T(0.0);
+        L.Bl[idx(v, e, p)] = T(0.0);
+        if constexpr (Phys::SRC) L.S[idx(v, e, p)] = T(0.0);
+        for (int d = 0; d < DIM; ++d) L.F[(size_t)d * M * E * P + idx(v, e, p)] = T(0.0);
+      }
+    {
       for (int j = 0; j < s; ++j) {
         // inner stage u^(j) = u^n - dt sum_{k<j} a_jk L^(k) (sum over the tableau's non-zero a_jk)
         for (int v = 0; v < M; ++v)
@@ -466,8 +515,15 @@ struct Scheme {
   // traces of F_d, U and u^n at the faces, and F^nc
   template <class T>
   void face_traces(const T* un, Local<T>& L) const {
-    std::vector<T> a(M), w(M), o(M);
-    for (int e = 0; e < E; ++e) {
+#pragma omp parallel for num_threads(nthreads()) schedule(static)
+    for (int e = 0; e < E; ++e) face_traces_elem(un, L, e);
+  }
+
+  // the face traces and F^nc of element e
+  template <class T>
+  void face_traces_elem(const T* un, Local<T>& L, int e) const {
+    T a[M], w[M], o[M];
+    {
       for (int d = 0; d < DIM; ++d)
         for (int side = 0; side < 2; ++side) {
           const std::vector<double>& V = side ? re.VR : re.VL;
@@ -492,7 +548,7 @@ struct Scheme {
               a[v] = L.untr[tidx(d, side, v, e, q)];
               w[v] = L.Utr[tidx(d, side, v, e, q)];
             }
-            ph.ncprod(d, a.data(), w.data(), o.data());
+            ph.ncprod(d, a, w, o);
             for (int v = 0; v < M; ++v) L.Fnc[tidx(d, side, v, e, q)] = o[v];
           }
         }
@@ -591,17 +647,31 @@ struct Scheme {
   template <class T>
   void faces(const T* un, const Local<T>& L, const std::vector<double>& alpha, double dt, double ch,
              Faces<T>& Fc) const {
-    Fc.Fm.assign((size_t)DIM * M * E * nfp, T(0.0));
-    Fc.Fp.assign(Fc.Fm.size(), T(0.0));
+    alloc_faces(Fc);
+#pragma omp parallel for num_threads(nthreads()) schedule(static)
+    for (int de = 0; de < DIM * E; ++de) faces_line(un, L, alpha, dt, ch, Fc, de / E, de % E);
+  }
+
+  // (every face line writes its F^- and, inside the mesh, its F^+)
+  template <class T>
+  void alloc_faces(Faces<T>& Fc) const {
+    Fc.Fm.resize((size_t)DIM * M * E * nfp);
+    Fc.Fp.resize(Fc.Fm.size());
     Fc.FpLeft.assign(Fc.Fm.size(), T(0.0));
     Fc.theta.assign((size_t)DIM * E * nfp, 1.0);
     Fc.guard.assign((size_t)DIM * E * nfp, 0);
     Fc.thetaLeft.assign((size_t)DIM * E * nfp, 1.0);
     Fc.guardLeft.assign((size_t)DIM * E * nfp, 0);
+  }
+
+  // the face points of the face in direction d on the upper side of element e
+  // (and, on a non-periodic direction's last element, the opposite boundary half face)
+  template <class T>
+  void faces_line(const T* un, const Local<T>& L, const std::vector<double>& alpha, double dt, double ch,
+                  Faces<T>& Fc, int d, int e) const {
     Side<T> mi, pl;
     T Fm[M], Fp[M];
-    for (int d = 0; d < DIM; ++d)
-      for (int e = 0; e < E; ++e) {
+    {
         int en = nbr(e, d, 1);
         for (int q = 0; q < nfp; ++q) {
           size_t fi = ((size_t)d * E + e) * nfp + q;
@@ -721,9 +791,26 @@ struct Scheme {
   void update(const T* un, const Local<T>& L, const Faces<T>& Fc, const std::vector<double>& alpha,
               double dt, double ch, T* unew, uint32_t* flags, double* theta_elem, T* uL_out = nullptr,
               T* ustar_out = nullptr) const {
-    std::vector<T> uH((size_t)M * P), uL((size_t)M * P), us((size_t)M * P);
+#pragma omp parallel num_threads(nthreads())
+    {
+      std::vector<T> W((size_t)3 * M * P);
+#pragma omp for schedule(static)
+      for (int e = 0; e < E; ++e)
+        update_elem(un, L, Fc, alpha, dt, ch, unew, flags, theta_elem, uL_out, ustar_out, e, W);
+    }
+  }
+
+  // the update of element e; W: scratch of 3 M P values
+  template <class T>
+  void update_elem(const T* un, const Local<T>& L, const Faces<T>& Fc, const std::vector<double>& alpha,
+                   double dt, double ch, T* unew, uint32_t* flags, double* theta_elem, T* uL_out, T* ustar_out,
+                   int e, std::vector<T>& W) const {
+    T* uH = W.data();
+    T* uL = W.data() + (size_t)M * P;
+    T* us = W.data() + (size_t)2 * M * P;
+    const size_t nMP = (size_t)M * P;
     T x0[M], x1[M], fm[M], fp[M], tmp[M];
-    for (int e = 0; e < E; ++e) {
+    {
       uint32_t fl = 0;
       // faces of this element: Alg. 1 activity
       for (int d = 0; d < DIM; ++d)
@@ -795,7 +882,7 @@ struct Scheme {
         }
         // blend (eq. blended.scheme)
         double al = alpha[e];
-        for (size_t i = 0; i < us.size(); ++i) us[i] = T(1.0 - al) * uH[i] + T(al) * uL[i];
+        for (size_t i = 0; i < nMP; ++i) us[i] = T(1.0 - al) * uH[i] + T(al) * uL[i];
         for (int v = 0; v < M; ++v)
           for (int p = 0; p < P; ++p) {
             if (uL_out) uL_out[idx(v, e, p)] = uL[(size_t)v * P + p];
@@ -821,7 +908,7 @@ struct Scheme {
               double Pb = val(ph.constraint(k, z));
               th = std::min(th, theta_concave(eps, Pa, Pb, guard));
             }
-            for (size_t i = 0; i < us.size(); ++i) us[i] = T(th) * us[i] + T(1.0 - th) * uL[i];
+            for (size_t i = 0; i < nMP; ++i) us[i] = T(th) * us[i] + T(1.0 - th) * uL[i];
             Theta *= th;
           }
         }
@@ -838,11 +925,15 @@ struct Scheme {
   }
 
   // full step for scalar type T with dt, c_h and alpha given (frozen)
+  // Lp, Fcp (nullable): buffers kept by the caller over several steps
   template <class T>
   void step(const T* un, T* unew, double dt, double ch, const std::vector<double>& alpha, uint32_t* flags,
-            double* theta_face, double* theta_elem, T* uL_out = nullptr, T* ustar_out = nullptr) const {
-    Local<T> L;
-    Faces<T> Fc;
+            double* theta_face, double* theta_elem, T* uL_out = nullptr, T* ustar_out = nullptr,
+            Local<T>* Lp = nullptr, Faces<T>* Fcp = nullptr) const {
+    Local<T> Lo;
+    Faces<T> Fco;
+    Local<T>& L = Lp ? *Lp : Lo;
+    Faces<T>& Fc = Fcp ? *Fcp : Fco;
     if (cfg.alw) stages_alw(un, dt, ch, L);
     else stages(un, dt, ch, L);
     face_traces(un, L);

@@ -37,7 +37,8 @@ def sw2d_state(xi, n, seed):
 
 
 def make_batch(specs, stream, **kw):
-    cfgs = [lwfr.make_config(lwfr.LWFR_EQ_SW2D, N, (n, n), **kw) for n, N in specs]
+    # the oracle's CFL numbers, so that the oracle and the GPU take the same dt rule
+    cfgs = [lwfr.make_config(lwfr.LWFR_EQ_SW2D, N, (n, n), cfl_number=oracle.cfl_number(N), **kw) for n, N in specs]
     return lwfr.Batch(cfgs, DEV, stream=stream), cfgs
 
 
@@ -98,7 +99,7 @@ def test_batch_against_oracle(stream):
     b.step(u, out, dt)
     torch.cuda.synchronize()
     for i, (n, N) in enumerate(MIXED):
-        oc = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, cs=0.9, cfl=lwfr.lwfr_cfl_number(N), blending=2)
+        oc = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, cs=0.9, cfl=oracle.cfl_number(N), blending=2)
         o = oracle.step(oc, states[i])
         g = b.view(out, i).cpu().numpy()
         assert abs(float(dt[i]) - o["dt"]) <= 1e-13 * o["dt"]
@@ -263,7 +264,7 @@ def test_full_size_batch_64_problems(stream):
     order = sorted(range(len(specs)), key=lambda i: specs[i][0] ** 2 * (specs[i][1] + 1) ** 2)[:3]
     for i in order:
         n, N = specs[i]
-        oc = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, cs=0.9, cfl=lwfr.lwfr_cfl_number(N), blending=2)
+        oc = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, cs=0.9, cfl=oracle.cfl_number(N), blending=2)
         o = oracle.step(oc, states[i])
         g = b.view(out, i).cpu().numpy()
         scale = np.maximum(np.abs(o["u"]), 1e-2 * np.abs(states[i]).max())

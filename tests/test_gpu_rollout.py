@@ -10,9 +10,19 @@ recipe with seed 1; loss J = 1/2 sum_e sum_pq w_p w_q dx dy (rho^20 - rho*)^2.
     difference of the two losses is formed as 1/2 sum w (rho+ - rho-)(rho+ +
     rho- - 2 rho*), which is the same number without cancellation;
   * on an 8x8 mesh, the adjoint gradient against the oracle's forward-mode
-    derivative chained through the 20 steps (dot products, relative 1e-9).
+    derivative chained through the 20 steps (dot products, relative 1e-9);
+  * the whole gradient lambda^0, value by value, against the oracle's reverse
+    mode (oracle/reverse.hpp) chained backwards through the oracle's own 20
+    steps, with the oracle's own target: |g - lambda| <= 1e-7 max(|lambda|,
+    1e-3 max|lambda|) for every solution point and variable (the largest over
+    all variables sets the floor: the gradient of a variable three orders
+    below the largest is a cancellation residual of the larger terms, and the
+    two runs' states differ at 1e-12), on the smooth
+    workload and on moving blocky data where the subcell blend and the
+    limiters act.  No oracle input comes from the GPU.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -27,7 +37,8 @@ DEV = "cuda:0"
 
 
 def setup(n, N=3, steps=20):
-    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), blending=2, flags=lwfr.LWFR_CFG_ADJOINT)
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), blending=2, cfl_number=oracle.cfl_number(N),
+                           flags=lwfr.LWFR_CFG_ADJOINT)
     st = lwfr.Stepper(cfg, DEV)
     xi = np.array(st.xi)
     u0 = torch.tensor(W.mhd_smooth(xi, n, n, seed=0), dtype=torch.float64, device=DEV)
@@ -92,11 +103,12 @@ def test_rollout_gradient_vs_oracle_forward_mode():
     J = loss_of(rollout.rollout(x, st, steps, every=5), target, wq)
     J.backward()
     g = x.grad.detach().cpu().numpy()
-    oc = oracle.make_cfg(oracle.EQ_MHD2D, N, n, n, blending=2, cfl=lwfr.lwfr_cfl_number(N))
+    oc = oracle.make_cfg(oracle.EQ_MHD2D, N, n, n, blending=2, cfl=oracle.cfl_number(N))
     rng = np.random.default_rng(5)
     u0n = u0.cpu().numpy()
-    tgt = target.cpu().numpy()
-    wqn = wq.cpu().numpy()
+    xi = oracle.refel(N)["xi"]
+    tgt = oracle.run(oc, W.mhd_smooth(xi, n, n, seed=1), steps, save_at=(steps,))[0][steps][0]
+    wqn = np.outer(oracle.refel(N)["w"], oracle.refel(N)["w"]).reshape(-1) / (n * n)
     for _ in range(3):
         v = rng.normal(size=u0n.shape) * np.sqrt(np.mean(u0n ** 2, axis=(1, 2), keepdims=True))
         u, dv = u0n.copy(), v.copy()
@@ -106,3 +118,70 @@ def test_rollout_gradient_vs_oracle_forward_mode():
         ref = float(np.sum(wqn * (u[0] - tgt) * dv[0]))
         got = float(np.sum(g * v))
         assert abs(ref - got) <= 1e-9 * abs(ref), (ref, got)
+
+
+def _threads():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def blocky_moving(xi, n, seed):
+    """Blocky data in motion: the 16x16-block recipe's density, pressure and field,
+    velocities and psi per block, and a 1e-3 relative jitter per node (no exact
+    tie between the two face states of a max, where either one-sided derivative
+    is valid)."""
+    rng = np.random.default_rng(seed)
+    u = W.mhd_blocky(xi, n, n, seed=seed, nblocks=8)
+    gam = 5.0 / 3.0
+    p = (gam - 1) * (u[4] - 0.5 * (u[5] ** 2 + u[6] ** 2 + u[7] ** 2))
+    u[1:4] = 0.3 * rng.uniform(-1, 1, (3, u.shape[1], 1)) * u[0:1]
+    u[8] = 0.05 * rng.uniform(-1, 1, (u.shape[1], 1))
+    for v in (0, 1, 2, 3, 5, 6, 7, 8):
+        u[v] = u[v] * (1 + 1e-3 * rng.uniform(-1, 1, u[v].shape)) + 1e-4 * rng.uniform(-1, 1, u[v].shape)
+    u[4] = p / (gam - 1) + 0.5 * (u[1] ** 2 + u[2] ** 2 + u[3] ** 2) / u[0] \
+        + 0.5 * (u[5] ** 2 + u[6] ** 2 + u[7] ** 2) + 0.5 * u[8] ** 2
+    return u
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kind", ["smooth", "blocky"])
+def test_rollout_gradient_per_value_vs_oracle_reverse_mode(kind):
+    n, N, steps, every = 128, 3, 20, 5
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, N, (n, n), blending=2, cfl_number=oracle.cfl_number(N),
+                           flags=lwfr.LWFR_CFG_ADJOINT)
+    st = lwfr.Stepper(cfg, DEV)
+    xi = oracle.refel(N)["xi"]
+    w = oracle.refel(N)["w"]
+    if kind == "smooth":
+        u0n, utn = W.mhd_smooth(xi, n, n, seed=0), W.mhd_smooth(xi, n, n, seed=1)
+    else:
+        u0n, utn = blocky_moving(xi, n, 0), blocky_moving(xi, n, 1)
+    wqn = np.outer(w, w).reshape(-1) / (n * n)
+    # GPU: rollout with checkpoints, its own target
+    u0 = torch.tensor(u0n, dtype=torch.float64, device=DEV)
+    with torch.no_grad():
+        tg = rollout.LwfrRollout.apply(torch.tensor(utn, dtype=torch.float64, device=DEV), st, steps, every)[0]
+    x = u0.clone().requires_grad_(True)
+    loss_of(rollout.rollout(x, st, steps, every=every), tg.clone(), torch.tensor(wqn, device=DEV)).backward()
+    g = x.grad.detach().cpu().numpy()
+    fl = torch.zeros(n * n, dtype=torch.int32, device=DEV)
+    al = torch.zeros(n * n, dtype=torch.float64, device=DEV)
+    st.step(u0, torch.empty_like(u0), 0.0, None, al, fl)
+    print(f"ROLLOUT {kind}: blended elements at step 0: {int((al > 0).sum())}, limited: "
+          f"{int(((fl & (lwfr.LWFR_FLAG_ALG1 | lwfr.LWFR_FLAG_ALG2)) != 0).sum())}", flush=True)
+    # oracle: its own run, its own target, its reverse mode step by step backwards
+    oc = oracle.make_cfg(oracle.EQ_MHD2D, N, n, n, blending=2, cfl=oracle.cfl_number(N), threads=_threads())
+    tgt = oracle.run(oc, utn, steps, save_at=(steps,))[0][steps][0]
+    states, dtch = oracle.run(oc, u0n, steps, save_at=range(steps + 1))
+    lam = np.zeros_like(u0n)
+    lam[0] = wqn * (states[steps][0] - tgt)
+    for k in reversed(range(steps)):
+        lam = oracle.vjp(oc, states[k], lam, dtch[k, 0], dtch[k, 1], threads=_threads())
+    err = np.abs(g - lam) / np.maximum(np.abs(lam), 1e-3 * np.abs(lam).max())
+    per_var = [float((np.abs(g[v] - lam[v]) / np.maximum(np.abs(lam[v]), 1e-3 * np.abs(lam[v]).max())).max())
+               for v in range(lam.shape[0])]
+    print(f"ROLLOUT {kind}: max per-value difference {err.max():.2e} (relative), "
+          f"{np.abs(g - lam).max():.2e} absolute, |lambda|max {np.abs(lam).max():.2e}, per variable with its own "
+          f"floor [{', '.join(f'{x:.1e}' for x in per_var)}]", flush=True)
+    assert err.max() <= 1e-7
+    if kind == "blocky":
+        assert int((al > 0).sum()) > 0
