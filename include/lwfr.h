@@ -226,6 +226,25 @@ lwfr_status lwfr_bind(lwfr_ctx* ctx, void* d_workspace, size_t bytes, void* stre
 lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
                       double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): one step as
+ * lwfr_step with d_alpha and d_stats NULL, whose workspace is a static device
+ * array of the library, LWFR_STATIC_SCRATCH_BYTES on each GPU it runs on (held
+ * until the process ends), instead of the bound workspace.  The context needs
+ * no lwfr_bind; the work is enqueued on hip_stream (hipStream_t as void*, NULL
+ * = the default stream) on the current device, whose array address is resolved
+ * by the first call on that device (make that first call outside a graph
+ * capture).  The call allocates nothing.  Every array the step reads from the
+ * scratch is written earlier in the same call, so nothing has to start at zero.
+ * All calls on one GPU share its array: calls that overlap in time on one GPU
+ * (concurrent streams or threads) race and give wrong results; calls in one
+ * stream order are safe.  Errors: LWFR_E_WORKSPACE when the step needs more
+ * than LWFR_STATIC_SCRATCH_BYTES (GLM-MHD at N = 3: up to about 180,000
+ * solution points, e.g. 106 x 106 elements), and those of lwfr_step. */
+#define LWFR_STATIC_SCRATCH_BYTES (64u << 20)
+lwfr_status lwfr_step_noalloc(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
+                              uint32_t* d_flags, void* hip_stream);
+
 /* One time step with both dt > 0 and the GLM cleaning speed ch >= 0 given
  * (ignored by systems without GLM), e.g. to replay a step sequence with the
  * values of an earlier run.  Otherwise as lwfr_step. */

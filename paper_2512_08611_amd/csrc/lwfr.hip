@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,7 @@ struct lwfr_ctx {
       off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, off_eflags, off_srows,
       ws_bytes;
   int nblk_stats = 0;
+  size_t fwd_bytes = 0;
   // non-periodic sides: k_bfaces threads (0: periodic mesh); Dirichlet sides
   int bface_threads = 0;
   bool dirichlet = false;
@@ -399,9 +401,8 @@ lwfr_status capture(hipStream_t s, Timing& tm, hipGraphExec_t& exec, int nsteps,
   return LWFR_OK;
 }
 
-// points the context's workspace arrays into the buffer at b
-void carve(lwfr_ctx* c, char* b) {
-  KParams& kp = c->kp;
+// points the workspace arrays of kp into the buffer at b (the context's layout)
+void carve_kp(const lwfr_ctx* c, char* b, KParams& kp) {
   kp.scal = reinterpret_cast<double*>(b + c->off_scal);
   kp.part = reinterpret_cast<double*>(b + c->off_part);
   kp.part2 = reinterpret_cast<double*>(b + c->off_part2);
@@ -423,6 +424,11 @@ void carve(lwfr_ctx* c, char* b) {
   kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
   kp.eflags = reinterpret_cast<uint32_t*>(b + c->off_eflags);
   kp.stats_rows = reinterpret_cast<double*>(b + c->off_srows);
+}
+
+// points the context's workspace arrays into the buffer at b
+void carve(lwfr_ctx* c, char* b) {
+  carve_kp(c, b, c->kp);
   if (c->adjoint) {
     AdjParams& ap = c->ap;
     ap.g_rvol = reinterpret_cast<double*>(b + c->off_grvol);
@@ -758,6 +764,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->nblk_stats = (c->E + 255) / 256;
   c->off_eflags = take((size_t)c->E * sizeof(uint32_t));
   c->off_srows = take((size_t)c->nblk_stats * kStatsRow * sizeof(double));
+  c->fwd_bytes = off;  // the forward step's part of the workspace (the adjoint's arrays follow)
   c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
   if (c->adjoint) {
     const size_t nst = (size_t)c->M * c->E * c->P * sizeof(double);
@@ -851,6 +858,68 @@ lwfr_status lwfr_step(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double
   kp.dt_in = dt > 0.0 ? dt : 0.0;
   kp.ch_in = -1.0;
   return dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+}
+
+}  // extern "C"
+
+// The workspace of lwfr_step_noalloc: a static device array, one per GPU, held
+// until the process ends.  Host code never passes its name to a kernel (on the
+// host the name is only a stand-in); it uses the device address resolved for
+// the current device by hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[LWFR_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (resolved once per device)
+lwfr_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return fail(LWFR_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(err));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LWFR_E_UNSUPPORTED, "device index beyond the library's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !p)
+      return fail(LWFR_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(err));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LWFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lwfr_status lwfr_step_noalloc(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
+                              uint32_t* d_flags, void* hip_stream) {
+  if (!c) return fail(LWFR_E_INVALID_ARG, "null context");
+  if (!d_u_in || !d_u_out) return fail(LWFR_E_INVALID_ARG, "null state pointer");
+  const size_t bytes = (size_t)c->M * c->E * c->P * sizeof(double);
+  if (ranges_overlap(d_u_in, d_u_out, bytes)) return fail(LWFR_E_INVALID_ARG, "u_out aliases u_in");
+  if (!std::isfinite(dt)) return fail(LWFR_E_INVALID_ARG, "dt is not finite");
+  if (c->fwd_bytes > (size_t)LWFR_STATIC_SCRATCH_BYTES)
+    return fail(LWFR_E_WORKSPACE, "the step needs " + std::to_string(c->fwd_bytes) +
+                                      " bytes of workspace, more than the static scratch of " +
+                                      std::to_string((size_t)LWFR_STATIC_SCRATCH_BYTES) + " bytes");
+  if (lwfr_status st = dirichlet_ready(c, dt); st != LWFR_OK) return st;
+  void* base = nullptr;
+  if (lwfr_status st = scratch_address(&base); st != LWFR_OK) return st;
+  KParams kp = c->kp;
+  carve_kp(c, static_cast<char*>(base), kp);
+  kp.dt_in = dt > 0.0 ? dt : 0.0;
+  kp.ch_in = -1.0;
+  // the launches go to the caller's stream; the context's bound stream is restored after
+  const hipStream_t bound = c->stream;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  const lwfr_status st = dispatch_step(c, kp, d_u_in, d_u_out, d_dt_ch, nullptr, d_flags);
+  c->stream = bound;
+  return st;
 }
 
 lwfr_status lwfr_step_fixed(lwfr_ctx* c, const double* d_u_in, double* d_u_out, double dt, double ch,

@@ -107,6 +107,8 @@ _SIGS = {
     "lwfr_set_boundary_data": [ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_step": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "lwfr_step_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_step_fixed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                         ctypes.c_void_p, ctypes.c_void_p],
     "lwfr_residual": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p],
@@ -253,6 +255,17 @@ def lwfr_step(ctx, u_in, u_out, dt=0.0, dt_ch=None, alpha=None, flags=None, stat
     """stats: nullable device buffer of STATS_BYTES (stats_buffer()); read it with read_stats."""
     _check(lib().lwfr_step(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(alpha), _ptr(flags),
                            _ptr(stats)))
+
+
+def lwfr_step_noalloc(ctx, u_in, u_out, dt=0.0, dt_ch=None, flags=None, stream=None):
+    """One step with the library's static scratch as workspace (no bind needed);
+    stream: a torch stream (None: the current one)."""
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream(u_in.device)
+    _check(lib().lwfr_step_noalloc(ctx, _ptr(u_in), _ptr(u_out), float(dt), _ptr(dt_ch), _ptr(flags),
+                                   ctypes.c_void_p(stream.cuda_stream)))
 
 
 def lwfr_step_fixed(ctx, u_in, u_out, dt, ch, alpha=None, flags=None):
