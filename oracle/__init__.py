@@ -258,12 +258,19 @@ def jvp(c, u, v, dt, ch):
 
 
 def count_ops(c, u, dt, ch):
-    """Operation counts [phase][add, mul, div, sqrt, exp] for phases (stage loop, face traces, faces, update)."""
+    """Operation counts [phase][add, mul, div, sqrt, exp] for phases (stage loop, face traces,
+    faces, update, means with dt / c_h / indicator); counted serially (threads is ignored)."""
     u = np.ascontiguousarray(u, dtype=np.float64).reshape(shape(c))
-    counts = np.zeros(20, dtype=np.uint64)
-    assert lib().ora_count_ops(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch),
-                               _p(counts, ctypes.c_uint64)) == 0
-    return counts.reshape(4, 5)
+    counts = np.zeros(25, dtype=np.uint64)
+    threads = c.threads
+    c.threads = 1
+    try:
+        rc = lib().ora_count_ops(ctypes.byref(c), _p(u), ctypes.c_double(dt), ctypes.c_double(ch),
+                                 _p(counts, ctypes.c_uint64))
+    finally:
+        c.threads = threads
+    assert rc == 0
+    return counts.reshape(5, 5)
 
 
 def step_parts(c, u, dt=0.0, ch=-1.0):

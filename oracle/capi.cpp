@@ -350,8 +350,9 @@ int ora_vjp(const ora_cfg* c, const double* u, const double* lam, double dt, dou
 }
 
 // Algorithmic operation counts of one step, split into the element-local
-// stages, the face traces (with F^nc), the interface fluxes and the element
-// update: counts[phase*5 + {add, mul, div, sqrt, exp}], phase 0..3.
+// stages, the face traces (with F^nc), the interface fluxes, the element
+// update, and the means with dt, c_h and the smoothness indicator:
+// counts[phase*5 + {add, mul, div, sqrt, exp}], phase 0..4 (serial).
 int ora_count_ops(const ora_cfg* c, const double* u, double dt, double ch, uint64_t* counts) {
   return dispatch(c, [&](auto& s) {
     using S = std::decay_t<decltype(s)>;
@@ -377,6 +378,12 @@ int ora_count_ops(const ora_cfg* c, const double* u, double dt, double ch, uint6
     grab(2);
     s.template update<Counting>(x.data(), L, Fc, alpha, dt, ch, y.data(), nullptr, nullptr);
     grab(3);
+    double dt2, ch2;
+    s.dt_ch(x.data(), dt2, ch2);
+    std::vector<double> ar2, al2;
+    std::vector<uint8_t> t2;
+    s.indicator(x.data(), ar2, al2, t2);
+    grab(4);
   });
 }
 

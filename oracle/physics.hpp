@@ -8,7 +8,6 @@
 //   sigma(d,u,ch)      spectral radius of f_d'(u) + B_d(u)  (eq. combined.wave.speed)
 //   constraint(k,u)    P_k(u) of the admissible set (eq. uad.form)
 //   indicator(u)       the variable the smoothness indicator looks at
-// and in double only:
 //   speeds(d,u,absv,c) |v_d| and the largest characteristic speed without GLM.
 // Systems with a source term (SRC = true, §2 eq. con.law.source) also provide
 //   source(u,s)        s(u)
@@ -47,8 +46,8 @@ struct SW1D {
   }
   template <class T> T constraint(int, const T* u) const { return u[0]; }
   template <class T> T indicator(const T* u) const { return u[0]; }
-  void speeds(int, const double* u, double& absv, double& c) const {
-    absv = std::fabs(u[1] / u[0]); c = std::sqrt(g * u[0]);
+  template <class T> void speeds(int, const T* u, T& absv, T& c) const {
+    absv = fabs(u[1] / u[0]); c = sqrt(T(g) * u[0]);
   }
 };
 
@@ -76,8 +75,8 @@ struct SW2D {
   }
   template <class T> T constraint(int, const T* u) const { return u[0]; }
   template <class T> T indicator(const T* u) const { return u[0]; }
-  void speeds(int d, const double* u, double& absv, double& c) const {
-    absv = std::fabs(u[1 + d] / u[0]); c = std::sqrt(g * u[0]);
+  template <class T> void speeds(int d, const T* u, T& absv, T& c) const {
+    absv = fabs(u[1 + d] / u[0]); c = sqrt(T(g) * u[0]);
   }
 };
 
@@ -155,8 +154,8 @@ struct MHD2D {
   }
   template <class T> T constraint(int k, const T* u) const { return k == 0 ? u[0] : pressure(u); }
   template <class T> T indicator(const T* u) const { return u[0] * pressure(u); }
-  void speeds(int d, const double* u, double& absv, double& c) const {
-    absv = std::fabs(u[1 + d] / u[0]); c = cfast<double>(d, u);
+  template <class T> void speeds(int d, const T* u, T& absv, T& c) const {
+    absv = fabs(u[1 + d] / u[0]); c = cfast<T>(d, u);
   }
 };
 
@@ -173,7 +172,7 @@ struct LinAdv1D {
   template <class T> T sigma(int, const T*, double) const { return T(1.0); }
   template <class T> T constraint(int, const T* u) const { return u[0]; }
   template <class T> T indicator(const T* u) const { return u[0]; }
-  void speeds(int, const double*, double& absv, double& c) const { absv = 0.0; c = 1.0; }
+  template <class T> void speeds(int, const T*, T& absv, T& c) const { absv = T(0.0); c = T(1.0); }
 };
 
 // Variable-coefficient advection cast as a non-conservative system (paper §5.1
@@ -188,7 +187,7 @@ struct VarAdv1D {
   template <class T> T sigma(int, const T* u, double) const { return fabs(u[1]); }
   template <class T> T constraint(int, const T* u) const { return u[0]; }
   template <class T> T indicator(const T* u) const { return u[0]; }
-  void speeds(int, const double* u, double& absv, double& c) const { absv = 0.0; c = std::fabs(u[1]); }
+  template <class T> void speeds(int, const T* u, T& absv, T& c) const { absv = T(0.0); c = fabs(u[1]); }
 };
 
 // Jin-Xin relaxation system (§5.1 eqs. jinxin1, jinxin2): u = (u, v), flux
@@ -208,7 +207,7 @@ struct JinXin1D {
   template <class T> T sigma(int, const T*, double) const { return T(a); }
   template <class T> T constraint(int, const T* u) const { return u[0]; }
   template <class T> T indicator(const T* u) const { return u[0]; }
-  void speeds(int, const double*, double& absv, double& c) const { absv = 0.0; c = a; }
+  template <class T> void speeds(int, const T*, T& absv, T& c) const { absv = T(0.0); c = T(a); }
   template <class T> void source(const T* u, T* s) const {
     s[0] = T(0.0);
     s[1] = -(u[1] - f(u[0])) / T(eps);

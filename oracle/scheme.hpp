@@ -131,47 +131,50 @@ struct Scheme {
   size_t fidx(int d, int v, int e, int q) const { return (((size_t)d * M + v) * E + e) * nfp + q; }
 
   // ------------------------------------------------- 1. means, dt and c_h ---
-  void mean(const double* u, int e, double* ub) const {
+  template <class T>
+  void mean(const T* u, int e, T* ub) const {
     for (int v = 0; v < M; ++v) {
-      double s = 0;
-      for (int p = 0; p < P; ++p) s += wnode(p) * u[idx(v, e, p)];
+      T s = T(0.0);
+      for (int p = 0; p < P; ++p) s = s + T(wnode(p)) * u[idx(v, e, p)];
       ub[v] = s;
     }
   }
   // Lambda = max_e sum_d (|v_d| + c_d)(ubar_e)/dx_d with the ideal (non-GLM)
   // speeds; dt = C_s CFL(N) / Lambda (eq. time.step.2d).  For GLM-MHD c_h is the
   // largest value whose waves |v_d| + max(c_f, c_h) leave Lambda unchanged.
-  void dt_ch(const double* u, double& dt, double& ch) const {
+  // (T: double, or the counting scalar for operation counts; the counting run is serial)
+  template <class T>
+  void dt_ch(const T* u, double& dt, double& ch) const {
     double Lam = 0;
 #pragma omp parallel for num_threads(nthreads()) schedule(static) reduction(max : Lam)
     for (int e = 0; e < E; ++e) {
-      double ub[M];
+      T ub[M];
       mean(u, e, ub);
-      double s = 0;
+      T s = T(0.0);
       for (int d = 0; d < DIM; ++d) {
-        double av, c;
+        T av, c;
         ph.speeds(d, ub, av, c);
-        s += (av + c) / dx[d];
+        s = s + (av + c) / T(dx[d]);
       }
-      Lam = std::max(Lam, s);
+      Lam = std::max(Lam, val(s));
     }
-    dt = cfg.cs * cfg.cfl / Lam;
+    dt = val(T(cfg.cs * cfg.cfl) / T(Lam));
     ch = 0.0;
     if (cfg.eq == EQ_MHD2D) {
       double best = INFINITY;
 #pragma omp parallel for num_threads(nthreads()) schedule(static) reduction(min : best)
       for (int e = 0; e < E; ++e) {
-        double ub[M];
+        T ub[M];
         mean(u, e, ub);
-        double av[2], c[2];
+        T av[2], c[2];
         for (int d = 0; d < 2; ++d) ph.speeds(d, ub, av[d], c[d]);
-        double wx = 1.0 / dx[0], wy = 1.0 / dx[1];
-        double R = Lam - (av[0] * wx + av[1] * wy);
+        const T wx = T(1.0 / dx[0]), wy = T(1.0 / dx[1]);
+        T R = T(Lam) - (av[0] * wx + av[1] * wy);
         // largest c with wx max(c_x, c) + wy max(c_y, c) <= R
-        double lo = c[0], hi = c[1], wlo = wx, whi = wy;
-        if (lo > hi) { std::swap(lo, hi); std::swap(wlo, whi); }
-        double ce = (wlo + whi) * hi >= R ? (R - whi * hi) / wlo : R / (wlo + whi);
-        best = std::min(best, ce);
+        T lo = c[0], hi = c[1], wlo = wx, whi = wy;
+        if (val(lo) > val(hi)) { std::swap(lo, hi); std::swap(wlo, whi); }
+        T ce = val((wlo + whi) * hi) >= val(R) ? (R - whi * hi) / wlo : R / (wlo + whi);
+        best = std::min(best, val(ce));
       }
       ch = best;
     }
@@ -183,45 +186,49 @@ struct Scheme {
   // modes; alpha = logistic((s/T)(E - T)), T(N) = 0.5 10^{-1.8 (N+1)^{1/4}},
   // s = ln(9999); clip below alpha_min / above 1-alpha_min, cap alpha_max;
   // smoothing alpha_e <- max(alpha_e, alpha_nb/2) over face neighbours.
-  void indicator(const double* u, std::vector<double>& araw, std::vector<double>& alpha,
+  template <class T>
+  void indicator(const T* u, std::vector<double>& araw, std::vector<double>& alpha,
                  std::vector<uint8_t>& tie) const {
     araw.assign(E, 0.0); alpha.assign(E, 0.0); tie.assign(E, 0);
     if (cfg.alpha_force >= 0.0) { alpha.assign(E, cfg.alpha_force); araw = alpha; return; }
     if (cfg.blending == 0 || N == 0) return;
-    const double T = 0.5 * std::pow(10.0, -1.8 * std::pow(N + 1.0, 0.25));
+    const double Tn = 0.5 * std::pow(10.0, -1.8 * std::pow(N + 1.0, 0.25));
     const double s = std::log(9999.0);
 #pragma omp parallel for num_threads(nthreads()) schedule(static)
     for (int e = 0; e < E; ++e) {
-      std::vector<double> q(P), ue(M);
+      std::vector<T> q(P), ue(M);
       for (int p = 0; p < P; ++p) {
         for (int v = 0; v < M; ++v) ue[v] = u[idx(v, e, p)];
         q[p] = ph.indicator(ue.data());
       }
-      double tot = 0, c1 = 0, c2 = 0;
+      T tot = T(0.0), c1 = T(0.0), c2 = T(0.0);
       if (DIM == 1) {
         for (int k = 0; k < n1; ++k) {
-          double m = 0;
-          for (int p = 0; p < n1; ++p) m += re.w[p] * q[p] * re.Leg[k * n1 + p];
-          tot += m * m;
-          if (k <= N - 1) c1 += m * m;
-          if (k <= N - 2) c2 += m * m;
+          T m = T(0.0);
+          for (int p = 0; p < n1; ++p) m = m + T(re.w[p]) * q[p] * T(re.Leg[k * n1 + p]);
+          tot = tot + m * m;
+          if (k <= N - 1) c1 = c1 + m * m;
+          if (k <= N - 2) c2 = c2 + m * m;
         }
       } else {
         for (int l = 0; l < n1; ++l)
           for (int k = 0; k < n1; ++k) {
-            double m = 0;
+            T m = T(0.0);
             for (int j = 0; j < n1; ++j)
               for (int i = 0; i < n1; ++i)
-                m += re.w[i] * re.w[j] * q[i + n1 * j] * re.Leg[k * n1 + i] * re.Leg[l * n1 + j];
+                m = m + T(re.w[i]) * T(re.w[j]) * q[i + n1 * j] * T(re.Leg[k * n1 + i]) * T(re.Leg[l * n1 + j]);
             int deg = std::max(k, l);
-            tot += m * m;
-            if (deg <= N - 1) c1 += m * m;
-            if (deg <= N - 2) c2 += m * m;
+            tot = tot + m * m;
+            if (deg <= N - 1) c1 = c1 + m * m;
+            if (deg <= N - 2) c2 = c2 + m * m;
           }
       }
-      double En = tot > 0 ? (tot - c1) / tot : 0.0;
-      if (N >= 2) En = std::max(En, c1 > 0 ? (c1 - c2) / c1 : 0.0);
-      double a = 1.0 / (1.0 + std::exp(-(s / T) * (En - T)));
+      T En = val(tot) > 0 ? (tot - c1) / tot : T(0.0);
+      if (N >= 2) {
+        T E2 = val(c1) > 0 ? (c1 - c2) / c1 : T(0.0);
+        if (val(E2) > val(En)) En = E2;
+      }
+      double a = val(T(1.0) / (T(1.0) + exp(-T(s / Tn) * (En - T(Tn)))));
       if (std::fabs(a - cfg.alpha_min) < 1e-9 || std::fabs(a - (1.0 - cfg.alpha_min)) < 1e-9) tie[e] = 1;
       if (a < cfg.alpha_min) a = 0.0;
       if (a > 1.0 - cfg.alpha_min) a = 1.0;

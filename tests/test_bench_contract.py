@@ -27,6 +27,21 @@ def test_stage_loop_flop_counts(key):
     assert per_dof == bench.STAGE_LOOP_FLOPS_PER_DOF[key]
 
 
+@pytest.mark.parametrize("key", sorted(bench.STEP_FLOPS_PER_DOF))
+def test_step_flop_counts(key):
+    N, data = key
+    n = 16
+    re = oracle.refel(N)
+    u = W.mhd_blocky(re["xi"], n, seed=0) if data == "blocky" else W.mhd_smooth(re["xi"], n, seed=0)
+    c = oracle.make_cfg(oracle.EQ_MHD2D, N, n, n, blending=2)
+    dt, ch = oracle.dt_ch(c, u)
+    counts = oracle.count_ops(c, u, dt, ch).astype(float)
+    per_dof = counts.sum() / (u.shape[1] * u.shape[2])
+    assert abs(per_dof - bench.STEP_FLOPS_PER_DOF[key]) < 0.05, per_dof
+    # the stage loop part is the dominant kernel's figure
+    assert counts[0].sum() / (u.shape[1] * u.shape[2]) == bench.STAGE_LOOP_FLOPS_PER_DOF[("GLMMHD2D", N)]
+
+
 def test_multi_gpu_request_exits_with_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True)
