@@ -63,14 +63,6 @@ union LdsByDegree {
 };
 
 template <class Ph, int NT>
-union StageLdsByDegree {
-  StageLdsT<Ph, 1, NT> n1;
-  StageLdsT<Ph, 2, NT> n2;
-  StageLdsT<Ph, 3, NT> n3;
-  StageLdsT<Ph, 4, NT> n4;
-};
-
-template <class Ph, int NT>
 __global__ void __launch_bounds__(NT) kb_pre(const BatchArgs ba, const double* __restrict__ u) {
   constexpr int DIM = Ph::DIM;
   __shared__ LdsByDegree<PreLds, Ph, NT> L;
@@ -111,11 +103,13 @@ __global__ void __launch_bounds__(256) kb_dt(const BatchArgs ba, const int* __re
   }
 }
 
-// The batched kernels hold the registers of their largest degree; the hint
-// keeps the stage kernel at two waves per SIMD (a few registers spill).
-template <class Ph, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) kb_stages(const BatchArgs ba, const double* __restrict__ u_in, double* __restrict__ u_out) {
-  __shared__ StageLdsByDegree<Ph, NT> L;
+// stage phase, one launch per degree: each launch walks the tiles of the
+// problems of degree N only (the tile table lists them together), so it holds
+// only that degree's registers
+template <class Ph, int N, int NT>
+__global__ void __launch_bounds__(NT) kb_stages(const BatchArgs ba, const double* __restrict__ u_in,
+                                                double* __restrict__ u_out) {
+  __shared__ StageLdsT<Ph, N, NT> L;
   int t0, t1, step;
   tile_range(ba.ntiles, ba.xcd, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
@@ -123,12 +117,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) kb
     const KParams& kp = ba.kps[inst];
     const double* un = u_in + ba.uoff[inst];
     double* rv = u_out + ba.uoff[inst];
-    switch (kp.N) {
-      case 1: stage_body<Ph, 1, batch_epb_stages<Ph, 1, NT>(), NT, Tableau<1>, true>(kp, L.n1, un, rv, nullptr, blk); break;
-      case 2: stage_body<Ph, 2, batch_epb_stages<Ph, 2, NT>(), NT, Tableau<2>, true>(kp, L.n2, un, rv, nullptr, blk); break;
-      case 3: stage_body<Ph, 3, batch_epb_stages<Ph, 3, NT>(), NT, Tableau<3>, true>(kp, L.n3, un, rv, nullptr, blk); break;
-      default: stage_body<Ph, 4, batch_epb_stages<Ph, 4, NT>(), NT, Tableau<4>, true>(kp, L.n4, un, rv, nullptr, blk); break;
-    }
+    stage_body<Ph, N, batch_epb_stages<Ph, N, NT>(), NT, Tableau<N>, true>(kp, L, un, rv, nullptr, blk);
     __syncthreads();
   }
 }

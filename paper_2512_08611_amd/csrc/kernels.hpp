@@ -95,7 +95,7 @@ struct KParams {
   double* untr;               // [d][side][M][E*nfp] trace of u^n
   double* Fm;                 // [d][M][E*nfp] F^- of face (e, e+1)
   double* Fp;                 // [d][M][E*nfp] F^+
-  double* Dm;                 // [d][M][E*nfp] F^- - F_tr^- - B(u^{n,-}) U^-
+  double* Dm;                 // [d][M][E*nfp] F^- - F_tr^- - B(u^{n,-}) U^- (systems that do not fold it)
   double* Dp;                 // [d][M][E*nfp] F^+ - F_tr^+ - B(u^{n,+}) U^+
   double* theta_face;         // [d][E*nfp] product of Algorithm 1 thetas
   uint32_t* guard_face;       // [d][E*nfp]
@@ -136,6 +136,16 @@ __device__ inline int alpha_nbr(const KParams& kp, int e, int d, int side) {
 
 template <int n1>
 __device__ __host__ constexpr int node_at(int d, int q, int r) { return d == 0 ? r + n1 * q : q + n1 * r; }
+
+// Where the element-local half of the correction terms of eq.
+// crkfr.non.cons.final goes.  The nine-variable 2-D systems (two lanes per
+// point in the stage and face kernels) fold C = F_tr + B_d(u^n_tr) U_tr at the
+// element's own faces into the volume residual in the stage kernel, and the
+// update adds F^num g'/dx: the face kernel writes only F^-, F^+.  The other
+// systems, whose stage kernel is light, keep the correction jumps D^± = F^± - C^±
+// that the face kernel writes beside F^±.
+template <class Ph>
+__host__ __device__ constexpr bool fold_correction() { return Ph::DIM == 2 && Ph::M >= 8; }
 
 __device__ inline double theta_limit(double eps, double Pa, double Pb, bool& guard) {
   // theta_{P_k}(eps, u_a, u_b) for a concave P_k (eq. theta.formula), weight on the
@@ -411,12 +421,141 @@ struct StagesLds {
 };
 
 // Outputs of the element-local phase, shared by the stage body and the
-// approximate Lax-Wendroff body: the volume residual Ra, the face traces of the
-// time averages F_d, U and of u^n, and the smoothed blending coefficient.
+// approximate Lax-Wendroff body: the face traces of the time averages F_d, U
+// and of u^n, the volume residual and the smoothed blending coefficient.  With
+// the correction folded (fold_correction) the volume residual written is
+// R = Ra - sum_d (C_{d,R} g_R'(xi) + C_{d,L} g_L'(xi)) / dx_d along the lines
+// through the point, with C = F_tr + B_d(u^n_tr) U_tr at the element's own
+// faces, so that the update adds only F^num g'/dx; otherwise R = Ra.
 // sb: the element's LDS rows (at least DIM*M + M of them); every thread of the
 // workgroup calls it (it synchronises).
+template <class Ph, int d>
+__device__ inline void correction_offset(const double* a, const double* U, double* C, const PhysParams& pp) {
+  double t[Ph::M];
+  Ph::template ncprod<d>(a, U, t, pp);
+#pragma unroll
+  for (int v = 0; v < Ph::M; ++v) C[v] += t[v];
+}
+
 template <class Ph, int N, int NB, int PS>
-__device__ __forceinline__ void stage_outputs(const KParams& kp, double (&sb)[NB][PS], int p, int e, bool act,
+__device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&sb)[NB][PS], int p, int e, bool act,
+                                              const double (&Fa)[Ph::DIM][Ph::M], const double (&Ua)[Ph::M],
+                                              const double (&Ra)[Ph::M], const double* __restrict__ un_g,
+                                              double* __restrict__ rvol_g, double* d_alpha_out) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
+  constexpr int NFT = 2 * DIM * NFP;          // face points of the element (both sides, every direction)
+  constexpr int NOWN = (NFT + P - 1) / P;     // face points per thread
+  static_assert(NB >= DIM * M + M && PS >= P, "LDS rows");
+  static_assert(NFT * M <= NB * PS, "LDS room for the correction offsets");
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
+  // time-averaged flux and solution to LDS for the face traces
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d)
+#pragma unroll
+    for (int v = 0; v < M; ++v) sb[d * M + v][p] = Fa[d][v];
+#pragma unroll
+  for (int v = 0; v < M; ++v) sb[DIM * M + v][p] = Ua[v];
+  __syncthreads();
+
+  if (act) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) rvol_g[((size_t)v * kp.E + e) * P + p] = Ra[v];
+  }
+  // face traces, one face point (all variables) per thread, and the correction
+  // offsets C of those face points (fenced from the stage loop: its loads are
+  // not to be hoisted into it)
+  __builtin_amdgcn_sched_barrier(0);
+  const size_t nf = (size_t)kp.E * NFP;
+  double C[NOWN][M];
+#pragma unroll
+  for (int k = 0; k < NOWN; ++k) {
+    const int w = p + k * P;
+    if (!act || w >= NFT) continue;
+    const int d = w / (2 * NFP);
+    const int rem = w - d * 2 * NFP;
+    const int side = rem / NFP;
+    const int q = rem - side * NFP;
+    const double* V = side ? kp.VR : kp.VL;
+    const size_t fo = (size_t)e * NFP + q;
+    // three passes (u^n, U, then F), each fenced from the next, so that few
+    // loads are in flight at once
+    double a[M], U[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) t += V[r] * un_g[((size_t)v * kp.E + e) * P + (d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r))];
+      a[v] = t;
+      kp.untr[((size_t)(d * 2 + side) * M + v) * nf + fo] = t;
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) t += V[r] * sb[DIM * M + v][d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r)];
+      U[v] = t;
+      kp.Utr[((size_t)(d * 2 + side) * M + v) * nf + fo] = t;
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) C[k][v] = 0.0;
+    if (d == 0) correction_offset<Ph, 0>(a, U, C[k], pp);
+    else if constexpr (DIM == 2) correction_offset<Ph, 1>(a, U, C[k], pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) t += V[r] * sb[d * M + v][d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r)];
+      kp.Ftr[((size_t)(d * 2 + side) * M + v) * nf + fo] = t;
+      C[k][v] = t + C[k][v];
+    }
+  }
+  __syncthreads();  // every read of the F and U rows is done
+  double* flat = &sb[0][0];
+#pragma unroll
+  for (int k = 0; k < NOWN; ++k) {
+    const int w = p + k * P;
+    if (act && w < NFT) {
+#pragma unroll
+      for (int v = 0; v < M; ++v) flat[w * M + v] = C[k][v];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    double R[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) R[v] = rvol_g[((size_t)v * kp.E + e) * P + p];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int q = DIM == 1 ? 0 : (d == 0 ? p / n1 : p % n1), ii = DIM == 1 ? p : (d == 0 ? p % n1 : p / n1);
+      const int wR = d * 2 * NFP + NFP + q, wL = d * 2 * NFP + q;
+#pragma unroll
+      for (int v = 0; v < M; ++v)
+        R[v] -= (flat[wR * M + v] * kp.gR[ii] + flat[wL * M + v] * kp.gL[ii]) * kp.inv_dx[d];
+    }
+#pragma unroll
+    for (int v = 0; v < M; ++v) rvol_g[((size_t)v * kp.E + e) * P + p] = R[v];
+    // blending coefficient of the element (smoothed over face neighbours)
+    if (p == 0) {
+      double a;
+      if (kp.alpha_force >= 0.0) a = kp.alpha_force;
+      else if (kp.blending == 0) a = 0.0;
+      else {
+        a = kp.alpha_raw[e];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+#pragma unroll
+          for (int sd = 0; sd < 2; ++sd) a = fmax(a, 0.5 * kp.alpha_raw[alpha_nbr(kp, e, d, sd)]);
+      }
+      kp.alpha[e] = a;
+      if (d_alpha_out) d_alpha_out[e] = a;
+    }
+  }
+  __syncthreads();  // the LDS rows are free again (batched tile loops reuse them)
+}
+
+template <class Ph, int N, int NB, int PS>
+__device__ __forceinline__ void stage_outputs_plain(const KParams& kp, double (&sb)[NB][PS], int p, int e, bool act,
                                               const double (&Fa)[Ph::DIM][Ph::M], const double (&Ua)[Ph::M],
                                               const double (&Ra)[Ph::M], const double* __restrict__ un_g,
                                               double* __restrict__ rvol_g, double* d_alpha_out) {
@@ -477,6 +616,18 @@ __device__ __forceinline__ void stage_outputs(const KParams& kp, double (&sb)[NB
       if (d_alpha_out) d_alpha_out[e] = a;
     }
   }
+}
+
+// the outputs of the element-local phase (see fold_correction)
+template <class Ph, int N, int NB, int PS>
+__device__ __forceinline__ void stage_outputs(const KParams& kp, double (&sb)[NB][PS], int p, int e, bool act,
+                                              const double (&Fa)[Ph::DIM][Ph::M], const double (&Ua)[Ph::M],
+                                              const double (&Ra)[Ph::M], const double* __restrict__ un_g,
+                                              double* __restrict__ rvol_g, double* d_alpha_out) {
+  if constexpr (fold_correction<Ph>())
+    stage_outputs_fold<Ph, N>(kp, sb, p, e, act, Fa, Ua, Ra, un_g, rvol_g, d_alpha_out);
+  else
+    stage_outputs_plain<Ph, N>(kp, sb, p, e, act, Fa, Ua, Ra, un_g, rvol_g, d_alpha_out);
 }
 
 // Tab: the explicit tableau of degree N, or for a system with a source its
@@ -836,8 +987,9 @@ struct Stages2Lds {
   double s_buf[EL][ES];
 };
 
-// outputs of the two-lane stage kernels: the volume residual (lane's half of
-// the variables), the face traces of F (lane's direction), U and u^n, and the
+// outputs of the two-lane stage kernels: the face traces of F (lane's
+// direction), U and u^n, the volume residual (lane's half of the variables,
+// with the element-local correction terms as in stage_outputs) and the
 // element's blending coefficient.  Fa holds the lane's direction for all
 // variables; Ua, Ra and uo the lane's half.
 template <class Ph, int N, int NT>
@@ -846,8 +998,11 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
                                              const double* uo, double* __restrict__ rvol_g, double* d_alpha_out) {
   constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NFP = n1;
   constexpr int H0 = (M + 1) / 2, H1 = M - H0;
+  constexpr int NFT = 4 * NFP;  // face points of the element
+  static_assert(NFT <= 2 * P && NFT * M <= 2 * M * P, "one face point per lane; LDS room for the offsets");
   const int vo = d ? H0 : 0;
   auto& s_buf = L.s_buf;
+  const PhysParams pp = phys_params(kp, kp.scal[1]);
   // time-averaged flux (lane's direction), solution and u^n (lane's half) to LDS
 #pragma unroll
   for (int v = 0; v < M; ++v) s_buf[le][(d * M + v) * P + (p)] = Fa[v];
@@ -859,37 +1014,75 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
     }
   __syncthreads();
 
-  if (act) {
+  // face traces, one face point (all variables) per lane, and the correction
+  // offsets C = F_tr + B_d(u^n_tr) U_tr of those face points
+  const int tl = 2 * p + d;
+  const bool own = act && tl < NFT;
+  double C[M];
+  if (own) {
+    const int dd = tl / (2 * NFP);
+    const int rem = tl - dd * 2 * NFP;
+    const int side = rem / NFP;
+    const int qq = rem - side * NFP;
+    const double* V = side ? kp.VR : kp.VL;
+    const size_t nf = (size_t)kp.E * NFP;
+    const size_t fo = (size_t)e * NFP + qq;
+    // three passes (u^n, U, then F), each fenced from the next, so that few
+    // LDS values are in flight at once
+    auto trace = [&](int field, int v) {
+      double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < H0; ++k)
-      if (k < (d ? H1 : H0)) rvol_g[((size_t)(vo + k) * kp.E + e) * P + p] = Ra[k];
-    // face traces: (variable, face point) pairs of the element, variable
-    // slowest, over the element's 2P lanes
-    constexpr int NFT = 4 * NFP;
-    const int tl = 2 * p + d;
-    for (int w = tl; w < NFT * M; w += 2 * P) {
-      const int v = w / NFT, t = w - v * NFT;
-      const int dd = t / (2 * NFP);
-      const int rem = t - dd * 2 * NFP;
-      const int side = rem / NFP;
-      const int qq = rem - side * NFP;
-      const double* V = side ? kp.VR : kp.VL;
-      const size_t nf = (size_t)kp.E * NFP;
-      const size_t fo = (size_t)e * NFP + qq;
-      {
-        double tf = 0.0, tu = 0.0, tn = 0.0;
-#pragma unroll
-        for (int r = 0; r < n1; ++r) {
-          const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
-          tf += V[r] * s_buf[le][(dd * M + v) * P + (nd)];
-          tu += V[r] * s_buf[le][(2 * M + v) * P + (nd)];
-          tn += V[r] * s_buf[le][(3 * M + v) * P + (nd)];
-        }
-        const size_t o = ((size_t)(dd * 2 + side) * M + v) * nf + fo;
-        kp.Ftr[o] = tf;
-        kp.Utr[o] = tu;
-        kp.untr[o] = tn;
+      for (int r = 0; r < n1; ++r) {
+        const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
+        t += V[r] * s_buf[le][(field + v) * P + (nd)];
       }
+      return t;
+    };
+    double a[M], U[M];
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      a[v] = trace(3 * M, v);
+      kp.untr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = a[v];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      U[v] = trace(2 * M, v);
+      kp.Utr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = U[v];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < M; ++v) C[v] = 0.0;
+    if (dd == 0) correction_offset<Ph, 0>(a, U, C, pp);
+    else correction_offset<Ph, 1>(a, U, C, pp);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int v = 0; v < M; ++v) {
+      const double tf = trace(dd * M, v);
+      kp.Ftr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = tf;
+      C[v] = tf + C[v];
+    }
+  }
+  __syncthreads();  // every read of the F, U and u^n fields is done
+  if (own) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) s_buf[le][tl * M + v] = C[v];
+  }
+  __syncthreads();
+  if (act) {
+    const int i = p % n1, j = p / n1;
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      if (k >= (d ? H1 : H0)) continue;
+      const int v = vo + k;
+      double R = Ra[k];
+#pragma unroll
+      for (int dd = 0; dd < 2; ++dd) {
+        const int q = dd == 0 ? j : i, ii = dd == 0 ? i : j;
+        const int wR = dd * 2 * NFP + NFP + q, wL = dd * 2 * NFP + q;
+        R -= (s_buf[le][wR * M + v] * kp.gR[ii] + s_buf[le][wL * M + v] * kp.gL[ii]) * kp.inv_dx[dd];
+      }
+      rvol_g[((size_t)v * kp.E + e) * P + p] = R;
     }
     // blending coefficient of the element (smoothed over face neighbours)
     if (p == 0 && d == 0) {
@@ -1276,9 +1469,9 @@ __device__ inline bool admissible(const double* x, const PhysParams& pp) {
 
 // one face point of direction d between element e (minus side) and en (plus
 // side).  Written so that few values are live at once: the traces die once
-// F^num, U^num and the two correction offsets C^- = F_tr^- + B(u^{n,-}) U^-,
-// C^+ = F_tr^+ + B(u^{n,+}) U^+ are formed, and the candidate states of
-// Algorithm 1 are rebuilt for each constraint.
+// F^num, U^num (and the correction offsets C^± of the systems that do not fold
+// them) are formed, and the candidate states of Algorithm 1 are rebuilt for
+// each constraint.
 template <class Ph, int N, int d>
 __device__ inline void face_point(const KParams& kp, const double* __restrict__ un_g, int e, int q, double dt,
                                   const PhysParams& pp) {
@@ -1334,12 +1527,15 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
     Ph::template ncprod<d>(b, Unum, t, pp);
 #pragma unroll
     for (int v = 0; v < M; ++v) Fp[v] += t[v];
-    Ph::template ncprod<d>(a, UL, t, pp);
+    if constexpr (!fold_correction<Ph>()) {
+      // correction offsets C^- = F_tr^- + B(u^{n,-}) U^-, C^+ = F_tr^+ + B(u^{n,+}) U^+
+      Ph::template ncprod<d>(a, UL, t, pp);
 #pragma unroll
-    for (int v = 0; v < M; ++v) Cm[v] += t[v];
-    Ph::template ncprod<d>(b, UR, t, pp);
+      for (int v = 0; v < M; ++v) Cm[v] += t[v];
+      Ph::template ncprod<d>(b, UR, t, pp);
 #pragma unroll
-    for (int v = 0; v < M; ++v) Cp[v] += t[v];
+      for (int v = 0; v < M; ++v) Cp[v] += t[v];
+    }
   }
   const double af = kp.blending == 0 ? 0.0 : 0.5 * (kp.alpha[e] + kp.alpha[en]);
   double Theta = 1.0;
@@ -1388,15 +1584,17 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
       }
     }
   }
-  // outputs: F^± and the correction differences F^± - (F_tr^± + B(u^{n,±}) U^±)
+  // outputs: F^- and F^+, and the correction jumps D^± = F^± - C^± (fold_correction)
   const size_t fo = (size_t)d * nf + fiL;
 #pragma unroll
   for (int v = 0; v < M; ++v) {
     const size_t o = ((size_t)d * M + v) * nf + fiL;
     kp.Fm[o] = Fm[v];
     kp.Fp[o] = Fp[v];
-    kp.Dm[o] = Fm[v] - Cm[v];
-    kp.Dp[o] = Fp[v] - Cp[v];
+    if constexpr (!fold_correction<Ph>()) {
+      kp.Dm[o] = Fm[v] - Cm[v];
+      kp.Dp[o] = Fp[v] - Cp[v];
+    }
   }
   kp.theta_face[fo] = Theta;
   kp.guard_face[fo] = guard ? 1u : 0u;
@@ -1482,9 +1680,6 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
     Ph::template ncprod<d>(a, Unum, t, pp);
 #pragma unroll
     for (int v = 0; v < M; ++v) F[v] += t[v];
-    Ph::template ncprod<d>(a, U, t, pp);
-#pragma unroll
-    for (int v = 0; v < M; ++v) C[v] += t[v];  // C^-/C^+ of the lane's side
   }
   const double af = kp.blending == 0 ? 0.0 : 0.5 * (kp.alpha[e] + kp.alpha[en]);
   double Theta = 1.0;
@@ -1543,16 +1738,11 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
       guard = (gl != 0.0) || (gh != 0.0);
     }
   }
-  // outputs: the minus lane F^- and D^-, the plus lane F^+ and D^+ (slot of the face = e's)
+  // outputs: the minus lane F^-, the plus lane F^+ (slot of the face = e's)
   const size_t fiL = (size_t)e * NFP + q;
   double* Fo = side ? kp.Fp : kp.Fm;
-  double* Do = side ? kp.Dp : kp.Dm;
 #pragma unroll
-  for (int v = 0; v < M; ++v) {
-    const size_t o = ((size_t)d * M + v) * nf + fiL;
-    Fo[o] = F[v];
-    Do[o] = F[v] - C[v];
-  }
+  for (int v = 0; v < M; ++v) Fo[((size_t)d * M + v) * nf + fiL] = F[v];
   if (!side) {
     kp.theta_face[(size_t)d * nf + fiL] = Theta;
     kp.guard_face[(size_t)d * nf + fiL] = guard ? 1u : 0u;
@@ -1601,8 +1791,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES_
 // side of the last element of a line (ghost state on the plus side) and the
 // left side of the first element (ghost on the minus side).  k_faces treats
 // the wrap-around face of the line as periodic; k_bfaces runs after it and
-// overwrites that face's slot (the slot of the last element): F^-, D^-, theta
-// and guard from the right half face, F^+ and D^+ from the left half face
+// overwrites that face's slot (the slot of the last element): F^- (and D^-),
+// theta and guard from the right half face, F^+ (and D^+) from the left half face
 // (k_update reads F^+ of an element's left face at the slot of its left
 // neighbour, which wraps to the last element), and the left half face's theta
 // and guard go to theta_left / guard_left.
@@ -1749,16 +1939,16 @@ __device__ inline void bface_point(const KParams& kp, const double* __restrict__
   bool guard;
   if (half == 0) half_face_flux<Ph, d>(kp, in, gh, af, true, false, dt, N, pp, Fm, Fp, Theta, guard);
   else half_face_flux<Ph, d>(kp, gh, in, af, false, true, dt, N, pp, Fm, Fp, Theta, guard);
-  // correction offset of the inside side: F_tr + B(u^n) U at its face
+  // correction offset of the inside side, F_tr + B(u^n) U at its face (fold_correction)
   double C[M];
-  Ph::template ncprod<d>(in.a, in.U, C, pp);
+  if constexpr (!fold_correction<Ph>()) Ph::template ncprod<d>(in.a, in.U, C, pp);
   const size_t slot = (size_t)eN * NFP + q;
   if (half == 0) {
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       const size_t o = ((size_t)d * M + v) * nf + slot;
       kp.Fm[o] = Fm[v];
-      kp.Dm[o] = Fm[v] - (in.F[v] + C[v]);
+      if constexpr (!fold_correction<Ph>()) kp.Dm[o] = Fm[v] - (in.F[v] + C[v]);
     }
     kp.theta_face[(size_t)d * nf + slot] = Theta;
     kp.guard_face[(size_t)d * nf + slot] = guard ? 1u : 0u;
@@ -1767,7 +1957,7 @@ __device__ inline void bface_point(const KParams& kp, const double* __restrict__
     for (int v = 0; v < M; ++v) {
       const size_t o = ((size_t)d * M + v) * nf + slot;
       kp.Fp[o] = Fp[v];
-      kp.Dp[o] = Fp[v] - (in.F[v] + C[v]);
+      if constexpr (!fold_correction<Ph>()) kp.Dp[o] = Fp[v] - (in.F[v] + C[v]);
     }
     const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + j;
     kp.theta_left[bl] = Theta;
@@ -1808,9 +1998,10 @@ inline int bface_threads(int DIM, int nx, int ny, int NFP, const int bc[2][2]) {
 
 // ------------------------------------------------------------------------
 // k_update: one thread per solution point.  High order update (eq.
-// crkfr.non.cons.final), subcell FV update (eq. low.order.update), blend
-// (eq. blended.scheme) and Algorithm 2.  io holds R_vol on entry and u^{n+1}
-// on exit.
+// crkfr.non.cons.final: the volume residual from the stage kernel plus the
+// correction terms, F^± g'/dx or D^± g'/dx, see fold_correction), subcell FV
+// update (eq. low.order.update), blend (eq. blended.scheme) and Algorithm 2.
+// io holds R_vol on entry and u^{n+1} on exit.
 template <class Ph, int N, int NT>
 struct UpdateLds {
   static constexpr int M = Ph::M, P = ipow(N + 1, Ph::DIM), EL = (NT + P - 1) / P;
@@ -1864,11 +2055,14 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     for (int d = 0; d < DIM; ++d) {
       const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
       const size_t fR = (size_t)es * NFP + q, fL = (size_t)eL[d] * NFP + q;
+      // the correction terms: F^± g'/dx after a folded volume residual, else D^± g'/dx
+      const double* cm = fold_correction<Ph>() ? kp.Fm : kp.Dm;
+      const double* cp = fold_correction<Ph>() ? kp.Fp : kp.Dp;
 #pragma unroll
       for (int v = 0; v < M; ++v) {
-        const double dm = kp.Dm[((size_t)d * M + v) * nf + fR];
-        const double dp = kp.Dp[((size_t)d * M + v) * nf + fL];
-        R[v] += (dm * kp.gR[ii] + dp * kp.gL[ii]) * kp.inv_dx[d];
+        const double fm = cm[((size_t)d * M + v) * nf + fR];
+        const double fp = cp[((size_t)d * M + v) * nf + fL];
+        R[v] += (fm * kp.gR[ii] + fp * kp.gL[ii]) * kp.inv_dx[d];
       }
     }
 #pragma unroll

@@ -415,8 +415,8 @@ void carve_kp(const lwfr_ctx* c, char* b, KParams& kp) {
   kp.untr = reinterpret_cast<double*>(b + c->off_untr);
   kp.Fm = reinterpret_cast<double*>(b + c->off_Fm);
   kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
-  kp.Dm = reinterpret_cast<double*>(b + c->off_Dm);
-  kp.Dp = reinterpret_cast<double*>(b + c->off_Dp);
+  kp.Dm = c->off_Dm ? reinterpret_cast<double*>(b + c->off_Dm) : nullptr;
+  kp.Dp = c->off_Dp ? reinterpret_cast<double*>(b + c->off_Dp) : nullptr;
   kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
   kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
   kp.theta_left = reinterpret_cast<double*>(b + c->off_thl);
@@ -458,6 +458,8 @@ struct BatchTable {     // one tile table
   int tile_threads = 0;  // threads per tile (per-point phases) or 256 (faces)
   int ntiles = 0;
   std::vector<int> tinst, tblk, tile_begin;  // tile_begin: [ninst+1]
+  // stage tables: tiles grouped by degree, degree N in [deg_begin[N], deg_begin[N+1])
+  int deg_begin[6] = {0, 0, 0, 0, 0, 0};
   size_t off_tinst = 0, off_tblk = 0, off_tb = 0;
 };
 
@@ -547,8 +549,28 @@ lwfr_status batch_phase(lwfr_batch* c, int phase, const double* u_in, double* u_
       }
       break;
     case LWFR_PHASE_STAGES:
-      if (big) LWFR_LAUNCH(KID_B_STAGES, "kb_stages", (kb_stages<Ph, 256>), g, dim3(256), 0, s, ba, u_in, u_out);
-      else LWFR_LAUNCH(KID_B_STAGES, "kb_stages", (kb_stages<Ph, 128>), g, dim3(128), 0, s, ba, u_in, u_out);
+      // one launch per degree present, over that degree's contiguous tiles
+      for (int deg = 1; deg <= 4; ++deg) {
+        const int n = t.deg_begin[deg + 1] - t.deg_begin[deg];
+        if (n == 0) continue;
+        BatchArgs bd = ba;
+        bd.tinst += t.deg_begin[deg];
+        bd.tblk += t.deg_begin[deg];
+        bd.ntiles = n;
+        const dim3 gd = batch_grid(l, n);
+#define LWFR_KB_STAGES(D)                                                                                   \
+  do {                                                                                                      \
+    if (big) LWFR_LAUNCH(KID_B_STAGES, "kb_stages", (kb_stages<Ph, D, 256>), gd, dim3(256), 0, s, bd, u_in, u_out); \
+    else LWFR_LAUNCH(KID_B_STAGES, "kb_stages", (kb_stages<Ph, D, 128>), gd, dim3(128), 0, s, bd, u_in, u_out);     \
+  } while (0)
+        switch (deg) {
+          case 1: LWFR_KB_STAGES(1); break;
+          case 2: LWFR_KB_STAGES(2); break;
+          case 3: LWFR_KB_STAGES(3); break;
+          default: LWFR_KB_STAGES(4); break;
+        }
+#undef LWFR_KB_STAGES
+      }
       break;
     case LWFR_PHASE_FACES:
       LWFR_LAUNCH(KID_B_FACES, "kb_faces", (kb_faces<Ph>), g, dim3(256), 0, s, ba, u_in);
@@ -751,8 +773,11 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_untr = take(nfpt * 2 * c->M * sizeof(double));
   c->off_Fm = take(nfpt * c->M * sizeof(double));
   c->off_Fp = take(nfpt * c->M * sizeof(double));
-  c->off_Dm = take(nfpt * c->M * sizeof(double));
-  c->off_Dp = take(nfpt * c->M * sizeof(double));
+  // the correction jumps D^± of the systems that do not fold the correction
+  // into the volume residual (fold_correction: 2-D with nine variables)
+  const bool fold = c->DIM == 2 && c->M >= 8;
+  c->off_Dm = fold ? 0 : take(nfpt * c->M * sizeof(double));
+  c->off_Dp = fold ? 0 : take(nfpt * c->M * sizeof(double));
   c->off_thf = take(nfpt * sizeof(double));
   c->off_guard = take(nfpt * sizeof(uint32_t));
   {
@@ -1125,14 +1150,22 @@ lwfr_status lwfr_batch_init(const lwfr_config* cfgs, int32_t count, lwfr_batch**
     BatchTable& t = v < 2 ? b->tab[v] : b->stab[v - 2];
     t.tile_threads = tt[v & 1];
     t.tile_begin.assign(count + 1, 0);
-    for (int i = 0; i < count; ++i) {
-      const lwfr_ctx* c = b->inst[i];
-      const int lanes = v < 2 ? 1 : (c->DIM == 2 && c->M >= 8 ? 2 : 1);  // stage_lanes
-      const int epb = tt[v & 1] / (lanes * c->P);
-      const int nb = (c->E + epb - 1) / epb;
-      for (int k = 0; k < nb; ++k) { t.tinst.push_back(i); t.tblk.push_back(k); }
-      t.tile_begin[i + 1] = (int)t.tinst.size();
+    // the stage tables list the tiles of each degree together (one launch per
+    // degree); the other tables keep the problems in order
+    for (int deg = 1; deg <= 4; ++deg) {
+      t.deg_begin[deg] = (int)t.tinst.size();
+      for (int i = 0; i < count; ++i) {
+        const lwfr_ctx* c = b->inst[i];
+        if (v >= 2 && c->N != deg) continue;
+        if (v < 2 && deg != 1) continue;
+        const int lanes = v < 2 ? 1 : (c->DIM == 2 && c->M >= 8 ? 2 : 1);  // stage_lanes
+        const int epb = tt[v & 1] / (lanes * c->P);
+        const int nb = (c->E + epb - 1) / epb;
+        for (int k = 0; k < nb; ++k) { t.tinst.push_back(i); t.tblk.push_back(k); }
+        t.tile_begin[i + 1] = (int)t.tinst.size();
+      }
     }
+    t.deg_begin[5] = (int)t.tinst.size();
     t.ntiles = (int)t.tinst.size();
   }
   {
