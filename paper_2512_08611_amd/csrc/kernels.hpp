@@ -60,6 +60,25 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+// Synchronisation of the lanes that share one element's LDS slot.  When no
+// element straddles two waves (LANES lanes per element dividing the 64 of a
+// wave), those lanes are one wave: a wave-level fence orders their LDS
+// accesses, and waves no longer wait for each other at workgroup barriers.
+// Otherwise a workgroup barrier.
+#ifndef LWFR_WAVE_LOCAL_SYNC
+#define LWFR_WAVE_LOCAL_SYNC 1
+#endif
+template <int LANES>
+__device__ __forceinline__ void elem_sync() {
+  if constexpr (LWFR_WAVE_LOCAL_SYNC && 64 % LANES == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 #ifndef STAGES_WAVES_PER_EU
 #define STAGES_WAVES_PER_EU 1
 #endif
@@ -199,7 +218,7 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
 #pragma unroll
   for (int v = 0; v < M; ++v) s_u[le][v][p] = x[v];
   if (want_alpha) s_q[le][p] = Ph::indicator(x, pp);
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
   // element mean of each variable, summed over the nodes in order
   for (int v = p; v < M; v += P) {
     double s = 0.0;
@@ -227,7 +246,7 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
       s_t[le][p] = t;
     }
   }
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
   if (want_alpha) {
     if constexpr (DIM == 2) {
       const int k = p % n1, l = p / n1;
@@ -236,7 +255,7 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
     }
     s_q[le][p] = mode * mode;
   }
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
   if (p == 0) {
     double lam = 0.0;
     if (act) {
@@ -279,7 +298,7 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
     a = fmin(a, kp.alpha_max);
     kp.alpha_raw[e] = a;
   }
-  __syncthreads();
+  __syncthreads();  // the block-wide maximum reads every element slot
   if (tid == 0) {
     double m = s_lam[0];
     for (int l = 1; l < EPB; ++l) m = fmax(m, s_lam[l]);
@@ -456,7 +475,7 @@ __device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&s
     for (int v = 0; v < M; ++v) sb[d * M + v][p] = Fa[d][v];
 #pragma unroll
   for (int v = 0; v < M; ++v) sb[DIM * M + v][p] = Ua[v];
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
 
   if (act) {
 #pragma unroll
@@ -510,7 +529,7 @@ __device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&s
       C[k][v] = t + C[k][v];
     }
   }
-  __syncthreads();  // every read of the F and U rows is done
+  elem_sync<ipow(N + 1, Ph::DIM)>();  // every read of the F and U rows is done
   double* flat = &sb[0][0];
 #pragma unroll
   for (int k = 0; k < NOWN; ++k) {
@@ -520,7 +539,7 @@ __device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&s
       for (int v = 0; v < M; ++v) flat[w * M + v] = C[k][v];
     }
   }
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
   if (act) {
     double R[M];
 #pragma unroll
@@ -551,7 +570,7 @@ __device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&s
       if (d_alpha_out) d_alpha_out[e] = a;
     }
   }
-  __syncthreads();  // the LDS rows are free again (batched tile loops reuse them)
+  elem_sync<ipow(N + 1, Ph::DIM)>();  // the LDS rows are free again (batched tile loops reuse them)
 }
 
 template <class Ph, int N, int NB, int PS>
@@ -568,7 +587,7 @@ __device__ __forceinline__ void stage_outputs_plain(const KParams& kp, double (&
     for (int v = 0; v < M; ++v) sb[d * M + v][p] = Fa[d][v];
 #pragma unroll
   for (int v = 0; v < M; ++v) sb[DIM * M + v][p] = Ua[v];
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
 
   if (act) {
 #pragma unroll
@@ -720,7 +739,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
         for (int d = 0; d < DIM; ++d) Fa[d][v] += bs * f[d][v];
       }
     }
-    __syncthreads();
+    elem_sync<ipow(N + 1, Ph::DIM)>();
     double Ls[M];
 #pragma unroll
     for (int v = 0; v < M; ++v) Ls[v] = 0.0;
@@ -750,7 +769,7 @@ __device__ __forceinline__ void stages_body(const KParams& kp, StagesLds<Ph, N, 
 #pragma unroll
       for (int v = 0; v < M; ++v) Ls[v] += (df[v] + nc[v]) * kp.inv_dx[d];
     }
-    __syncthreads();
+    elem_sync<ipow(N + 1, Ph::DIM)>();
     if (bs != 0.0) {
 #pragma unroll
       for (int v = 0; v < M; ++v) Ra[v] += bs * Ls[v];
@@ -1012,7 +1031,7 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
       s_buf[le][(2 * M + vo + k) * P + (p)] = Ua[k];
       s_buf[le][(3 * M + vo + k) * P + (p)] = uo[k];
     }
-  __syncthreads();
+  elem_sync<2 * (N + 1) * (N + 1)>();
 
   // face traces, one face point (all variables) per lane, and the correction
   // offsets C = F_tr + B_d(u^n_tr) U_tr of those face points
@@ -1063,12 +1082,12 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
       C[v] = tf + C[v];
     }
   }
-  __syncthreads();  // every read of the F, U and u^n fields is done
+  elem_sync<2 * (N + 1) * (N + 1)>();  // every read of the F, U and u^n fields is done
   if (own) {
 #pragma unroll
     for (int v = 0; v < M; ++v) s_buf[le][tl * M + v] = C[v];
   }
-  __syncthreads();
+  elem_sync<2 * (N + 1) * (N + 1)>();
   if (act) {
     const int i = p % n1, j = p / n1;
 #pragma unroll
@@ -1180,7 +1199,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
       for (int k = 0; k < H0; ++k) Ua[k] += bs * uh[k];
     }
-    __syncthreads();
+    elem_sync<2 * (N + 1) * (N + 1)>();
     // L_d = (D_d f_d + B_d(u) D_d u) / dx_d
     double Ld[M];
     {
@@ -1205,7 +1224,7 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
         Ld[v] = (sacc + nc[v]) * idx;
       }
     }
-    __syncthreads();
+    elem_sync<2 * (N + 1) * (N + 1)>();
     // L = L_x + L_y on the lane's half
     double Lh[H0];
 #pragma unroll
@@ -2068,7 +2087,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
     for (int v = 0; v < M; ++v) uH[v] = un[v] - dt * R[v];
   }
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
   double us[M];
   if (kp.blending == 0) {
 #pragma unroll
@@ -2091,7 +2110,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
       for (int v = 0; v < M; ++v) s_f[le][v][p] = fo[v];
       s_red[le][p] = sg;
-      __syncthreads();
+      elem_sync<ipow(N + 1, Ph::DIM)>();
       double right[M];
       if (ii < N) {
         const int pn = node_at<n1>(d, q, ii < N ? ii + 1 : ii);
@@ -2116,7 +2135,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
         for (int v = 0; v < M; ++v) right[v] = kp.Fm[((size_t)d * M + v) * nf + fR];
       }
-      __syncthreads();
+      elem_sync<ipow(N + 1, Ph::DIM)>();
       double left[M];
       if (ii > 0) {
 #pragma unroll
@@ -2128,7 +2147,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
       }
 #pragma unroll
       for (int v = 0; v < M; ++v) RL[v] += (right[v] - left[v]) * kp.inv_wdx[d][ii];
-      __syncthreads();
+      elem_sync<ipow(N + 1, Ph::DIM)>();
     }
     double uL[M];
 #pragma unroll
@@ -2153,7 +2172,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
       Pa[k] = Ph::constraint(k, uL, pp);
       s_f[le][k][p] = Pa[k];
     }
-    __syncthreads();
+    elem_sync<ipow(N + 1, Ph::DIM)>();
     if (p == 0) {
 #pragma unroll
       for (int k = 0; k < Ph::K; ++k) {
@@ -2163,7 +2182,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
         s_red[le][k] = m;
       }
     }
-    __syncthreads();
+    elem_sync<ipow(N + 1, Ph::DIM)>();
     double Pmin[Ph::K > 0 ? Ph::K : 1];
 #pragma unroll
     for (int k = 0; k < Ph::K; ++k) {
@@ -2175,16 +2194,16 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
       for (int k = 0; k < Ph::K; ++k) {
         bool guard = false;
         const double th_p = theta_limit(0.1 * Pmin[k], Pa[k], Ph::constraint(k, us, pp), guard);
-        __syncthreads();  // every point has read the previous minimum
+        elem_sync<ipow(N + 1, Ph::DIM)>();  // every point has read the previous minimum
         s_left[le][0][p] = th_p;
-        __syncthreads();
+        elem_sync<ipow(N + 1, Ph::DIM)>();
         if (p == 0) {
           double m = s_left[le][0][0];
 #pragma unroll
           for (int r = 1; r < P; ++r) m = fmin(m, s_left[le][0][r]);
           s_red[le][Ph::K + k] = m;
         }
-        __syncthreads();
+        elem_sync<ipow(N + 1, Ph::DIM)>();
         const double th = s_red[le][Ph::K + k];
         if (th < 1.0) {
 #pragma unroll
@@ -2221,7 +2240,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     fl |= (th < 1.0 ? 4u : 0u) | (gu ? 16u : 0u);
   }
   s_fl[le][p] = fl;
-  __syncthreads();
+  elem_sync<ipow(N + 1, Ph::DIM)>();
   if (act && p == 0) {
     uint32_t f = 0;
 #pragma unroll
