@@ -111,7 +111,7 @@ struct KParams {
   double* alpha;              // [E] smoothed alpha used by the step
   double* Ftr;                // [d][side][M][E*nfp] trace of F_d
   double* Utr;                // [d][side][M][E*nfp] trace of U
-  double* untr;               // [d][side][M][E*nfp] trace of u^n
+  double* untr;               // [d][side][M][E*nfp] trace of u^n (adjoint records only; null: not written)
   double* Fm;                 // [d][M][E*nfp] F^- of face (e, e+1)
   double* Fp;                 // [d][M][E*nfp] F^+
   double* Dm;                 // [d][M][E*nfp] F^- - F_tr^- - B(u^{n,-}) U^- (systems that do not fold it)
@@ -506,7 +506,7 @@ __device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&s
 #pragma unroll
       for (int r = 0; r < n1; ++r) t += V[r] * un_g[((size_t)v * kp.E + e) * P + (d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r))];
       a[v] = t;
-      kp.untr[((size_t)(d * 2 + side) * M + v) * nf + fo] = t;
+      if (kp.untr) kp.untr[((size_t)(d * 2 + side) * M + v) * nf + fo] = t;
     }
 #pragma unroll
     for (int v = 0; v < M; ++v) {
@@ -605,18 +605,25 @@ __device__ __forceinline__ void stage_outputs_plain(const KParams& kp, double (&
       const size_t nf = (size_t)kp.E * NFP;
       const size_t fo = (size_t)e * NFP + q;
       {
-        double tf = 0.0, tu = 0.0, tn = 0.0;
+        double tf = 0.0, tu = 0.0;
 #pragma unroll
         for (int r = 0; r < n1; ++r) {
           const int nd = d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r);
           tf += V[r] * sb[d * M + v][nd];
           tu += V[r] * sb[DIM * M + v][nd];
-          tn += V[r] * un_g[((size_t)v * kp.E + e) * P + nd];
         }
         const size_t o = ((size_t)(d * 2 + side) * M + v) * nf + fo;
         kp.Ftr[o] = tf;
         kp.Utr[o] = tu;
-        kp.untr[o] = tn;
+        // the u^n trace only for the adjoint's records: the face kernels form it
+        // from the line of nodes they read anyway
+        if (kp.untr) {
+          double tn = 0.0;
+#pragma unroll
+          for (int r = 0; r < n1; ++r)
+            tn += V[r] * un_g[((size_t)v * kp.E + e) * P + (d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r))];
+          kp.untr[o] = tn;
+        }
       }
     }
     // blending coefficient of the element (smoothed over face neighbours)
@@ -1061,7 +1068,7 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       a[v] = trace(3 * M, v);
-      kp.untr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = a[v];
+      if (kp.untr) kp.untr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = a[v];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1486,6 +1493,31 @@ __device__ inline bool admissible(const double* x, const PhysParams& pp) {
   return ok;
 }
 
+// u^n along the line of direction d through face point q of element el: its
+// trace at the element's face fs (0 left, 1 right), the sum the stage kernel
+// forms for its face traces, the node on that face (s) and the next one inward
+// (si).  The line lies in the cache lines the face kernel reads for s and si,
+// so the trace costs no HBM traffic of its own.
+template <class Ph, int N, int d>
+__device__ __forceinline__ void line_trace(const KParams& kp, const double* __restrict__ un_g, int el, int q, int fs,
+                                           double (&a)[Ph::M], double (&s)[Ph::M], double (&si)[Ph::M]) {
+  constexpr int n1 = N + 1, P = ipow(n1, Ph::DIM), M = Ph::M;
+  const double* V = fs ? kp.VR : kp.VL;
+#pragma unroll
+  for (int v = 0; v < M; ++v) {
+    const double* x = un_g + ((size_t)v * kp.E + el) * P;
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < n1; ++r) {
+      const double y = x[node_at<n1>(d, q, r)];
+      t += V[r] * y;
+      if (r == (fs ? N : 0)) s[v] = y;
+      if (r == (fs ? N - 1 : 1)) si[v] = y;
+    }
+    a[v] = t;
+  }
+}
+
 // one face point of direction d between element e (minus side) and en (plus
 // side).  Written so that few values are live at once: the traces die once
 // F^num, U^num (and the correction offsets C^± of the systems that do not fold
@@ -1498,31 +1530,18 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
   const int en = nbr_elem(kp, e, d, 1);
   const size_t nf = (size_t)kp.E * NFP;
   const size_t fiL = (size_t)e * NFP + q, fiR = (size_t)en * NFP + q;
-  // trace index of side (0 left face, 1 right face); u^n of point r along the line
+  // trace index of side (0 left face, 1 right face)
   auto tr = [&](int side, int v, size_t fi) { return ((size_t)(d * 2 + side) * M + v) * nf + fi; };
-  auto node = [&](int v, int el, int r) { return un_g[((size_t)v * kp.E + el) * P + node_at<n1>(d, q, r)]; };
-  double sL[M], sR[M];
-#pragma unroll
-  for (int v = 0; v < M; ++v) {
-    sL[v] = node(v, e, N);
-    sR[v] = node(v, en, 0);
-  }
-  // the next nodes inward (Algorithm 1) share those cache lines: read them now
-  double sLi[M], sRi[M];
-  if (kp.blending == 2 && N >= 1) {
-#pragma unroll
-    for (int v = 0; v < M; ++v) {
-      sLi[v] = node(v, e, N - 1);
-      sRi[v] = node(v, en, 1);
-    }
-  }
+  // u^n at the face from each side's line of nodes, the nodes on the face and
+  // the next ones inward (Algorithm 1)
+  double sL[M], sR[M], sLi[M], sRi[M];
   double Fm[M], Fp[M], Cm[M], Cp[M];
   {
     double a[M], b[M], UL[M], UR[M];
+    line_trace<Ph, N, d>(kp, un_g, e, q, 1, a, sL, sLi);
+    line_trace<Ph, N, d>(kp, un_g, en, q, 0, b, sR, sRi);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      a[v] = kp.untr[tr(1, v, fiL)];
-      b[v] = kp.untr[tr(0, v, fiR)];
       UL[v] = kp.Utr[tr(1, v, fiL)];
       UR[v] = kp.Utr[tr(0, v, fiR)];
       Cm[v] = kp.Ftr[tr(1, v, fiL)];
@@ -1663,23 +1682,15 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
   const size_t nf = (size_t)kp.E * NFP;
   const size_t fio = (size_t)eo * NFP + q;
   auto tr = [&](int v) { return ((size_t)(d * 2 + ts) * M + v) * nf + fio; };
-  auto node = [&](int v, int r) { return un_g[((size_t)v * kp.E + eo) * P + node_at<n1>(d, q, r)]; };
-  double s[M];
-#pragma unroll
-  for (int v = 0; v < M; ++v) s[v] = node(v, side ? 0 : N);
-  // the next node inward (Algorithm 1) shares s's cache lines: read it now, while
-  // they are still in L2, rather than after the face flux
-  double si[M];
-  if (kp.blending == 2 && N >= 1) {
-#pragma unroll
-    for (int v = 0; v < M; ++v) si[v] = node(v, side ? 1 : N - 1);
-  }
+  // u^n at the face from the lane's line of nodes, the node on the face (s)
+  // and the next one inward (si, Algorithm 1)
+  double s[M], si[M];
   double F[M], C[M];
   {
     double a[M], U[M];
+    line_trace<Ph, N, d>(kp, un_g, eo, q, ts, a, s, si);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
-      a[v] = kp.untr[tr(v)];
       U[v] = kp.Utr[tr(v)];
       C[v] = kp.Ftr[tr(v)];
     }
@@ -1946,12 +1957,10 @@ __device__ inline void bface_point(const KParams& kp, const double* __restrict__
 #pragma unroll
   for (int v = 0; v < M; ++v) {
     const size_t o = ((size_t)(d * 2 + fs) * M + v) * nf + fi;
-    in.a[v] = kp.untr[o];
     in.U[v] = kp.Utr[o];
     in.F[v] = kp.Ftr[o];
-    in.s[v] = un_g[((size_t)v * kp.E + ei) * P + node_at<n1>(d, q, fs ? N : 0)];
-    in.si[v] = un_g[((size_t)v * kp.E + ei) * P + node_at<n1>(d, q, fs ? N - 1 : 1)];
   }
+  line_trace<Ph, N, d>(kp, un_g, ei, q, fs, in.a, in.s, in.si);
   ghost_state<Ph, NFP>(kp, d, fs, j, in, gh);
   const double af = kp.blending == 0 ? 0.0 : kp.alpha[ei];
   double Fm[M], Fp[M], Theta;

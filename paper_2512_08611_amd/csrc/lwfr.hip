@@ -412,7 +412,7 @@ void carve_kp(const lwfr_ctx* c, char* b, KParams& kp) {
   kp.theta_elem = reinterpret_cast<double*>(b + c->off_thel);
   kp.Ftr = reinterpret_cast<double*>(b + c->off_Ftr);
   kp.Utr = reinterpret_cast<double*>(b + c->off_Utr);
-  kp.untr = reinterpret_cast<double*>(b + c->off_untr);
+  kp.untr = c->off_untr ? reinterpret_cast<double*>(b + c->off_untr) : nullptr;
   kp.Fm = reinterpret_cast<double*>(b + c->off_Fm);
   kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
   kp.Dm = c->off_Dm ? reinterpret_cast<double*>(b + c->off_Dm) : nullptr;
@@ -770,7 +770,10 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_thel = take((size_t)c->E * sizeof(double));
   c->off_Ftr = take(nfpt * 2 * c->M * sizeof(double));
   c->off_Utr = take(nfpt * 2 * c->M * sizeof(double));
-  c->off_untr = take(nfpt * 2 * c->M * sizeof(double));
+  // the u^n traces are kept only for the adjoint (the face kernels of a step
+  // form them from the solution points they read)
+  c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
+  c->off_untr = c->adjoint ? take(nfpt * 2 * c->M * sizeof(double)) : 0;
   c->off_Fm = take(nfpt * c->M * sizeof(double));
   c->off_Fp = take(nfpt * c->M * sizeof(double));
   // the correction jumps D^± of the systems that do not fold the correction
@@ -790,7 +793,6 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_eflags = take((size_t)c->E * sizeof(uint32_t));
   c->off_srows = take((size_t)c->nblk_stats * kStatsRow * sizeof(double));
   c->fwd_bytes = off;  // the forward step's part of the workspace (the adjoint's arrays follow)
-  c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
   if (c->adjoint) {
     const size_t nst = (size_t)c->M * c->E * c->P * sizeof(double);
     c->off_uscr = take(nst);

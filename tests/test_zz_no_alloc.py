@@ -2,8 +2,9 @@
 static device scratch as workspace) against lwfr_step with a caller workspace,
 through the C ABI: two calls in a row, the second on a smaller problem (so stale
 scratch contents of the first would show), each bit for bit equal to lwfr_step
-(the same kernels in the same order), with dt, c_h and the element flags; and a
-problem whose workspace exceeds the scratch is refused with LWFR_E_WORKSPACE."""
+(the same kernels in the same order), with dt, c_h and the element flags; the
+largest square GLM-MHD N=3 mesh whose workspace fits the scratch steps equal to
+lwfr_step too, and the next larger one is refused with LWFR_E_WORKSPACE."""
 import numpy as np
 import pytest
 import torch
@@ -45,10 +46,25 @@ def test_noalloc_step_equals_bound_step_twice():
     assert nb > 0  # the limiters acted, so the flag paths were exercised
 
 
-def test_noalloc_refuses_a_problem_beyond_the_scratch():
-    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (128, 128), blending=2)
+SCRATCH_BYTES = 64 << 20  # LWFR_STATIC_SCRATCH_BYTES
+
+
+def _ws_bytes(n):
+    ctx = lwfr.lwfr_init(lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (n, n), blending=2))
+    b = lwfr.lwfr_workspace_bytes(ctx)
+    lwfr.lwfr_destroy(ctx)
+    return b
+
+
+def test_noalloc_largest_problem_fits_and_the_next_is_refused():
+    """GLM-MHD N=3: 136 x 136 elements are the largest square mesh whose step
+    workspace fits the scratch; it steps equal to lwfr_step, and 137 x 137 is refused."""
+    assert _ws_bytes(136) <= SCRATCH_BYTES < _ws_bytes(137)
+    st, u = _case(3, 136, 136, 2)
+    _compare(st, u)
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (137, 137), blending=2)
     ctx = lwfr.lwfr_init(cfg)
-    u = torch.zeros((9, 128 * 128, 16), dtype=torch.float64, device=DEV)
+    u = torch.zeros((9, 137 * 137, 16), dtype=torch.float64, device=DEV)
     with pytest.raises(lwfr.LwfrError) as ei:
         lwfr.lwfr_step_noalloc(ctx, u, torch.empty_like(u))
     assert ei.value.status == lwfr.LWFR_E_WORKSPACE and "static scratch" in str(ei.value)
