@@ -1779,16 +1779,34 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
   }
 }
 
+// Face point slot `slot` (of `slots` per workgroup) of workgroup blk, as
+// (direction, face point index within the direction).  In 2-D the first half of
+// the slots take face points [blk*W, blk*W + W) of direction 0 and the second
+// half the same points of direction 1 (W = slots/2): one workgroup reads each
+// element's nodes and traces for both directions while they are in cache, and
+// every wave keeps one direction.  The grid is the same as for direction-major
+// slots.
+template <int DIM>
+__device__ __forceinline__ void face_slot(int blk, int slot, int slots, int& d, int& fi) {
+  if constexpr (DIM == 2) {
+    const int W = slots / 2;
+    d = slot >= W ? 1 : 0;
+    fi = blk * W + slot - d * W;
+  } else {
+    d = 0;
+    fi = blk * slots + slot;
+  }
+}
+
 template <class Ph, int N>
 __device__ __forceinline__ void faces2_body(const KParams& kp, const double* __restrict__ un_g, int blk) {
   constexpr int DIM = Ph::DIM, NFP = DIM == 1 ? 1 : N + 1;
   const int t = threadIdx.x;
   const int side = (t >> 5) & 1;
-  const int gid = blk * (int)(blockDim.x / 2) + (((t >> 6) << 5) | (t & 31));
   const int nf = kp.E * NFP;
-  if (gid >= DIM * nf) return;  // both lanes of a face point leave together
-  const int d = gid / nf;
-  const int fi = gid - d * nf;
+  int d, fi;
+  face_slot<DIM>(blk, ((t >> 6) << 5) | (t & 31), (int)(blockDim.x / 2), d, fi);
+  if (fi >= nf) return;  // both lanes of a face point leave together
   const int e = fi / NFP, q = fi - (fi / NFP) * NFP;
   const double dt = kp.scal[0];
   const PhysParams pp = phys_params(kp, kp.scal[1]);
@@ -1813,7 +1831,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES2
 template <class Ph, int N>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FACES_WAVES_PER_EU)))
     k_faces(const KParams kp, const double* __restrict__ un_g) {
-  faces_body<Ph, N>(kp, un_g, xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x);
+  constexpr int NFP = Ph::DIM == 1 ? 1 : N + 1;
+  const int nf = kp.E * NFP;
+  int d, fi;
+  face_slot<Ph::DIM>(xcd_block(blockIdx.x, gridDim.x), threadIdx.x, (int)blockDim.x, d, fi);
+  if (fi >= nf) return;
+  faces_body<Ph, N>(kp, un_g, d * nf + fi);
 }
 
 // ------------------------------------------------------------------------
