@@ -1457,6 +1457,32 @@ __global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((
 
 // ------------------------------------------------------------------------
 // lower order fluxes f^{num,-}, f^{num,+}(uL, uR) of eq. combined.num.flux
+// The same with the fluxes fL = f_d(uL), fR = f_d(uR) and wave speeds sl, sr of
+// the two states given (a state shared by two subfaces is evaluated once).
+template <class Ph, int d>
+__device__ inline void low_flux_given(const double* uL, const double* uR, const double* fL, const double* fR,
+                                      double sl, double sr, double* fm, double* fp, const PhysParams& pp) {
+  constexpr int M = Ph::M;
+  double fc[M], t[M];
+  const double lam = sl >= sr ? sl : sr;
+#pragma unroll
+  for (int v = 0; v < M; ++v) fc[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+#pragma unroll
+  for (int v = 0; v < M; ++v) t[v] = 0.5 * (uL[v] + uR[v]);  // average state
+  if (fm) {
+    double b[M];
+    Ph::template ncprod<d>(uL, t, b, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) fm[v] = fc[v] + b[v];
+  }
+  if (fp) {
+    double b[M];
+    Ph::template ncprod<d>(uR, t, b, pp);
+#pragma unroll
+    for (int v = 0; v < M; ++v) fp[v] = fc[v] + b[v];
+  }
+}
+
 template <class Ph, int d>
 __device__ inline void low_flux(const double* uL, const double* uR, double* fm, double* fp, const PhysParams& pp) {
   // few live arrays: the central part is formed in fc, then the two
@@ -1549,8 +1575,18 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
     }
     // wave speed from the face values of u^n; an inadmissible face value uses
     // its neighbouring solution point instead
-    const double sa = admissible<Ph>(a, pp) ? Ph::template sigma<d>(a, pp) : Ph::template sigma<d>(sL, pp);
-    const double sb = admissible<Ph>(b, pp) ? Ph::template sigma<d>(b, pp) : Ph::template sigma<d>(sR, pp);
+    // (the state is selected first: one wave speed evaluation per side)
+    double sa, sb;
+    {
+      const bool oka = admissible<Ph>(a, pp), okb = admissible<Ph>(b, pp);
+      double w[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) w[v] = oka ? a[v] : sL[v];
+      sa = Ph::template sigma<d>(w, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) w[v] = okb ? b[v] : sR[v];
+      sb = Ph::template sigma<d>(w, pp);
+    }
     const double lam = sa >= sb ? sa : sb;
     double Unum[M], t[M];
 #pragma unroll
@@ -1579,21 +1615,30 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
   double Theta = 1.0;
   bool guard = false;
   if (!(af == 0.0 && kp.blending != 2)) {
+    // the two face nodes' fluxes and wave speeds serve the face's lower order
+    // flux and the inner subface fluxes of Algorithm 1
+    double fL[M], fR[M];
+    Ph::template flux<d>(sL, fL, pp);
+    Ph::template flux<d>(sR, fR, pp);
+    const double gL = Ph::template sigma<d>(sL, pp), gR = Ph::template sigma<d>(sR, pp);
+    // Algorithm 1 with DIM*dt in the candidate updates of the two subcells
+    // next to the face: their inner subface fluxes f^{num,+}(sLi, sL), f^{num,-}(sR, sRi)
+    double finL[M], finR[M];
+    if (kp.blending == 2 && N >= 1) {
+      double f2[M];
+      Ph::template flux<d>(sLi, f2, pp);
+      low_flux_given<Ph, d>(sLi, sL, f2, fL, Ph::template sigma<d>(sLi, pp), gL, nullptr, finL, pp);
+      Ph::template flux<d>(sRi, f2, pp);
+      low_flux_given<Ph, d>(sR, sRi, fR, f2, gR, Ph::template sigma<d>(sRi, pp), finR, nullptr, pp);
+    }
     double fLOm[M], fLOp[M];
-    low_flux<Ph, d>(sL, sR, fLOm, fLOp, pp);
+    low_flux_given<Ph, d>(sL, sR, fL, fR, gL, gR, fLOm, fLOp, pp);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       Fm[v] = (1.0 - af) * Fm[v] + af * fLOm[v];
       Fp[v] = (1.0 - af) * Fp[v] + af * fLOp[v];
     }
     if (kp.blending == 2 && N >= 1) {
-      // Algorithm 1 with DIM*dt in the candidate updates of the two subcells
-      // next to the face
-      double finL[M], finR[M];
-      {
-        low_flux<Ph, d>(sLi, sL, nullptr, finL, pp);
-        low_flux<Ph, d>(sR, sRi, finR, nullptr, pp);
-      }
       const double cN = DIM * dt * kp.inv_wdx[d][N], c0 = DIM * dt * kp.inv_wdx[d][0];
 #pragma unroll
       for (int k = 0; k < Ph::K; ++k) {
@@ -1694,7 +1739,16 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
       U[v] = kp.Utr[tr(v)];
       C[v] = kp.Ftr[tr(v)];
     }
-    const double sg = admissible<Ph>(a, pp) ? Ph::template sigma<d>(a, pp) : Ph::template sigma<d>(s, pp);
+    // wave speed at the face value of u^n, or at the node if that is not
+    // admissible (the state is selected first: one wave speed evaluation)
+    double sg;
+    {
+      const bool ok = admissible<Ph>(a, pp);
+      double w[M];
+#pragma unroll
+      for (int v = 0; v < M; ++v) w[v] = ok ? a[v] : s[v];
+      sg = Ph::template sigma<d>(w, pp);
+    }
     double sa, sb;
     pair_values(sg, sa, sb);
     const double lam = sa >= sb ? sa : sb;
@@ -1715,35 +1769,53 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
   double Theta = 1.0;
   bool guard = false;
   if (!(af == 0.0 && kp.blending != 2)) {
+    // the node's flux and wave speed, for the lower order flux at the face and
+    // for the inner subface flux of Algorithm 1
+    double fs[M];
+    Ph::template flux<d>(s, fs, pp);
+    const double gs = Ph::template sigma<d>(s, pp);
+    // Algorithm 1 works on the lane's subcell next to the face (DIM*dt in its
+    // update).  Its inner subface flux (eq. combined.num.flux): on the plus
+    // lane f^{e+1,-}_{1/2} = f^{num,-}(s, si), on the minus lane f^{e,+}_{N-1/2}
+    // = f^{num,+}(si, s); both take the non-conservative product at s.  Formed
+    // first, so that si and its flux die before the face's fluxes are blended
+    double fin[M];
+    if (kp.blending == 2 && N >= 1) {
+      double fi[M], avg[M], t[M];
+      Ph::template flux<d>(si, fi, pp);
+      const double gi = Ph::template sigma<d>(si, pp);
+      const double lam = side ? (gs >= gi ? gs : gi) : (gi >= gs ? gi : gs);
+#pragma unroll
+      for (int v = 0; v < M; ++v) {
+        fin[v] = 0.5 * (fs[v] + fi[v]) - 0.5 * lam * (side ? si[v] - s[v] : s[v] - si[v]);
+        avg[v] = 0.5 * (s[v] + si[v]);
+      }
+      Ph::template ncprod<d>(s, avg, t, pp);
+#pragma unroll
+      for (int v = 0; v < M; ++v) fin[v] += t[v];
+    }
     // lower order flux at the face from the two neighbouring node states
     double fLO[M];
     {
-      double f[M], sl[M], sh[M], avg[M];
-      Ph::template flux<d>(s, f, pp);
+      double sl[M], sh[M], avg[M], t[M];
       double gl, gh;
-      pair_values(Ph::template sigma<d>(s, pp), gl, gh);
+      pair_values(gs, gl, gh);
       const double lam = gl >= gh ? gl : gh;
 #pragma unroll
       for (int v = 0; v < M; ++v) {
         double fl, fh;
-        pair_values(f[v], fl, fh);
+        pair_values(fs[v], fl, fh);
         pair_values(s[v], sl[v], sh[v]);
         fLO[v] = 0.5 * (fl + fh) - 0.5 * lam * (sh[v] - sl[v]);
         avg[v] = 0.5 * (sl[v] + sh[v]);
       }
-      Ph::template ncprod<d>(s, avg, f, pp);
+      Ph::template ncprod<d>(s, avg, t, pp);
 #pragma unroll
-      for (int v = 0; v < M; ++v) fLO[v] += f[v];
+      for (int v = 0; v < M; ++v) fLO[v] += t[v];
     }
 #pragma unroll
     for (int v = 0; v < M; ++v) F[v] = (1.0 - af) * F[v] + af * fLO[v];
     if (kp.blending == 2 && N >= 1) {
-      // Algorithm 1: the lane's subcell next to the face, DIM*dt in its update
-      double fin[M];
-      {
-        if (side) low_flux<Ph, d>(s, si, fin, nullptr, pp);  // f^{e+1,-}_{1/2}
-        else low_flux<Ph, d>(si, s, nullptr, fin, pp);       // f^{e,+}_{N-1/2}
-      }
       const double cs = DIM * dt * kp.inv_wdx[d][side ? 0 : N];
 #pragma unroll
       for (int k = 0; k < Ph::K; ++k) {
