@@ -184,12 +184,15 @@ __device__ inline double theta_limit(double eps, double Pa, double Pb, bool& gua
 // batched kernels (several problems, one launch) run the same code.  A block
 // of NT threads has ceil(NT/P) element slots in LDS; slots at or beyond EPB
 // hold no element (their threads only take part in the barriers).
+// Rows are padded by one double: with P a multiple of 16 (2-D, N = 3) the
+// threads that walk a row each (one per variable, one per element) would
+// otherwise all hit the same LDS banks.
 template <class Ph, int N, int NT>
 struct PreLds {
   static constexpr int P = ipow(N + 1, Ph::DIM), EL = (NT + P - 1) / P;
-  double s_u[EL][Ph::M][P];
-  double s_q[EL][P];   // indicator variable at the nodes, then the squared modes
-  double s_t[EL][P];   // 2-D: the first pass of the modal projection
+  double s_u[EL][Ph::M][P + 1];
+  double s_q[EL][P + 1];   // indicator variable at the nodes, then the squared modes
+  double s_t[EL][P + 1];   // 2-D: the first pass of the modal projection
   double s_ub[EL][Ph::M];
   double s_lam[EL];
 };
