@@ -2174,6 +2174,24 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
   for (int d = 0; d < DIM; ++d) eL[d] = nbr_elem(kp, es, d, 0);
   uint32_t fl = 0;
+  const double al = kp.alpha[es];
+  // Algorithm 1 activity on the element's faces (a theta below 1, or the guard),
+  // loaded first so that the loads' latency hides behind the update: the
+  // element's threads take face points w = (side, d, q), its right faces, then
+  // its left faces, whose slot is the left neighbour's, or a boundary half face
+  // (a boundary half face's own values are read at the end, by its threads only)
+  constexpr int NFW = 2 * DIM * NFP, NW = (NFW + P - 1) / P;
+  double thw[NW];
+  uint32_t guw[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int w = p + k * P < NFW ? p + k * P : 0;  // threads past the face points read point 0
+    const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
+    const int ef = side ? (d == 0 ? eL[0] : eL[DIM - 1]) : es;
+    const size_t fo = (size_t)d * nf + (size_t)ef * NFP + q;
+    thw[k] = kp.blending == 2 ? kp.theta_face[fo] : 1.0;
+    guw[k] = kp.blending == 2 ? kp.guard_face[fo] : 0u;
+  }
   // high order update
   double uH[M];
   {
@@ -2266,7 +2284,6 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
       for (int v = 0; v < M; ++v) uL[v] = x[v];
     }
-    const double al = kp.alpha[es];
 #pragma unroll
     for (int v = 0; v < M; ++v) us[v] = (1.0 - al) * uH[v] + al * uL[v];
     // Algorithm 2.  Element minima: every point stores its value, one thread
@@ -2330,21 +2347,17 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
     for (int v = 0; v < M; ++v) io[((size_t)v * kp.E + e) * P + p] = us[v];
   }
-  // Algorithm 1 activity on the element's faces: the element's threads read
-  // face points w = (side, d, q) (its right faces, then its left faces, whose
-  // slot is the left neighbour's, or a boundary half face)
-  for (int w = p; kp.blending == 2 && w < 2 * DIM * NFP; w += P) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int w = p + k * P;
+    if (w >= NFW) continue;
     const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
-    const int ef = side ? (d == 0 ? eL[0] : eL[DIM - 1]) : es;
-    const size_t fo = (size_t)d * nf + (size_t)ef * NFP + q;
-    double th = kp.theta_face[fo];
-    uint32_t gu = kp.guard_face[fo];
-    if (side && on_boundary(kp, es, d, 0)) {  // a boundary half face
+    if (kp.blending == 2 && side && on_boundary(kp, es, d, 0)) {  // a boundary half face
       const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + (size_t)(d == 0 ? es / kp.nx : es % kp.nx) * NFP + q;
-      th = kp.theta_left[bl];
-      gu = kp.guard_left[bl];
+      thw[k] = kp.theta_left[bl];
+      guw[k] = kp.guard_left[bl];
     }
-    fl |= (th < 1.0 ? 4u : 0u) | (gu ? 16u : 0u);
+    fl |= (thw[k] < 1.0 ? 4u : 0u) | (guw[k] ? 16u : 0u);
   }
   s_fl[le][p] = fl;
   elem_sync<ipow(N + 1, Ph::DIM)>();
