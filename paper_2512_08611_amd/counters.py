@@ -60,11 +60,14 @@ def _counter_means(path, counter):
 
 
 def _copy_factor(vals, copy_bytes):
-    """bytes per counter KiB from the largest device copy in the run."""
+    """bytes per counter KiB from the calibration copy: the last of the run's
+    device copies with the largest grid (bench.py makes it after every other
+    launch; an upload of a larger state earlier in the run has the same grid)."""
     copies = [v for k, lst in vals.items() if "copyBuffer" in k for v in lst]
     if not copies:
         raise ValueError("no device copy in the counter run (run bench.py with --copy-calibration)")
-    grid, kib = max(copies)
+    gmax = max(g for g, _ in copies)
+    kib = [c for g, c in copies if g == gmax][-1]
     return copy_bytes / kib
 
 

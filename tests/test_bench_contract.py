@@ -63,3 +63,19 @@ def test_counter_summary_is_tied_to_the_kernel_sources(tmp_path):
     assert counters.read_traffic(str(p), "k_update") == (None, None)
     assert counters.read_traffic(str(p), "k_stages", digest="0" * 64) == (None, None)
     assert counters.read_traffic(str(tmp_path / "missing.md"), "k_stages") == (None, None)
+
+
+def test_copy_calibration_takes_the_last_large_copy(tmp_path):
+    """A state upload larger than the calibration copy, earlier in the run and with
+    the same grid, does not set the factor."""
+    from paper_2512_08611_amd import counters
+
+    head = "Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n"
+    rows = ["__amd_rocclr_copyBuffer,131072,FETCH_SIZE,147475",   # 302 MB state upload
+            "__amd_rocclr_copyBuffer,512,FETCH_SIZE,1.5",
+            "lwfr::k_pre,16384,FETCH_SIZE,131000",
+            "__amd_rocclr_copyBuffer,131072,FETCH_SIZE,131072"]   # the 256 MiB calibration copy
+    p = tmp_path / "c.csv"
+    p.write_text(head + "\n".join(rows) + "\n")
+    vals = counters._counter_means(str(p), "FETCH_SIZE")
+    assert counters._copy_factor(vals, 256 * 1024 * 1024) == 2048.0
