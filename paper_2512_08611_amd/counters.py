@@ -226,7 +226,55 @@ def write_trace_md(path, title, trace_csv, steps, commands, ms_per_step):
     open(path, "w").write("\n".join(lines) + "\n")
 
 
+def launches_by_grid(trace_csv, match="lwfr::"):
+    """{(kernel, grid threads): [durations ns]} from a --kernel-trace run: launches
+    of one kernel on problems of different sizes apart."""
+    out = {}
+    for r in csv.DictReader(open(trace_csv)):
+        if match not in r["Kernel_Name"]:
+            continue
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        out.setdefault((_short(r["Kernel_Name"]), grid), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def write_stats_md(path, title, stats_csv, commands, top=40, trace_csv=None):
+    """The per-kernel table of a rocprofv3 --stats run (every launch of the run);
+    with the run's kernel trace, also the library's kernels per launch grid."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# {title}", "", "Command (run from the repository root R):", "", "```"] + list(commands) + ["```", ""]
+    lines += ["| kernel | calls | total (us) | average (us) | min (us) | max (us) | % |",
+              "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    if trace_csv:
+        by = launches_by_grid(trace_csv)
+        lines += ["", "The library's kernels per launch grid (one grid size per problem size), from the same "
+                  "run's kernel trace:", "",
+                  "| kernel | grid (threads) | launches | mean (us) | min (us) | max (us) |", "|---|---|---|---|---|---|"]
+        for (k, g), v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:top]:
+            lines.append(f"| `{k}` | {g} | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {min(v) / 1e3:.1f} | "
+                         f"{max(v) / 1e3:.1f} |")
+    lines += ["", f"kernel sources sha256: {sources_digest()}", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main():
+    if len(os.sys.argv) > 1 and os.sys.argv[1] == "stats":
+        sp = argparse.ArgumentParser(description="table of a rocprofv3 --stats kernel summary")
+        sp.add_argument("cmd")
+        sp.add_argument("--stats", required=True, help="rocprofv3 --stats kernel_stats.csv")
+        sp.add_argument("--trace", default=None, help="the same run's kernel_trace.csv (per-grid table)")
+        sp.add_argument("--title", default="Kernel statistics")
+        sp.add_argument("--command", action="append", default=[])
+        sp.add_argument("--out", required=True)
+        a = sp.parse_args()
+        write_stats_md(a.out, a.title, a.stats, a.command, trace_csv=a.trace)
+        return
     if len(os.sys.argv) > 1 and os.sys.argv[1] == "trace":
         tp = argparse.ArgumentParser(description="summary of a graph-replay kernel trace")
         tp.add_argument("cmd")
