@@ -1527,21 +1527,40 @@ __device__ inline bool admissible(const double* x, const PhysParams& pp) {
 // forms for its face traces, the node on that face (s) and the next one inward
 // (si).  The line lies in the cache lines the face kernel reads for s and si,
 // so the trace costs no HBM traffic of its own.
-template <class Ph, int N, int d>
+// FS: the face when every lane has the same one (0 or 1), else -1 and the
+// lane's face in fs.
+template <class Ph, int N, int d, int FS = -1>
 __device__ __forceinline__ void line_trace(const KParams& kp, const double* __restrict__ un_g, int el, int q, int fs,
                                            double (&a)[Ph::M], double (&s)[Ph::M], double (&si)[Ph::M]) {
   constexpr int n1 = N + 1, P = ipow(n1, Ph::DIM), M = Ph::M;
-  const double* V = fs ? kp.VR : kp.VL;
+  if constexpr (FS >= 0) fs = FS;
+  // the line is walked from the face inward (step k at node N - k on a right
+  // face, k on a left face), so that the face node and the next one are the
+  // first two steps whichever face the lane has
+  double w[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    if constexpr (FS >= 0) {
+      w[k] = FS ? kp.VR[N - k] : kp.VL[k];
+    } else {
+      // both weights are loaded, then one is picked per lane (the empty asm
+      // keeps the compiler from selecting between the two kernel-argument
+      // addresses instead, which would copy the argument block to scratch)
+      double wl = kp.VL[k], wr = kp.VR[N - k];
+      asm volatile("" : "+v"(wl), "+v"(wr));
+      w[k] = fs ? wr : wl;
+    }
+  }
 #pragma unroll
   for (int v = 0; v < M; ++v) {
     const double* x = un_g + ((size_t)v * kp.E + el) * P;
     double t = 0.0;
 #pragma unroll
-    for (int r = 0; r < n1; ++r) {
-      const double y = x[node_at<n1>(d, q, r)];
-      t += V[r] * y;
-      if (r == (fs ? N : 0)) s[v] = y;
-      if (r == (fs ? N - 1 : 1)) si[v] = y;
+    for (int k = 0; k < n1; ++k) {
+      const double y = x[node_at<n1>(d, q, fs ? N - k : k)];
+      t += w[k] * y;
+      if (k == 0) s[v] = y;
+      if (k == 1) si[v] = y;
     }
     a[v] = t;
   }
@@ -1567,8 +1586,8 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
   double Fm[M], Fp[M], Cm[M], Cp[M];
   {
     double a[M], b[M], UL[M], UR[M];
-    line_trace<Ph, N, d>(kp, un_g, e, q, 1, a, sL, sLi);
-    line_trace<Ph, N, d>(kp, un_g, en, q, 0, b, sR, sRi);
+    line_trace<Ph, N, d, 1>(kp, un_g, e, q, 1, a, sL, sLi);
+    line_trace<Ph, N, d, 0>(kp, un_g, en, q, 0, b, sR, sRi);
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       UL[v] = kp.Utr[tr(1, v, fiL)];
@@ -1578,18 +1597,10 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
     }
     // wave speed from the face values of u^n; an inadmissible face value uses
     // its neighbouring solution point instead
-    // (the state is selected first: one wave speed evaluation per side)
-    double sa, sb;
-    {
-      const bool oka = admissible<Ph>(a, pp), okb = admissible<Ph>(b, pp);
-      double w[M];
-#pragma unroll
-      for (int v = 0; v < M; ++v) w[v] = oka ? a[v] : sL[v];
-      sa = Ph::template sigma<d>(w, pp);
-#pragma unroll
-      for (int v = 0; v < M; ++v) w[v] = okb ? b[v] : sR[v];
-      sb = Ph::template sigma<d>(w, pp);
-    }
+    // (branches that admissible data never take)
+    double sa = Ph::template sigma<d>(a, pp), sb = Ph::template sigma<d>(b, pp);
+    if (!admissible<Ph>(a, pp)) sa = Ph::template sigma<d>(sL, pp);
+    if (!admissible<Ph>(b, pp)) sb = Ph::template sigma<d>(sR, pp);
     const double lam = sa >= sb ? sa : sb;
     double Unum[M], t[M];
 #pragma unroll
@@ -1743,15 +1754,9 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
       C[v] = kp.Ftr[tr(v)];
     }
     // wave speed at the face value of u^n, or at the node if that is not
-    // admissible (the state is selected first: one wave speed evaluation)
-    double sg;
-    {
-      const bool ok = admissible<Ph>(a, pp);
-      double w[M];
-#pragma unroll
-      for (int v = 0; v < M; ++v) w[v] = ok ? a[v] : s[v];
-      sg = Ph::template sigma<d>(w, pp);
-    }
+    // admissible (a branch that admissible data never take)
+    double sg = Ph::template sigma<d>(a, pp);
+    if (!admissible<Ph>(a, pp)) sg = Ph::template sigma<d>(s, pp);
     double sa, sb;
     pair_values(sg, sa, sb);
     const double lam = sa >= sb ? sa : sb;
