@@ -79,6 +79,27 @@ __device__ __forceinline__ void elem_sync() {
   }
 }
 
+// Minimum and OR over the P lanes of one element, the result in every one of
+// them, by lane exchanges: for elements whose lanes are an aligned group of a
+// power of two lanes within one wave (thread t works for element t / P).  Both
+// are exact, so the order of the exchanges does not change the result.
+template <int P>
+__host__ __device__ constexpr bool elem_lane_exchange() {
+  return LWFR_WAVE_LOCAL_SYNC && P <= 64 && (P & (P - 1)) == 0;
+}
+template <int P>
+__device__ __forceinline__ double elem_min(double x) {
+#pragma unroll
+  for (int o = P / 2; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, P));
+  return x;
+}
+template <int P>
+__device__ __forceinline__ uint32_t elem_or(uint32_t x) {
+#pragma unroll
+  for (int o = P / 2; o > 0; o >>= 1) x |= (uint32_t)__shfl_xor((int)x, o, P);
+  return x;
+}
+
 #ifndef STAGES_WAVES_PER_EU
 #define STAGES_WAVES_PER_EU 1
 #endif
@@ -2295,45 +2316,57 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     // per element reduces, every point reads the result.
     static_assert(2 * Ph::K <= P && Ph::K <= M, "reduction slots");
     double Theta = 1.0;
-    double Pa[Ph::K > 0 ? Ph::K : 1];
-#pragma unroll
-    for (int k = 0; k < Ph::K; ++k) {
-      Pa[k] = Ph::constraint(k, uL, pp);
-      s_f[le][k][p] = Pa[k];
-    }
-    elem_sync<ipow(N + 1, Ph::DIM)>();
-    if (p == 0) {
+    double Pa[Ph::K > 0 ? Ph::K : 1], Pmin[Ph::K > 0 ? Ph::K : 1];
+    if constexpr (elem_lane_exchange<P>()) {
 #pragma unroll
       for (int k = 0; k < Ph::K; ++k) {
-        double m = s_f[le][k][0];
-#pragma unroll
-        for (int r = 1; r < P; ++r) m = fmin(m, s_f[le][k][r]);
-        s_red[le][k] = m;
+        Pa[k] = Ph::constraint(k, uL, pp);
+        Pmin[k] = elem_min<P>(Pa[k]);
       }
-    }
-    elem_sync<ipow(N + 1, Ph::DIM)>();
-    double Pmin[Ph::K > 0 ? Ph::K : 1];
+    } else {
 #pragma unroll
-    for (int k = 0; k < Ph::K; ++k) {
-      Pmin[k] = s_red[le][k];
-      if (Pmin[k] <= 0.0) fl |= 2u;
+      for (int k = 0; k < Ph::K; ++k) {
+        Pa[k] = Ph::constraint(k, uL, pp);
+        s_f[le][k][p] = Pa[k];
+      }
+      elem_sync<ipow(N + 1, Ph::DIM)>();
+      if (p == 0) {
+#pragma unroll
+        for (int k = 0; k < Ph::K; ++k) {
+          double m = s_f[le][k][0];
+#pragma unroll
+          for (int r = 1; r < P; ++r) m = fmin(m, s_f[le][k][r]);
+          s_red[le][k] = m;
+        }
+      }
+      elem_sync<ipow(N + 1, Ph::DIM)>();
+#pragma unroll
+      for (int k = 0; k < Ph::K; ++k) Pmin[k] = s_red[le][k];
     }
+#pragma unroll
+    for (int k = 0; k < Ph::K; ++k)
+      if (Pmin[k] <= 0.0) fl |= 2u;
     if (kp.blending == 2) {
 #pragma unroll
       for (int k = 0; k < Ph::K; ++k) {
         bool guard = false;
         const double th_p = theta_limit(0.1 * Pmin[k], Pa[k], Ph::constraint(k, us, pp), guard);
-        elem_sync<ipow(N + 1, Ph::DIM)>();  // every point has read the previous minimum
-        s_left[le][0][p] = th_p;
-        elem_sync<ipow(N + 1, Ph::DIM)>();
-        if (p == 0) {
-          double m = s_left[le][0][0];
+        double th;
+        if constexpr (elem_lane_exchange<P>()) {
+          th = elem_min<P>(th_p);
+        } else {
+          elem_sync<ipow(N + 1, Ph::DIM)>();  // every point has read the previous minimum
+          s_left[le][0][p] = th_p;
+          elem_sync<ipow(N + 1, Ph::DIM)>();
+          if (p == 0) {
+            double m = s_left[le][0][0];
 #pragma unroll
-          for (int r = 1; r < P; ++r) m = fmin(m, s_left[le][0][r]);
-          s_red[le][Ph::K + k] = m;
+            for (int r = 1; r < P; ++r) m = fmin(m, s_left[le][0][r]);
+            s_red[le][Ph::K + k] = m;
+          }
+          elem_sync<ipow(N + 1, Ph::DIM)>();
+          th = s_red[le][Ph::K + k];
         }
-        elem_sync<ipow(N + 1, Ph::DIM)>();
-        const double th = s_red[le][Ph::K + k];
         if (th < 1.0) {
 #pragma unroll
           for (int v = 0; v < M; ++v) us[v] = th * us[v] + (1.0 - th) * uL[v];
@@ -2364,12 +2397,18 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     }
     fl |= (thw[k] < 1.0 ? 4u : 0u) | (guw[k] ? 16u : 0u);
   }
-  s_fl[le][p] = fl;
-  elem_sync<ipow(N + 1, Ph::DIM)>();
-  if (act && p == 0) {
-    uint32_t f = 0;
+  uint32_t f = 0;
+  if constexpr (elem_lane_exchange<P>()) {
+    f = elem_or<P>(fl);
+  } else {
+    s_fl[le][p] = fl;
+    elem_sync<ipow(N + 1, Ph::DIM)>();
+    if (p == 0) {
 #pragma unroll
-    for (int r = 0; r < P; ++r) f |= s_fl[le][r];
+      for (int r = 0; r < P; ++r) f |= s_fl[le][r];
+    }
+  }
+  if (act && p == 0) {
     if (d_flags) d_flags[e] = f;
     // every flag reaches the context's word; the atomic is skipped once its
     // bits are set (a stale read only costs an extra atomic)
@@ -2380,8 +2419,13 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   }
 }
 
+#ifndef UPDATE_WAVES_PER_EU
+#define UPDATE_WAVES_PER_EU 3
+#endif
+// at least three waves per SIMD: GLM-MHD at N = 2 otherwise takes 170 VGPRs
+// and runs at two
 template <class Ph, int N, int EPB>
-__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM))
+__global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES_PER_EU)))
     k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
   constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
   __shared__ UpdateLds<Ph, N, NT> L;
