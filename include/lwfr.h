@@ -262,7 +262,7 @@ lwfr_status lwfr_residual(lwfr_ctx* ctx, const double* d_u, double dt, int32_t m
 
 /* Bytes of one step's tape: the values a forward step hands to the adjoint
  * (dt and c_h, alpha_e, the thetas of Algorithms 1 and 2, the face traces of
- * u^n and of the time-averaged solution U).  256-byte alignment required. */
+ * the time-averaged solution U).  256-byte alignment required. */
 lwfr_status lwfr_tape_bytes(const lwfr_ctx* ctx, size_t* bytes);
 
 /* A forward step like lwfr_step (dt > 0 given, <= 0 from eq. time.step.2d)

@@ -208,14 +208,18 @@ __device__ inline void adj_face_point(const KParams& kp, const AdjParams& ap, co
   const size_t fiL = (size_t)e * NFP + q, fiR = (size_t)en * NFP + q;
   double a[M], b[M], UL[M], UR[M], sL[M], sR[M];
   double gFm[M], gFp[M], gDm[M], gDp[M];
+  {
+    // u^n at the face from each side's line of nodes, as the forward face
+    // kernel forms it (the next nodes inward are not needed here)
+    double inner[M];
+    line_trace<Ph, N, d, 1>(kp, un_g, e, q, 1, a, sL, inner);
+    line_trace<Ph, N, d, 0>(kp, un_g, en, q, 0, b, sR, inner);
+  }
 #pragma unroll
   for (int v = 0; v < M; ++v) {
     const size_t oL = ((size_t)(d * 2 + 1) * M + v) * nf + fiL;
     const size_t oR = ((size_t)(d * 2 + 0) * M + v) * nf + fiR;
-    a[v] = kp.untr[oL]; b[v] = kp.untr[oR];
     UL[v] = kp.Utr[oL]; UR[v] = kp.Utr[oR];
-    sL[v] = un_g[((size_t)v * kp.E + e) * P + node_at<n1>(d, q, N)];
-    sR[v] = un_g[((size_t)v * kp.E + en) * P + node_at<n1>(d, q, 0)];
     const size_t o = ((size_t)d * M + v) * nf + fiL;
     gFm[v] = ap.gFm[o]; gFp[v] = ap.gFp[o];
     gDm[v] = ap.gDm[o]; gDp[v] = ap.gDp[o];

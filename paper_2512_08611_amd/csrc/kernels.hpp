@@ -132,7 +132,6 @@ struct KParams {
   double* alpha;              // [E] smoothed alpha used by the step
   double* Ftr;                // [d][side][M][E*nfp] trace of F_d
   double* Utr;                // [d][side][M][E*nfp] trace of U
-  double* untr;               // [d][side][M][E*nfp] trace of u^n (adjoint records only; null: not written)
   double* Fm;                 // [d][M][E*nfp] F^- of face (e, e+1)
   double* Fp;                 // [d][M][E*nfp] F^+
   double* Dm;                 // [d][M][E*nfp] F^- - F_tr^- - B(u^{n,-}) U^- (systems that do not fold it)
@@ -438,7 +437,7 @@ __global__ void __launch_bounds__(1024) k_ch_fin(const KParams kp, double* d_dt_
 // (same order of summation), so only the partial sums still needed stay live.
 // Output: the volume part of the high order residual, B^loc + sum_d D_d F_d/dx_d,
 // which by linearity of D_d equals sum_s b_s L^(s) (written to the output state
-// buffer), and the face traces of F_d, U and u^n.
+// buffer), and the face traces of F_d and U.
 template <class Tab>
 __host__ __device__ constexpr int first_nz_t(int t) {
   for (int k = 0; k < t; ++k)
@@ -464,8 +463,8 @@ struct StagesLds {
 };
 
 // Outputs of the element-local phase, shared by the stage body and the
-// approximate Lax-Wendroff body: the face traces of the time averages F_d, U
-// and of u^n, the volume residual and the smoothed blending coefficient.  With
+// approximate Lax-Wendroff body: the face traces of the time averages F_d and
+// U, the volume residual and the smoothed blending coefficient.  With
 // the correction folded (fold_correction) the volume residual written is
 // R = Ra - sum_d (C_{d,R} g_R'(xi) + C_{d,L} g_L'(xi)) / dx_d along the lines
 // through the point, with C = F_tr + B_d(u^n_tr) U_tr at the element's own
@@ -530,7 +529,6 @@ __device__ __forceinline__ void stage_outputs_fold(const KParams& kp, double (&s
 #pragma unroll
       for (int r = 0; r < n1; ++r) t += V[r] * un_g[((size_t)v * kp.E + e) * P + (d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r))];
       a[v] = t;
-      if (kp.untr) kp.untr[((size_t)(d * 2 + side) * M + v) * nf + fo] = t;
     }
 #pragma unroll
     for (int v = 0; v < M; ++v) {
@@ -639,15 +637,6 @@ __device__ __forceinline__ void stage_outputs_plain(const KParams& kp, double (&
         const size_t o = ((size_t)(d * 2 + side) * M + v) * nf + fo;
         kp.Ftr[o] = tf;
         kp.Utr[o] = tu;
-        // the u^n trace only for the adjoint's records: the face kernels form it
-        // from the line of nodes they read anyway
-        if (kp.untr) {
-          double tn = 0.0;
-#pragma unroll
-          for (int r = 0; r < n1; ++r)
-            tn += V[r] * un_g[((size_t)v * kp.E + e) * P + (d == 0 ? node_at<n1>(0, q, r) : node_at<n1>(1, q, r))];
-          kp.untr[o] = tn;
-        }
       }
     }
     // blending coefficient of the element (smoothed over face neighbours)
@@ -1038,7 +1027,7 @@ struct Stages2Lds {
 };
 
 // outputs of the two-lane stage kernels: the face traces of F (lane's
-// direction), U and u^n, the volume residual (lane's half of the variables,
+// direction) and U, the volume residual (lane's half of the variables,
 // with the element-local correction terms as in stage_outputs) and the
 // element's blending coefficient.  Fa holds the lane's direction for all
 // variables; Ua, Ra and uo the lane's half.
@@ -1092,7 +1081,6 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       a[v] = trace(3 * M, v);
-      if (kp.untr) kp.untr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = a[v];
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll

@@ -44,7 +44,7 @@ struct lwfr_ctx {
   double cfl = 0.0;
   KParams kp;
   // workspace carving (byte offsets)
-  size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr, off_untr,
+  size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr,
       off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, off_eflags, off_srows,
       ws_bytes;
   int nblk_stats = 0;
@@ -58,7 +58,7 @@ struct lwfr_ctx {
       off_gsR;
   AdjParams ap;
   // per-step tape: what the reverse kernels read from a forward step
-  size_t tp_scal, tp_alpha, tp_thf, tp_thel, tp_untr, tp_Utr, tape_bytes;
+  size_t tp_scal, tp_alpha, tp_thf, tp_thel, tp_Utr, tape_bytes;
   void* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
@@ -322,7 +322,6 @@ KParams with_tape(const lwfr_ctx* c, KParams kp, void* tape) {
   kp.alpha = reinterpret_cast<double*>(t + c->tp_alpha);
   kp.theta_face = reinterpret_cast<double*>(t + c->tp_thf);
   kp.theta_elem = reinterpret_cast<double*>(t + c->tp_thel);
-  kp.untr = reinterpret_cast<double*>(t + c->tp_untr);
   kp.Utr = reinterpret_cast<double*>(t + c->tp_Utr);
   return kp;
 }
@@ -412,7 +411,6 @@ void carve_kp(const lwfr_ctx* c, char* b, KParams& kp) {
   kp.theta_elem = reinterpret_cast<double*>(b + c->off_thel);
   kp.Ftr = reinterpret_cast<double*>(b + c->off_Ftr);
   kp.Utr = reinterpret_cast<double*>(b + c->off_Utr);
-  kp.untr = c->off_untr ? reinterpret_cast<double*>(b + c->off_untr) : nullptr;
   kp.Fm = reinterpret_cast<double*>(b + c->off_Fm);
   kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
   kp.Dm = c->off_Dm ? reinterpret_cast<double*>(b + c->off_Dm) : nullptr;
@@ -770,10 +768,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_thel = take((size_t)c->E * sizeof(double));
   c->off_Ftr = take(nfpt * 2 * c->M * sizeof(double));
   c->off_Utr = take(nfpt * 2 * c->M * sizeof(double));
-  // the u^n traces are kept only for the adjoint (the face kernels of a step
-  // form them from the solution points they read)
   c->adjoint = (cfg->flags & LWFR_CFG_ADJOINT) != 0;
-  c->off_untr = c->adjoint ? take(nfpt * 2 * c->M * sizeof(double)) : 0;
   c->off_Fm = take(nfpt * c->M * sizeof(double));
   c->off_Fp = take(nfpt * c->M * sizeof(double));
   // the correction jumps D^± of the systems that do not fold the correction
@@ -816,7 +811,6 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     c->tp_alpha = tk((size_t)c->E * sizeof(double));
     c->tp_thf = tk(nfpt * sizeof(double));
     c->tp_thel = tk((size_t)c->E * sizeof(double));
-    c->tp_untr = tk(nfpt * 2 * c->M * sizeof(double));
     c->tp_Utr = tk(nfpt * 2 * c->M * sizeof(double));
     c->tape_bytes = t;
   }
