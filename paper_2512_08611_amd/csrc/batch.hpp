@@ -122,16 +122,21 @@ __global__ void __launch_bounds__(NT) kb_stages(const BatchArgs ba, const double
   }
 }
 
-// face phase: tiles of 256 face points
+// face phase: tiles of 128 face points in each direction
 template <class Ph>
 __global__ void __launch_bounds__(256) kb_faces(const BatchArgs ba, const double* __restrict__ u_in) {
   int t0, t1, step;
   tile_range(ba.ntiles, ba.xcd, t0, t1, step);
   for (int t = t0; t < t1; t += step) {
     const int inst = ba.tinst[t];
-    const int gid = ba.tblk[t] * 256 + threadIdx.x;
     const KParams& kp = ba.kps[inst];
     const double* un = u_in + ba.uoff[inst];
+    // the tile's face points in both directions (face_slot); a slot past the
+    // problem's face points gets an index past them too, which the body skips
+    int d, fi;
+    face_slot<Ph::DIM>(ba.tblk[t], threadIdx.x, 256, d, fi);
+    const int nf = kp.E * (Ph::DIM == 1 ? 1 : kp.N + 1);
+    const int gid = fi < nf ? d * nf + fi : Ph::DIM * nf;
     switch (kp.N) {
       case 1: faces_body<Ph, 1>(kp, un, gid); break;
       case 2: faces_body<Ph, 2>(kp, un, gid); break;
