@@ -25,6 +25,9 @@ def test_stage_loop_flop_counts(key):
     counts = oracle.count_ops(c, u, dt, ch).astype(float)
     per_dof = counts[0].sum() / (u.shape[1] * u.shape[2])
     assert per_dof == bench.STAGE_LOOP_FLOPS_PER_DOF[key]
+    # the stage kernel's figure: the stage loop and the face traces
+    kernel = counts[:2].sum() / (u.shape[1] * u.shape[2])
+    assert abs(kernel - bench.STAGE_KERNEL_FLOPS_PER_DOF[key]) < 0.05, kernel
 
 
 @pytest.mark.parametrize("key", sorted(bench.STEP_FLOPS_PER_DOF))

@@ -11,10 +11,12 @@ Checks, all through the C ABI:
   * a captured graph of 10 steps, replayed three times with other work and
     synchronisations between the replays, equals 10 eager steps each time;
   * the 64-problem workload (sizes 32^2..256^2, degrees 2..4, seed 0): one
-    autotuned batched step equals the single-problem steps bit for bit, the three
-    smallest problems match the oracle, and 50 graph-captured steps equal 50
-    eager batched steps.
+    autotuned batched step equals the single-problem steps bit for bit, every
+    problem matches the oracle (dt to 1e-13, values to the parity bar), and 50
+    graph-captured steps equal 50 eager batched steps.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -261,16 +263,20 @@ def test_full_size_batch_64_problems(stream):
         ref, dti = single_step(cfg, states[i], stream)
         assert float(dt[i]) == dti, i
         assert torch.equal(b.view(out, i).cpu(), ref), (i, specs[i])
-    order = sorted(range(len(specs)), key=lambda i: specs[i][0] ** 2 * (specs[i][1] + 1) ** 2)[:3]
-    for i in order:
+    # every problem against the oracle (its element and face loops on the host's cores)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    worst = 0.0
+    for i in range(len(specs)):
         n, N = specs[i]
-        oc = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, cs=0.9, cfl=oracle.cfl_number(N), blending=2)
+        oc = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, cs=0.9, cfl=oracle.cfl_number(N), blending=2, threads=threads)
         o = oracle.step(oc, states[i])
+        assert float(dt[i]) == pytest.approx(o["dt"], rel=1e-13), i
         g = b.view(out, i).cpu().numpy()
         scale = np.maximum(np.abs(o["u"]), 1e-2 * np.abs(states[i]).max())
         err = (np.abs(g - o["u"]) / scale).max()
-        print(f"BATCH PARITY problem {i} n={n} N={N} rel={err:.3e}", flush=True)
-        assert err <= TOL
+        worst = max(worst, err)
+        assert err <= TOL, (i, n, N, err)
+    print(f"BATCH PARITY all 64 problems against the oracle: worst rel={worst:.3e}", flush=True)
     # 50 graph-captured steps against 50 eager batched steps
     nsteps = 50
     ua, ub = u.clone(), b.empty()
