@@ -233,3 +233,38 @@ def sw2d_batch_specs(count=64, seed=0):
     n = rng.integers(32, 257, size=count)
     N = rng.integers(2, 5, size=count)
     return [(int(a), int(b)) for a, b in zip(n, N)]
+
+
+def steep_near_vacuum(xi, eq_dim, nvar, nx, seed=0, kmin=6.0, kmax=10.0, mhd=False, gamma=GAMMA_MHD):
+    """Per element a steep exponential depth (shallow water) or density (GLM-MHD,
+    then with uniform pressure 1) in x or in y, decaying over the element to near
+    zero, toward a seeded side: every node is admissible, but the value a degree
+    N >= 1 polynomial through the nodes extrapolates to the element's faces is
+    negative on the low side at some degrees.  Small seeded velocities and
+    fields, constant per element; zero bed."""
+    rng = np.random.default_rng(seed)
+    n1 = len(xi)
+    E = nx if eq_dim == 1 else nx * nx
+    P = n1 if eq_dim == 1 else n1 * n1
+    u = np.zeros((nvar, E, P))
+    for e in range(E):
+        k = rng.uniform(kmin, kmax)
+        x = xi if rng.uniform() < 0.5 else 1.0 - np.asarray(xi)
+        prof = np.exp(-k * np.asarray(x))
+        if eq_dim == 1:
+            q = prof
+        else:
+            q = np.tile(prof, n1) if rng.uniform() < 0.5 else np.repeat(prof, n1)
+        if not mhd:
+            h = 0.5 * q + 1e-4
+            u[0, e] = h
+            u[1, e] = 0.05 * h * rng.uniform(-1, 1)
+            if eq_dim == 2:
+                u[2, e] = 0.05 * h * rng.uniform(-1, 1)
+        else:
+            rho = q + 1e-3
+            v = 0.1 * rng.uniform(-1, 1, 3)
+            B = 0.1 * rng.uniform(-1, 1, 3)
+            c = [np.full_like(rho, x) for x in (v[0], v[1], v[2], 1.0, B[0], B[1], B[2], 0.0)]
+            u[:, e] = _mhd_cons(rho, *c, gamma=gamma)
+    return u
