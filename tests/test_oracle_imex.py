@@ -208,3 +208,56 @@ def test_stiff_limit_keeps_the_order_of_u():
         ev.append(math.sqrt(((u[1] - ve) ** 2 * re["w"]).sum() / nx))
     assert math.log(eu[0] / eu[1], 2) > 3.0, eu
     assert 0.7 < math.log(ev[0] / ev[1], 2) < 1.5, ev
+
+
+def _golden_tableaux():
+    """Entries of tests/golden/imex_tableaux.txt (the printed tableaux of eqs.
+    ht112.butcher and ssp33.butcher), each expression evaluated from its
+    numbers, fractions, named constants, + and -."""
+    import ast
+    import operator
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "imex_tableaux.txt")
+    consts, entries = {}, []
+    ops = {ast.Add: operator.add, ast.Sub: operator.sub, ast.Div: operator.truediv, ast.USub: operator.neg}
+
+    def ev(node):
+        if isinstance(node, ast.Expression):
+            return ev(node.body)
+        if isinstance(node, ast.Constant):
+            return float(node.value)
+        if isinstance(node, ast.Name):
+            return consts[node.id]
+        if isinstance(node, ast.BinOp) and type(node.op) in ops:
+            return ops[type(node.op)](ev(node.left), ev(node.right))
+        if isinstance(node, ast.UnaryOp) and type(node.op) in ops:
+            return ops[type(node.op)](ev(node.operand))
+        raise ValueError(ast.dump(node))
+
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        f = line.split()
+        if f[0] == "const":
+            consts[f[1]] = float(f[2])
+        else:
+            entries.append((f[0], f[1], None if f[2] == "-" else int(f[2]), int(f[3]),
+                            ev(ast.parse(f[4], mode="eval"))))
+    return entries
+
+
+def test_tableaux_match_the_printed_values():
+    """The oracle's IMEX tableaux carry the printed entries of eqs. ht112.butcher
+    and ssp33.butcher (the golden fixture), to the printed digits."""
+    ent = _golden_tableaux()
+    assert len(ent) == 46
+    for name, imex in (("HT112", HT), ("SSP3", SSP3)):
+        At, bt, A, b = oracle.tableau_imex(imex)
+        parts = {"A_explicit": At, "b_explicit": bt, "A_implicit": A, "b_implicit": b}
+        for nm, part, r, c, val in ent:
+            if nm != name:
+                continue
+            got = parts[part][c] if r is None else parts[part][r, c]
+            assert abs(got - val) <= 1e-15, (name, part, r, c, got, val)
