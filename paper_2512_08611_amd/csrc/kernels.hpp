@@ -217,9 +217,12 @@ struct PreLds {
   double s_lam[EL];
 };
 
+// The element data from the state x at the thread's node (x: every variable at
+// node p of element e, the thread's): pre_body without its loads, also run by
+// the update kernel on the state it has just written (chained steps).
 template <class Ph, int N, int EPB, int NT>
-__device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L, const double* __restrict__ un,
-                                         int blk, double* part_out) {
+__device__ __forceinline__ void pre_from_state(const KParams& kp, PreLds<Ph, N, NT>& L, const double (&x)[Ph::M],
+                                               int blk, double* part_out) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
   auto& s_u = L.s_u;
   auto& s_q = L.s_q;
@@ -232,12 +235,6 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
   const bool act = le < EPB && e < kp.E;
   const PhysParams pp = phys_params(kp, 0.0);
   const bool want_alpha = kp.blending >= 1 && kp.alpha_force < 0.0;
-  // lanes without an element read element 0 (unconditional loads pipeline;
-  // a load under a lane condition waits for its data before the next one)
-  const int es = act ? e : 0;
-  double x[M];
-#pragma unroll
-  for (int v = 0; v < M; ++v) x[v] = un[((size_t)v * kp.E + es) * P + p];
 #pragma unroll
   for (int v = 0; v < M; ++v) s_u[le][v][p] = x[v];
   if (want_alpha) s_q[le][p] = Ph::indicator(x, pp);
@@ -327,6 +324,23 @@ __device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L
     for (int l = 1; l < EPB; ++l) m = fmax(m, s_lam[l]);
     part_out[0] = m;
   }
+}
+
+template <class Ph, int N, int EPB, int NT>
+__device__ __forceinline__ void pre_body(const KParams& kp, PreLds<Ph, N, NT>& L, const double* __restrict__ un,
+                                         int blk, double* part_out) {
+  constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM);
+  const int tid = threadIdx.x;
+  const int le = tid / P, p = tid - le * P;
+  const int e = blk * EPB + le;
+  const bool act = le < EPB && e < kp.E;
+  // lanes without an element read element 0 (unconditional loads pipeline;
+  // a load under a lane condition waits for its data before the next one)
+  const int es = act ? e : 0;
+  double x[M];
+#pragma unroll
+  for (int v = 0; v < M; ++v) x[v] = un[((size_t)v * kp.E + es) * P + p];
+  pre_from_state<Ph, N, EPB, NT>(kp, L, x, blk, part_out);
 }
 
 template <class Ph, int N, int EPB>
@@ -2155,10 +2169,11 @@ struct UpdateLds {
   uint32_t s_fl[EL][P];
 };
 
-template <class Ph, int N, int EPB, int NT, bool OT = false>
+// KEEP: the final state of the thread's node also goes to us_keep (M values)
+template <class Ph, int N, int EPB, int NT, bool OT = false, bool KEEP = false>
 __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, NT>& L,
                                             const double* __restrict__ un_g, double* __restrict__ io,
-                                            uint32_t* d_flags, int blk) {
+                                            uint32_t* d_flags, int blk, double* us_keep = nullptr) {
   constexpr int n1 = N + 1, DIM = Ph::DIM, M = Ph::M, P = ipow(n1, DIM), NFP = DIM == 1 ? 1 : n1;
   auto& s_u = L.s_u;
   auto& s_f = L.s_f;
@@ -2373,6 +2388,10 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
     for (int v = 0; v < M; ++v) io[((size_t)v * kp.E + e) * P + p] = us[v];
   }
+  if constexpr (KEEP) {
+#pragma unroll
+    for (int v = 0; v < M; ++v) us_keep[v] = us[v];
+  }
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
     const int w = p + k * P;
@@ -2412,12 +2431,30 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #endif
 // at least three waves per SIMD: GLM-MHD at N = 2 otherwise takes 170 VGPRs
 // and runs at two
-template <class Ph, int N, int EPB>
+// NEXT: a step of a chain whose next step starts from this one's result (the
+// steps of a captured graph): the kernel also forms the next step's element
+// data (means, speeds, Lambda_e, raw indicator and the block maxima, exactly
+// what k_pre would compute from the state it has written), so that the next
+// step needs no k_pre.  Its workgroups are k_pre's.
+template <class Ph, int N, int EPB, bool NEXT = false>
 __global__ void __launch_bounds__(EPB* ipow(N + 1, Ph::DIM)) __attribute__((amdgpu_waves_per_eu(UPDATE_WAVES_PER_EU)))
     k_update(const KParams kp, const double* __restrict__ un_g, double* __restrict__ io, uint32_t* d_flags) {
   constexpr int NT = EPB * ipow(N + 1, Ph::DIM);
-  __shared__ UpdateLds<Ph, N, NT> L;
-  update_body<Ph, N, EPB, NT>(kp, L, un_g, io, d_flags, xcd_block(blockIdx.x, gridDim.x));
+  if constexpr (!NEXT) {
+    __shared__ UpdateLds<Ph, N, NT> L;
+    update_body<Ph, N, EPB, NT>(kp, L, un_g, io, d_flags, xcd_block(blockIdx.x, gridDim.x));
+  } else {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    union Lds {
+      UpdateLds<Ph, N, NT> update;
+      PreLds<Ph, N, NT> pre;
+    };
+    __shared__ Lds L;
+    double us[Ph::M];
+    update_body<Ph, N, EPB, NT, false, true>(kp, L.update, un_g, io, d_flags, b, us);
+    __syncthreads();  // the update's LDS is free
+    pre_from_state<Ph, N, EPB, NT>(kp, L.pre, us, b, kp.part + b);
+  }
 }
 
 // ------------------------------------------------------------------------

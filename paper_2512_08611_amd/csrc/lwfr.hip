@@ -166,15 +166,22 @@ struct TimedLaunch {
 #define LWFR_ALW2 1
 #endif
 
+// chain (steps of a captured graph, each starting from the previous one's
+// result): kChainFromPrev, the previous step's update formed this step's element
+// data, so k_pre is skipped; kChainToNext, this step's update forms the next
+// step's.
+constexpr int kChainFromPrev = 1, kChainToNext = 2;
+
 template <class Ph, int N, class Tab = Tableau<N>>
 lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
-                        double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats) {
+                        double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats, int chain = 0) {
   constexpr int DIM = Ph::DIM, P = ipow(N + 1, DIM), NFP = DIM == 1 ? 1 : N + 1;
   constexpr int EPB = epb_for<N>(DIM, Ph::M);
   const int E = c->E;
   hipStream_t s = c->stream;
   const bool has_ch = std::is_same<Ph, MHD2D>::value && kp.ch_in < 0.0;
-  LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N, EPB>), dim3(c->nblk_pre), dim3(EPB * P), 0, s, kp, u_in);
+  if (!(chain & kChainFromPrev))
+    LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N, EPB>), dim3(c->nblk_pre), dim3(EPB * P), 0, s, kp, u_in);
   LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(1024), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
   if (has_ch) {
     LWFR_LAUNCH(KID_CH, "k_ch", k_ch, dim3(c->nblk_ch), dim3(256), 0, s, kp);
@@ -205,8 +212,12 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
                 u_in);
   // statistics need the element flags: the context's own array when the caller takes none
   uint32_t* eflags = d_stats && !d_flags ? kp.eflags : d_flags;
-  LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
-              eflags);
+  if (chain & kChainToNext)
+    LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB, true>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in,
+                u_out, eflags);
+  else
+    LWFR_LAUNCH(KID_UPDATE, "k_update", (k_update<Ph, N, EPB>), dim3(nblk_el), dim3(EPB * P), 0, s, kp, u_in, u_out,
+                eflags);
   if (d_stats) {
     double* rows = kp.stats_rows;
     hipLaunchKernelGGL((k_stats<Ph, N>), dim3(c->nblk_stats), dim3(256), 0, s, kp, (const double*)u_out,
@@ -277,40 +288,40 @@ lwfr_status dispatch_adjoint(lwfr_ctx* c, const KParams& kp, const double* u_n, 
 
 template <class Ph>
 lwfr_status launch_step_n(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
-                          double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats) {
+                          double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats, int chain) {
   if constexpr (Ph::SRC) {
     const bool ht = (c->cfg.flags & LWFR_CFG_IMEX_HT112) != 0;
     switch (c->N) {
-      case 1: return ht ? launch_step<Ph, 1, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
-                        : launch_step<Ph, 1, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-      case 2: return ht ? launch_step<Ph, 2, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
-                        : launch_step<Ph, 2, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-      case 3: return ht ? launch_step<Ph, 3, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
-                        : launch_step<Ph, 3, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-      case 4: return ht ? launch_step<Ph, 4, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats)
-                        : launch_step<Ph, 4, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 1: return ht ? launch_step<Ph, 1, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain)
+                        : launch_step<Ph, 1, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+      case 2: return ht ? launch_step<Ph, 2, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain)
+                        : launch_step<Ph, 2, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+      case 3: return ht ? launch_step<Ph, 3, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain)
+                        : launch_step<Ph, 3, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+      case 4: return ht ? launch_step<Ph, 4, ImexHT>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain)
+                        : launch_step<Ph, 4, ImexSSP3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
     }
     return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
   } else {
     switch (c->N) {
-      case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-      case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-      case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-      case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+      case 1: return launch_step<Ph, 1>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+      case 2: return launch_step<Ph, 2>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+      case 3: return launch_step<Ph, 3>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+      case 4: return launch_step<Ph, 4>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
     }
     return fail(LWFR_E_UNSUPPORTED, "degree must be 1..4");
   }
 }
 
 lwfr_status dispatch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, double* u_out, double* d_dt_ch,
-                          double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats = nullptr) {
+                          double* d_alpha, uint32_t* d_flags, lwfr_stats* d_stats = nullptr, int chain = 0) {
   switch (c->cfg.equation) {
-    case LWFR_EQ_SW1D: return launch_step_n<SW1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-    case LWFR_EQ_SW2D: return launch_step_n<SW2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-    case LWFR_EQ_GLMMHD2D: return launch_step_n<MHD2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-    case LWFR_EQ_LINADV1D: return launch_step_n<LinAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-    case LWFR_EQ_VARADV1D: return launch_step_n<VarAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
-    case LWFR_EQ_JINXIN1D: return launch_step_n<JinXin1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats);
+    case LWFR_EQ_SW1D: return launch_step_n<SW1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+    case LWFR_EQ_SW2D: return launch_step_n<SW2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+    case LWFR_EQ_GLMMHD2D: return launch_step_n<MHD2D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+    case LWFR_EQ_LINADV1D: return launch_step_n<LinAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+    case LWFR_EQ_VARADV1D: return launch_step_n<VarAdv1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
+    case LWFR_EQ_JINXIN1D: return launch_step_n<JinXin1D>(c, kp, u_in, u_out, d_dt_ch, d_alpha, d_flags, d_stats, chain);
   }
   return fail(LWFR_E_UNSUPPORTED, "unknown equation");
 }
@@ -1060,10 +1071,14 @@ lwfr_status lwfr_graph_capture(lwfr_ctx* c, double* d_u_a, double* d_u_b, int32_
   KParams kp = c->kp;
   kp.dt_in = 0.0;
   kp.ch_in = -1.0;
+  // each step after the first starts from the previous one's result: the
+  // previous update forms its element data (the same values k_pre would)
   return capture(c->stream, c->tm, c->graph, nsteps, [&](int k) {
     const double* in = (k & 1) ? d_u_b : d_u_a;
     double* out = (k & 1) ? d_u_a : d_u_b;
-    return dispatch_step(c, kp, in, out, d_dt_ch_hist ? d_dt_ch_hist + 2 * (size_t)k : nullptr, nullptr, nullptr);
+    const int chain = (k > 0 ? kChainFromPrev : 0) | (k + 1 < nsteps ? kChainToNext : 0);
+    return dispatch_step(c, kp, in, out, d_dt_ch_hist ? d_dt_ch_hist + 2 * (size_t)k : nullptr, nullptr, nullptr,
+                         nullptr, chain);
   });
 }
 
