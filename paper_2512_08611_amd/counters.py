@@ -198,11 +198,11 @@ def trace_summary(trace_csv, steps, match="lwfr::"):
     kernel time: {kernel: [durations ns]}, span_ns, busy_ns."""
     rows = [r for r in csv.DictReader(open(trace_csv)) if match in r["Kernel_Name"]]
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    # launches per step: the kernels between two consecutive launches of k_pre (a step's first kernel)
+    # a step ends with its update kernel (chained steps have no k_pre): the last
+    # `steps` steps are the launches after the update of the step before them
     names = [_short(r["Kernel_Name"]) for r in rows]
-    starts = [i for i, n in enumerate(names) if n.startswith("k_pre<")]
-    per_step = starts[-1] - starts[-2] if len(starts) >= 2 else len(rows)
-    last = rows[-per_step * steps:]
+    ups = [i for i, n in enumerate(names) if n.startswith("k_update<")]
+    last = rows[ups[-steps - 1] + 1:] if len(ups) > steps else rows
     out = {}
     for r in last:
         out.setdefault(_short(r["Kernel_Name"]), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
