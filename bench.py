@@ -371,6 +371,42 @@ def workload_text(n, N, data):
             f"N={N} Gauss-Legendre ({dofs} DOF, 9 variables), blending + Algorithms 1-2, C_s=0.9")
 
 
+def kernel_rooflines(table, per_kernel, K):
+    """Every kernel of a step against both rooflines, and the HBM bytes of one
+    graph-replayed step: counter figures (table: counters.read_table of the
+    committed summary) with the live eager durations (per_kernel)."""
+    by_kernel = None
+    step_bytes = None
+    if table:
+        by_kernel, step_bytes = {}, 0.0
+        for name, row in table.items():
+            base = name.split("<")[0]
+            key = next((k for k in per_kernel if base == k or base.startswith(k + "2")), None)
+            if key is None or not per_kernel[key]["ms_per_launch"]:
+                continue
+            # a captured K-step sequence runs k_pre once, the update that also
+            # forms the next step's element data K-1 times and the plain update
+            # once; every other kernel once a step
+            chained = name.endswith(", true>")
+            per_graph_step = {"k_pre": 1.0 / K}.get(key, 1.0)
+            if key == "k_update":
+                per_graph_step = (K - 1) / K if chained else 1.0 / K
+            if "bytes" in row:
+                step_bytes += row["bytes"] * per_graph_step
+            if chained:
+                continue  # the live durations are those of the eager steps' plain update
+            sec = per_kernel[key]["ms_per_launch"] * 1e-3
+            ent = {"counted_kernel": name, "ms_per_launch": per_kernel[key]["ms_per_launch"]}
+            if "bytes" in row:
+                gbs = row["bytes"] / sec / 1e9
+                ent.update(hbm_bytes=row["bytes"], hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+            if "fp64_ops" in row:
+                tf = row["fp64_ops"] / sec / 1e12
+                ent.update(fp64_hw_ops=row["fp64_ops"], fp64_TFLOPs=tf, fp64_frac=tf / FP64_VECTOR_PEAK_TFLOPS)
+            by_kernel[key] = ent
+    return by_kernel, step_bytes
+
+
 def measure(torch, np, lwfr, workloads, counters, n, N, data, K, Wm, graph_trace=False):
     """One workload: Wm warm-up steps, K steps launched one by one with HIP events
     around every kernel (per-kernel durations, ms_per_step_eager), then the timed
@@ -445,26 +481,7 @@ def measure(torch, np, lwfr, workloads, counters, n, N, data, K, Wm, graph_trace
     }
     # every kernel of the step against both rooflines (counter figures from the
     # committed summary while it matches the sources, durations measured live)
-    table = counters.read_table(summary)
-    by_kernel = None
-    step_bytes = None
-    if table:
-        by_kernel, step_bytes = {}, 0.0
-        for name, row in table.items():
-            base = name.split("<")[0]
-            key = next((k for k in per_kernel if base == k or base.startswith(k + "2")), None)
-            if key is None or not per_kernel[key]["ms_per_launch"]:
-                continue
-            sec = per_kernel[key]["ms_per_launch"] * 1e-3
-            ent = {"counted_kernel": name, "ms_per_launch": per_kernel[key]["ms_per_launch"]}
-            if "bytes" in row:
-                gbs = row["bytes"] / sec / 1e9
-                ent.update(hbm_bytes=row["bytes"], hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
-                step_bytes += row["bytes"] * per_kernel[key]["launches"] / K
-            if "fp64_ops" in row:
-                tf = row["fp64_ops"] / sec / 1e12
-                ent.update(fp64_hw_ops=row["fp64_ops"], fp64_TFLOPs=tf, fp64_frac=tf / FP64_VECTOR_PEAK_TFLOPS)
-            by_kernel[key] = ent
+    by_kernel, step_bytes = kernel_rooflines(counters.read_table(summary), per_kernel, K)
     res["rooflines_by_kernel"] = by_kernel
     # the whole step (graph-replayed) against both rooflines: algorithmic FP64
     # operations of every phase (oracle counts per solution point) and the HBM

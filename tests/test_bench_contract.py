@@ -82,3 +82,27 @@ def test_copy_calibration_takes_the_last_large_copy(tmp_path):
     p.write_text(head + "\n".join(rows) + "\n")
     vals = counters._counter_means(str(p), "FETCH_SIZE")
     assert counters._copy_factor(vals, 256 * 1024 * 1024) == 2048.0
+
+
+def test_graph_step_bytes_weight_each_update_variant_by_its_launches():
+    """A captured K-step sequence launches k_pre and the plain update once and the
+    update that forms the next step's element data K-1 times; the per-kernel rows
+    pair the eager steps' kernels (plain update) with their live durations."""
+    table = {
+        "k_stages<MHD2D, 3, 8, Tableau<3> >": {"bytes": 1000.0, "mean_us": 1.0, "fp64_ops": 5e6},
+        "k_update<MHD2D, 3, 16, true>": {"bytes": 300.0, "mean_us": 1.0, "fp64_ops": 4e6},
+        "k_update<MHD2D, 3, 16, false>": {"bytes": 200.0, "mean_us": 1.0, "fp64_ops": 3e6},
+        "k_faces2<MHD2D, 3>": {"bytes": 400.0, "mean_us": 1.0},
+        "k_pre<MHD2D, 3, 16>": {"bytes": 100.0, "mean_us": 1.0},
+    }
+    per_kernel = {k: {"ms_per_launch": 1e-3, "launches": 10, "ms_total": 1e-2}
+                  for k in ("k_pre", "k_dt", "k_stages", "k_faces", "k_update")}
+    K = 10
+    by_kernel, step_bytes = bench.kernel_rooflines(table, per_kernel, K)
+    assert step_bytes == pytest.approx(1000 + 400 + 300 * (K - 1) / K + 200 / K + 100 / K)
+    assert by_kernel["k_update"]["counted_kernel"] == "k_update<MHD2D, 3, 16, false>"
+    assert by_kernel["k_update"]["hbm_bytes"] == 200.0
+    assert by_kernel["k_update"]["fp64_hw_ops"] == 3e6
+    assert by_kernel["k_faces"]["counted_kernel"] == "k_faces2<MHD2D, 3>"
+    assert set(by_kernel) == {"k_pre", "k_stages", "k_faces", "k_update"}
+    assert bench.kernel_rooflines({}, per_kernel, K) == (None, None)
