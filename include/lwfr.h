@@ -309,6 +309,9 @@ lwfr_status lwfr_timing_end(lwfr_ctx* ctx, double* ms, uint32_t* launches);
  * replacing any earlier one: step k reads d_u_a and writes d_u_b for even k,
  * the reverse for odd k, so the result is in d_u_a for even nsteps.
  * d_dt_ch_hist (nullable, device, nsteps x 2) receives each step's (dt, c_h).
+ * Inside the sequence each step's update kernel also forms the next step's
+ * element means, wave speeds and raw indicator, so that kernel of its own runs
+ * for the first step only; the results equal nsteps lwfr_step calls bit for bit.
  * The graph holds kernel launches only (no memory set or copy nodes).  Needs a
  * bound non-default stream (else LWFR_E_STATE).  Nothing runs until
  * lwfr_graph_launch, which enqueues the whole sequence on the bound stream;

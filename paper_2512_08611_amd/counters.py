@@ -13,8 +13,8 @@ per launch, (2 FMA + ADD + MUL) * 64 lanes, with the transcendental ones
 L2-to-fabric read requests by size (TCC_EA0_RDREQ_32B/_64B/_128B): their bytes
 need no calibration and check the scaled FETCH_SIZE kernel by kernel.
 
-The summary carries a digest of the kernel sources (csrc/*, include/lwfr.h);
-bench.py reports the measured traffic only while the digest matches the
+The summary carries a digest of the kernel sources (csrc/*, include/lwfr.h,
+comments removed); bench.py reports the measured traffic only while the digest matches the
 current sources, and null otherwise.
 
   python -m paper_2512_08611_amd.counters --stats KT_STATS.csv --fetch FETCH.csv \\
@@ -32,15 +32,42 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 
 
+def code_only(text):
+    """C/C++ source without its comments, trailing blanks and empty lines: what
+    the compiler sees, so that a comment edit leaves the digest unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":  # string or character literal, copied whole
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (line.rstrip() for line in "".join(out).splitlines())
+    return "\n".join(line for line in lines if line) + "\n"
+
+
 def sources_digest(root=ROOT):
-    """sha256 over the kernel sources and the C ABI header, in name order."""
+    """sha256 over the kernel sources and the C ABI header (code only, comments
+    removed), in name order."""
     files = sorted(glob.glob(os.path.join(root, "paper_2512_08611_amd", "csrc", "*")))
     files.append(os.path.join(root, "include", "lwfr.h"))
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()
 
 

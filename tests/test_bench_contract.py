@@ -106,3 +106,24 @@ def test_graph_step_bytes_weight_each_update_variant_by_its_launches():
     assert by_kernel["k_faces"]["counted_kernel"] == "k_faces2<MHD2D, 3>"
     assert set(by_kernel) == {"k_pre", "k_stages", "k_faces", "k_update"}
     assert bench.kernel_rooflines({}, per_kernel, K) == (None, None)
+
+
+def test_digest_ignores_comments_but_not_code(tmp_path):
+    """A comment edit in the kernel sources keeps the counter summaries valid; a code
+    edit, also inside a string literal that looks like a comment, does not."""
+    from paper_2512_08611_amd import counters
+
+    def tree(kernel, header):
+        root = tmp_path / str(len(list(tmp_path.iterdir())))
+        (root / "paper_2512_08611_amd" / "csrc").mkdir(parents=True)
+        (root / "include").mkdir()
+        (root / "paper_2512_08611_amd" / "csrc" / "k.hpp").write_text(kernel)
+        (root / "include" / "lwfr.h").write_text(header)
+        return counters.sources_digest(str(root))
+
+    base = tree('int f() { return 1; }  // one\nconst char* s = "a // b";\n', "/* api */\nint g();\n")
+    assert base == tree('// note\nint f() { return 1; }  /* one,\n two */\n\nconst char* s = "a // b";\n',
+                        "/* the api,\n reworded */\nint g();\n")
+    assert base != tree('int f() { return 2; }  // one\nconst char* s = "a // b";\n', "/* api */\nint g();\n")
+    assert base != tree('int f() { return 1; }  // one\nconst char* s = "a // c";\n', "/* api */\nint g();\n")
+    assert base != tree('int f() { return 1; }  // one\nconst char* s = "a // b";\n', "/* api */\nint g(int);\n")
