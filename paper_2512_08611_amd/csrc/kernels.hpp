@@ -2224,18 +2224,45 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   // high order update
   double uH[M];
   {
+    // the correction terms: F^± g'/dx after a folded volume residual, else D^± g'/dx
+    const double* cm = fold_correction<Ph>() ? kp.Fm : kp.Dm;
+    const double* cp = fold_correction<Ph>() ? kp.Fp : kp.Dp;
+    if constexpr (NFW <= P) {
+      // each face value of the element is loaded once, by the thread of its
+      // face point w (the layout of the flag loads above), and shared through
+      // the flux slots, which the subcell update only fills after the barrier
+      // that follows
+      const int w = p < NFW ? p : 0;
+      const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
+      const double* src = side ? cp : cm;
+      const size_t fo = (size_t)(side ? (d == 0 ? eL[0] : eL[DIM - 1]) : es) * NFP + q;
+      double fw[M];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
-      const size_t fR = (size_t)es * NFP + q, fL = (size_t)eL[d] * NFP + q;
-      // the correction terms: F^± g'/dx after a folded volume residual, else D^± g'/dx
-      const double* cm = fold_correction<Ph>() ? kp.Fm : kp.Dm;
-      const double* cp = fold_correction<Ph>() ? kp.Fp : kp.Dp;
+      for (int v = 0; v < M; ++v) fw[v] = src[((size_t)d * M + v) * nf + fo];
+      if (p < NFW) {
 #pragma unroll
-      for (int v = 0; v < M; ++v) {
-        const double fm = cm[((size_t)d * M + v) * nf + fR];
-        const double fp = cp[((size_t)d * M + v) * nf + fL];
-        R[v] += (fm * kp.gR[ii] + fp * kp.gL[ii]) * kp.inv_dx[d];
+        for (int v = 0; v < M; ++v) s_f[le][v][p] = fw[v];
+      }
+      elem_sync<ipow(N + 1, Ph::DIM)>();
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
+        const int wR = d * NFP + q, wL = (DIM + d) * NFP + q;
+#pragma unroll
+        for (int v = 0; v < M; ++v)
+          R[v] += (s_f[le][v][wR] * kp.gR[ii] + s_f[le][v][wL] * kp.gL[ii]) * kp.inv_dx[d];
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int q = d == 0 ? j : i, ii = d == 0 ? i : j;
+        const size_t fR = (size_t)es * NFP + q, fL = (size_t)eL[d] * NFP + q;
+#pragma unroll
+        for (int v = 0; v < M; ++v) {
+          const double fm = cm[((size_t)d * M + v) * nf + fR];
+          const double fp = cp[((size_t)d * M + v) * nf + fL];
+          R[v] += (fm * kp.gR[ii] + fp * kp.gL[ii]) * kp.inv_dx[d];
+        }
       }
     }
 #pragma unroll
