@@ -1049,7 +1049,7 @@ template <class Ph, int N, int NT>
 __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N, NT>& L, int le, int p, int d, int e,
                                              bool act, const double* Fa, const double* Ua, const double* Ra,
                                              const double* uo, double* __restrict__ rvol_g, double* d_alpha_out) {
-  constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NFP = n1;
+  constexpr int n1 = N + 1, M = Ph::M, P = n1 * n1, NFP = n1, NCD = Ph::NCD;
   constexpr int H0 = (M + 1) / 2, H1 = M - H0;
   constexpr int NFT = 4 * NFP;  // face points of the element
   static_assert(NFT <= 2 * P && NFT * M <= 2 * M * P, "one face point per lane; LDS room for the offsets");
@@ -1067,6 +1067,86 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
     }
   elem_sync<2 * (N + 1) * (N + 1)>();
 
+  if constexpr (NFT <= P) {
+    // face traces, one face point per point slot: both lanes of the slot work
+    // on it, each on its half of the variables of every trace, and swap halves
+    // where the correction offset C = F_tr + B_d(u^n_tr) U_tr needs the whole
+    // state.  Slots past the face points work on face point 0 and store nothing
+    // (the swaps take every lane of the wave)
+    const int f = p < NFT ? p : 0;
+    const bool own = act && p < NFT;
+    const int dd = f / (2 * NFP);
+    const int rem = f - dd * 2 * NFP;
+    const int side = rem / NFP;
+    const int qq = rem - side * NFP;
+    const double* V = side ? kp.VR : kp.VL;
+    const size_t nf = (size_t)kp.E * NFP;
+    const size_t fo = (size_t)e * NFP + qq;
+    const int nh = d ? H1 : H0;
+    auto trace = [&](int field, int v) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) {
+        const int nd = dd == 0 ? node_at<n1>(0, qq, r) : node_at<n1>(1, qq, r);
+        t += V[r] * s_buf[le][(field + v) * P + (nd)];
+      }
+      return t;
+    };
+    // the lane's half of each trace (the upper lane, with one variable fewer,
+    // repeats its first), all reads of a field issued together
+    double ah[H0], Uh[H0], Fh[H0];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) ah[k] = trace(3 * M, vo + (k < nh ? k : 0));
+#pragma unroll
+    for (int k = 0; k < H0; ++k) Uh[k] = trace(2 * M, vo + (k < nh ? k : 0));
+    // u^n and U from both halves: u^n whole, U in the entries the product takes
+    double a[M], U[M];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) {
+      double x = ah[k], y = ah[k];
+      cross_pair(x, y);
+      a[k] = x;
+      if (k < H1) a[H0 + k] = y;
+      U[k] = Uh[k];  // the lower lane's half; unused where the upper lane holds it
+    }
+#pragma unroll
+    for (int k = 0; k < H1; ++k) {
+      double x = Uh[k], y = Uh[k];
+      cross_pair(x, y);
+      U[H0 + k] = y;
+    }
+#pragma unroll
+    for (int k = 0; k < H0; ++k) Fh[k] = trace(dd * M, vo + (k < nh ? k : 0));
+    // B_dd(u^n_tr) U_tr from the columns of U that the product takes (indices
+    // known at compile time, one select each)
+    double wc[NCD], t[M];
+#pragma unroll
+    for (int c = 0; c < NCD; ++c) wc[c] = dd ? U[Ph::nc_comp(1, c)] : U[Ph::nc_comp(0, c)];
+    Ph::ncprod_rd(a, wc, dd, t, pp);
+    double Ch[H0];
+#pragma unroll
+    for (int k = 0; k < H0; ++k) Ch[k] = Fh[k] + (d ? (k < H1 ? t[H0 + k] : 0.0) : t[k]);
+    if (own) {
+      double* ut = kp.Utr + ((size_t)(dd * 2 + side) * M + vo) * nf + fo;
+      double* ft = kp.Ftr + ((size_t)(dd * 2 + side) * M + vo) * nf + fo;
+#pragma unroll
+      for (int k = 0; k < H1; ++k) {
+        ut[k * nf] = Uh[k];
+        ft[k * nf] = Fh[k];
+      }
+      if (nh > H1) {
+        ut[H1 * nf] = Uh[H1];
+        ft[H1 * nf] = Fh[H1];
+      }
+    }
+    elem_sync<2 * (N + 1) * (N + 1)>();  // every read of the F, U and u^n fields is done
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < H0; ++k)
+        if (k < nh) s_buf[le][f * M + vo + k] = Ch[k];
+    }
+    elem_sync<2 * (N + 1) * (N + 1)>();
+  } else {
   // face traces, one face point (all variables) per lane, and the correction
   // offsets C = F_tr + B_d(u^n_tr) U_tr of those face points
   const int tl = 2 * p + d;
@@ -1121,6 +1201,7 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
     for (int v = 0; v < M; ++v) s_buf[le][tl * M + v] = C[v];
   }
   elem_sync<2 * (N + 1) * (N + 1)>();
+  }
   if (act) {
     const int i = p % n1, j = p / n1;
 #pragma unroll
