@@ -1127,16 +1127,17 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
     for (int k = 0; k < H0; ++k) Ch[k] = Fh[k] + (d ? (k < H1 ? t[H0 + k] : 0.0) : t[k]);
     if (own) {
+      // F_d components that follow from U (TraceAlias) are not stored
       double* ut = kp.Utr + ((size_t)(dd * 2 + side) * M + vo) * nf + fo;
       double* ft = kp.Ftr + ((size_t)(dd * 2 + side) * M + vo) * nf + fo;
 #pragma unroll
       for (int k = 0; k < H1; ++k) {
         ut[k * nf] = Uh[k];
-        ft[k * nf] = Fh[k];
+        if (TraceAlias<Ph>::src(dd, vo + k) < 0) ft[k * nf] = Fh[k];
       }
       if (nh > H1) {
         ut[H1 * nf] = Uh[H1];
-        ft[H1 * nf] = Fh[H1];
+        if (TraceAlias<Ph>::src(dd, vo + H1) < 0) ft[H1 * nf] = Fh[H1];
       }
     }
     elem_sync<2 * (N + 1) * (N + 1)>();  // every read of the F, U and u^n fields is done
@@ -1191,7 +1192,7 @@ __device__ __forceinline__ void stages2_tail(const KParams& kp, Stages2Lds<Ph, N
 #pragma unroll
     for (int v = 0; v < M; ++v) {
       const double tf = trace(dd * M, v);
-      kp.Ftr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = tf;
+      if (TraceAlias<Ph>::src(dd, v) < 0) kp.Ftr[((size_t)(dd * 2 + side) * M + v) * nf + fo] = tf;
       C[v] = tf + C[v];
     }
   }
@@ -1853,9 +1854,12 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
     double a[M], U[M];
     line_trace<Ph, N, d>(kp, un_g, eo, q, ts, a, s, si);
 #pragma unroll
+    for (int v = 0; v < M; ++v) U[v] = kp.Utr[tr(v)];
+#pragma unroll
     for (int v = 0; v < M; ++v) {
-      U[v] = kp.Utr[tr(v)];
-      C[v] = kp.Ftr[tr(v)];
+      constexpr int dc = d;
+      const int w = TraceAlias<Ph>::src(dc, v);
+      C[v] = w < 0 ? kp.Ftr[tr(v)] : (TraceAlias<Ph>::ch_scaled(v) ? pp.ch * U[w < 0 ? 0 : w] : U[w < 0 ? 0 : w]);
     }
     // wave speed at the face value of u^n, or at the node if that is not
     // admissible (a branch that admissible data never take)
@@ -2162,10 +2166,12 @@ __device__ inline void bface_point(const KParams& kp, const double* __restrict__
   HalfSide<M> in, gh;
   const size_t fi = (size_t)ei * NFP + q;
 #pragma unroll
+  for (int v = 0; v < M; ++v) in.U[v] = kp.Utr[((size_t)(d * 2 + fs) * M + v) * nf + fi];
+#pragma unroll
   for (int v = 0; v < M; ++v) {
-    const size_t o = ((size_t)(d * 2 + fs) * M + v) * nf + fi;
-    in.U[v] = kp.Utr[o];
-    in.F[v] = kp.Ftr[o];
+    const int w = TraceAlias<Ph>::src(d, v);  // F_d components that follow from U
+    in.F[v] = w < 0 ? kp.Ftr[((size_t)(d * 2 + fs) * M + v) * nf + fi]
+                    : (TraceAlias<Ph>::ch_scaled(v) ? pp.ch * in.U[w < 0 ? 0 : w] : in.U[w < 0 ? 0 : w]);
   }
   line_trace<Ph, N, d>(kp, un_g, ei, q, fs, in.a, in.s, in.si);
   ghost_state<Ph, NFP>(kp, d, fs, j, in, gh);

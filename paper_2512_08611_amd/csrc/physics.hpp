@@ -518,4 +518,23 @@ struct JinXin1D {
   }
 };
 
+// Components of the time-averaged flux whose face traces follow from those of
+// the time-averaged solution.  Where f_d(u)[v] = c u[w] for a constant c, the
+// average F_d = sum_s b_s f_d(u^(s)) equals c U[w] with U = sum_s b_s u^(s), and
+// so do their face traces.  GLM-MHD: f_d[0] = u[1+d] (mass flux), f_d[5+d] =
+// c_h psi and f_d[8] = c_h B_d.  src(d, v): w, or -1 where F_d[v] is stored;
+// ch_scaled(v): the factor is c_h (else 1).
+template <class Ph>
+struct TraceAlias {
+  __host__ __device__ static constexpr int src(int, int) { return -1; }
+  __host__ __device__ static constexpr bool ch_scaled(int) { return false; }
+};
+template <>
+struct TraceAlias<MHD2D> {
+  __host__ __device__ static constexpr int src(int d, int v) {
+    return v == 0 ? 1 + d : v == 5 + d ? 8 : v == 8 ? 5 + d : -1;
+  }
+  __host__ __device__ static constexpr bool ch_scaled(int v) { return v != 0; }
+};
+
 }  // namespace lwfr
