@@ -214,7 +214,7 @@ struct PreLds {
   double s_q[EL][P + 1];   // indicator variable at the nodes, then the squared modes
   double s_t[EL][P + 1];   // 2-D: the first pass of the modal projection
   double s_ub[EL][Ph::M];
-  double s_lam[EL];
+  double s_lam[EL][2];     // (|v_d| + c_d)/dx_d of each direction
 };
 
 // The element data from the state x at the thread's node (x: every variable at
@@ -276,26 +276,23 @@ __device__ __forceinline__ void pre_from_state(const KParams& kp, PreLds<Ph, N, 
     s_q[le][p] = mode * mode;
   }
   elem_sync<ipow(N + 1, Ph::DIM)>();
-  if (p == 0) {
+  if (p < DIM) {
+    // the ideal speeds at the mean, lane p for direction p (one instruction
+    // stream for both directions)
     double lam = 0.0;
     if (act) {
       double ub[M];
 #pragma unroll
       for (int v = 0; v < M; ++v) ub[v] = s_ub[le][v];
       double av, c;
-      Ph::template speeds<0>(ub, av, c, pp);
-      lam = (av + c) * kp.inv_dx[0];
-      kp.speeds[(size_t)e * 2 * DIM + 0] = av;
-      kp.speeds[(size_t)e * 2 * DIM + 1] = c;
-      if constexpr (DIM == 2) {
-        Ph::template speeds<1>(ub, av, c, pp);
-        lam += (av + c) * kp.inv_dx[1];
-        kp.speeds[(size_t)e * 4 + 2] = av;
-        kp.speeds[(size_t)e * 4 + 3] = c;
-      }
+      if constexpr (DIM == 2) Ph::speeds_rd(ub, p, av, c, pp);
+      else Ph::template speeds<0>(ub, av, c, pp);
+      lam = (av + c) * (p ? kp.inv_dx[1] : kp.inv_dx[0]);
+      kp.speeds[(size_t)e * 2 * DIM + 2 * p] = av;
+      kp.speeds[(size_t)e * 2 * DIM + 2 * p + 1] = c;
     }
-    s_lam[le] = lam;
-  } else if (p == 1 % P && want_alpha && act) {
+    s_lam[le][p] = lam;
+  } else if (p == DIM && want_alpha && act) {
     // smoothness indicator, part 2: energy fractions of the highest modes,
     // logistic map, clip and cap (mode (l, k) of degree max(k, l) at slot k + n1 l)
     double tot = 0.0, c1 = 0.0, c2 = 0.0;
@@ -320,8 +317,9 @@ __device__ __forceinline__ void pre_from_state(const KParams& kp, PreLds<Ph, N, 
   }
   __syncthreads();  // the block-wide maximum reads every element slot
   if (tid == 0) {
-    double m = s_lam[0];
-    for (int l = 1; l < EPB; ++l) m = fmax(m, s_lam[l]);
+    // Lambda_e = sum over the directions, then the largest of the block
+    double m = 0.0;
+    for (int l = 0; l < EPB; ++l) m = fmax(m, DIM == 2 ? s_lam[l][0] + s_lam[l][1] : s_lam[l][0]);
     part_out[0] = m;
   }
 }

@@ -125,6 +125,10 @@ struct SW2D {
   __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
     av = fabs(u[1 + d] / u[0]); c = sqrt(pp.g * u[0]);
   }
+  // speeds<d> with the direction a run-time value (the same operations)
+  __device__ static void speeds_rd(const double* u, int d, double& av, double& c, const PhysParams& pp) {
+    av = fabs((d ? u[2] : u[1]) / u[0]); c = sqrt(pp.g * u[0]);
+  }
   template <int d>
   __device__ static void flux_vjp(const double* u, const double* fb, double* ub, const PhysParams& pp) {
     const double vel = u[1 + d] / u[0];
@@ -278,6 +282,18 @@ struct MHD2D {
   template <int d>
   __device__ static void speeds(const double* u, double& av, double& c, const PhysParams& pp) {
     av = fabs(u[1 + d] / u[0]); c = cfast<d>(u, pp);
+  }
+  // speeds<d> with the direction a run-time value (the same operations)
+  __device__ static void speeds_rd(const double* u, int d, double& av, double& c, const PhysParams& pp) {
+    const double ir = 1.0 / u[0];
+    const double p = pressure(u, pp);
+    const double a2 = pp.gamma * p * ir;
+    const double b2 = (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * ir;
+    const double Bd = d ? u[6] : u[5];
+    const double bd2 = Bd * Bd * ir;
+    const double s = a2 + b2;
+    av = fabs((d ? u[2] : u[1]) / u[0]);
+    c = sqrt(0.5 * (s + sqrt(s * s - 4.0 * a2 * bd2)));
   }
 
   // the components with x and y exchanged when d = 1 (an involution R, the
