@@ -290,7 +290,78 @@ def write_stats_md(path, title, stats_csv, commands, top=40, trace_csv=None):
         f.write("\n".join(lines))
 
 
+def pipes_summary(csvs, match="lwfr::", min_waves=10000):
+    """Per kernel and launch grid, the per-launch means of every counter in the
+    counter_collection.csv files of several rocprofv3 --pmc passes (each pass a
+    run of the same command), and the launch duration of those passes."""
+    agg, cnt, dur = {}, {}, {}
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            if match not in r["Kernel_Name"]:
+                continue
+            k = (_short(r["Kernel_Name"]), int(r["Grid_Size"]))
+            c = r["Counter_Name"]
+            agg.setdefault(k, {}).setdefault(c, 0.0)
+            agg[k][c] += float(r["Counter_Value"])
+            cnt.setdefault(k, {}).setdefault(c, 0)
+            cnt[k][c] += 1
+            dur.setdefault(k, {}).setdefault(c, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = {}
+    for k, d in agg.items():
+        mean = {c: v / cnt[k][c] for c, v in d.items()}
+        if mean.get("SQ_WAVES", 0.0) < min_waves:
+            continue
+        ds = [x for v in dur[k].values() for x in v]
+        g = dur[k].get("GRBM_GUI_ACTIVE", ds)
+        # the clock takes the durations of the pass that counted GRBM_GUI_ACTIVE
+        out[k] = dict(mean, duration_ns=sum(ds) / len(ds), grbm_duration_ns=sum(g) / len(g))
+    return out
+
+
+def write_pipes_md(path, title, csvs, commands, xcds=8, cus=256, lds_bytes_per_clk=128):
+    """VALU issue and LDS activity per kernel: instructions per wave, the clock from
+    GRBM_GUI_ACTIVE (cycles summed over the XCDs) over the launch, VALU busy as
+    4 cycles per wave instruction over the waves of one SIMD, LDS bytes per wave
+    from the LDS bandwidth counters (64-byte units), LDS busy from SQ_LDS_IDX_ACTIVE
+    over SQ_BUSY_CU_CYCLES and the bank-conflict share of it."""
+    s = pipes_summary(csvs)
+    lines = [f"# {title}", "", "Commands (run from the repository root R; one counter pass per run):", "", "```"]
+    lines += list(commands) + ["```", ""]
+    lines += ["| kernel | grid | waves | us | clock (GHz) | VALU / wave | VALU busy | LDS instr / wave | LDS KB / wave | "
+              "LDS busy | bank conflicts (of LDS busy) |", "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for (k, g), m in sorted(s.items(), key=lambda kv: -kv[1]["duration_ns"]):
+        w = m["SQ_WAVES"]
+        cyc = m.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        ghz = cyc / m["grbm_duration_ns"] if m["grbm_duration_ns"] else 0.0
+        valu = m.get("SQ_INSTS_VALU", 0.0) / w
+        valu_busy = 4 * m.get("SQ_INSTS_VALU", 0.0) / (4 * cus) / cyc if cyc else 0.0
+        lds_i = m.get("SQ_INSTS_LDS", 0.0) / w
+        lds_kb = 64 * (m.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0) + m.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0)) / w / 1024
+        busy_cu = m.get("SQ_BUSY_CU_CYCLES", 0.0)
+        lds_busy = m.get("SQ_LDS_IDX_ACTIVE", 0.0) / busy_cu if busy_cu else 0.0
+        conf = m.get("SQ_LDS_BANK_CONFLICT", 0.0) / m["SQ_LDS_IDX_ACTIVE"] if m.get("SQ_LDS_IDX_ACTIVE") else 0.0
+        lines.append(f"| `{k}` | {g} | {w:.0f} | {m['duration_ns'] / 1e3:.1f} | {ghz:.2f} | {valu:.0f} | "
+                     f"{100 * valu_busy:.0f} % | {lds_i:.0f} | {lds_kb:.1f} | {100 * lds_busy:.0f} % | {100 * conf:.0f} % |")
+    lines += ["", "Per-launch means of every counter:", ""]
+    names = sorted({c for m in s.values() for c in m if not c.endswith("duration_ns")})
+    lines += ["| kernel | grid | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for (k, g), m in sorted(s.items(), key=lambda kv: -kv[1]["duration_ns"]):
+        lines.append(f"| `{k}` | {g} | " + " | ".join(f"{m.get(c, float('nan')):.4g}" for c in names) + " |")
+    lines += ["", f"kernel sources sha256: {sources_digest()}", ""]
+    open(path, "w").write("\n".join(lines) + "\n")
+
+
 def main():
+    if len(os.sys.argv) > 1 and os.sys.argv[1] == "pipes":
+        pp = argparse.ArgumentParser(description="VALU and LDS activity per kernel from rocprofv3 --pmc passes")
+        pp.add_argument("cmd")
+        pp.add_argument("--pmc", action="append", required=True, help="counter_collection.csv of one pass")
+        pp.add_argument("--title", default="VALU and LDS activity")
+        pp.add_argument("--command", action="append", default=[])
+        pp.add_argument("--out", required=True)
+        a = pp.parse_args()
+        write_pipes_md(a.out, a.title, a.pmc, a.command)
+        return
     if len(os.sys.argv) > 1 and os.sys.argv[1] == "stats":
         sp = argparse.ArgumentParser(description="table of a rocprofv3 --stats kernel summary")
         sp.add_argument("cmd")
