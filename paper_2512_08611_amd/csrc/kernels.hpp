@@ -1297,9 +1297,18 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     }
     double f[M];
     Ph::flux_rd(u, d, f, pp);
+    // the flux components whose derivative is c_h times that of a
+    // non-conservative column are not exchanged: f_d[8] = c_h B_d, and (N <= 3)
+    // of the pair (PA, PA+1) = (5, 6) the lane's f_d[5+d] = c_h psi; slot PA
+    // holds the other member of the pair (f[6] for direction 0, f[5] for
+    // direction 1).  At N = 4 the pair stays as two fields: the compiler then
+    // overlaps more of the line reads and needs two waves' registers
+    constexpr bool PAIR = N <= 3;
+    constexpr int PA = PAIR ? Ph::flux_pair_nc_alias : -2;
 #pragma unroll
     for (int v = 0; v < M; ++v)
-      if (Ph::flux_nc_alias(v) < 0) s_buf[le][(d * M + v) * P + pw] = f[v];
+      if (Ph::flux_nc_alias(v) < 0 && v != PA && v != PA + 1) s_buf[le][(d * M + v) * P + pw] = f[v];
+    if constexpr (PAIR) s_buf[le][(d * M + PA) * P + pw] = d ? f[PA] : f[PA + 1];
 #pragma unroll
     for (int c = 0; c < NCD; ++c) {
       const double x0 = u[Ph::nc_comp(0, c)], x1 = u[Ph::nc_comp(1, c)];
@@ -1325,11 +1334,22 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
         wc[c] = sacc;
       }
       Ph::ncprod_rd(u, wc, d, nc, pp);
+      // D_d of the stored member of the pair, and D_d (c_h psi) = c_h D_d psi
+      double spair = 0.0, spsi = 0.0;
+      if constexpr (PAIR) {
+#pragma unroll
+        for (int r = 0; r < n1; ++r) spair += Drow[r] * s_buf[le][(d * M + PA) * P + (q * sq + r * sr)];
+        spsi = pp.ch * wc[1];
+      }
 #pragma unroll
       for (int v = 0; v < M; ++v) {
         double sacc = 0.0;
         if (Ph::flux_nc_alias(v) >= 0) {
           sacc = pp.ch * wc[Ph::flux_nc_alias(v)];  // D_d (c_h w) = c_h D_d w
+        } else if (v == PA) {
+          sacc = d ? spair : spsi;
+        } else if (v == PA + 1) {
+          sacc = d ? spsi : spair;
         } else {
 #pragma unroll
           for (int r = 0; r < n1; ++r) sacc += Drow[r] * s_buf[le][(d * M + v) * P + (q * sq + r * sr)];

@@ -168,6 +168,9 @@ struct MHD2D {
   // flux components equal to c_h times a non-conservative column in every
   // direction (f_d[8] = c_h B_d): index of that column, else -1
   __host__ __device__ static constexpr int flux_nc_alias(int v) { return v == 8 ? 0 : -1; }
+  // of the pair (5, 6), component 5+d of f_d is c_h times the psi column (f_d[5+d]
+  // = c_h psi); a lane of direction d that forms D_d f_d needs the other one only
+  static constexpr int flux_pair_nc_alias = 5;
   __device__ static double pressure(const double* u, const PhysParams& pp) {
     const double ir = 1.0 / u[0];
     const double mm = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
