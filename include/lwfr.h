@@ -362,7 +362,9 @@ lwfr_status lwfr_batch_step(lwfr_batch* batch, const double* d_u_in, double* d_u
 /* Launch shape of a phase: tile_threads 256 or 128 threads per tile of
  * elements (floor(tile_threads/P) elements each; faces: 256 face points),
  * grid workgroups walking the tiles (0: one workgroup per tile), xcd 1 to give
- * each XCD a contiguous range of tiles.  Results do not depend on the shape. */
+ * each XCD a contiguous range of tiles, xcd 2, 3 or 4 to deal the tiles out to
+ * the XCDs in chunks of 16, 64 or 256 consecutive tiles (0: no XCD grouping;
+ * other values are an error).  Results do not depend on the shape. */
 lwfr_status lwfr_batch_set_launch(lwfr_batch* batch, int32_t phase, int32_t tile_threads, int32_t grid, int32_t xcd);
 lwfr_status lwfr_batch_get_launch(const lwfr_batch* batch, int32_t phase, int32_t* tile_threads, int32_t* grid,
                                   int32_t* xcd);

@@ -8,11 +8,14 @@
 // device bodies as the single-problem kernels, selected by the problem's degree.
 //
 // Launches are persistent: a grid of G workgroups walks the tile table.  With
-// G a multiple of 8 and the XCD option set, workgroup b (dispatched to XCD
-// b mod 8) takes its tiles from the (b mod 8)-th contiguous eighth of the
-// table, so the tiles one XCD works on are neighbours in memory and their face
-// neighbours are mostly in the same L2.  The time step of each problem comes
-// from its own reduction (kb_dt, one workgroup per problem).
+// G a multiple of 8 and an XCD option set, workgroup b (dispatched to XCD
+// b mod 8) takes its tiles from the tiles of XCD b mod 8, so that the tiles one
+// XCD works on are neighbours in memory and their face neighbours are mostly
+// in the same L2: option 1 gives each XCD a contiguous eighth of the table;
+// options 2, 3 and 4 deal the table out in chunks of 16, 64 or 256 tiles, chunk
+// c to XCD c mod 8 (neighbours within a chunk, the problems of every degree
+// spread over all XCDs).  The time step of each problem comes from its own
+// reduction (kb_dt, one workgroup per problem).
 #pragma once
 #include "kernels.hpp"
 
@@ -24,22 +27,37 @@ struct BatchArgs {
   const int* tinst;       // [ntiles] problem of each tile
   const int* tblk;        // [ntiles] block index of the tile within its problem
   int ntiles;
-  int xcd;                // 1: XCD-contiguous tile ranges (needs gridDim.x % 8 == 0)
+  int xcd;                // 0: none; 1: XCD-contiguous eighths; 2..4: chunks of 16 << 2(xcd - 2) tiles per XCD
   double* part;           // [ntiles] per-tile maximum of Lambda_e (pre phase)
 };
 
-__device__ inline void tile_range(int ntiles, int xcd, int& t0, int& t1, int& step) {
+// The workgroup's walk over the tile table: for k = k0; k < k1; k += step, tile
+// tile_at(k) (-1: the walk is over)
+__device__ inline void tile_range(int ntiles, int xcd, int& k0, int& k1, int& step) {
   const int G = gridDim.x;
-  if (xcd && (G & 7) == 0) {
+  if (xcd == 1 && (G & 7) == 0) {
     const int x = blockIdx.x & 7, w = blockIdx.x >> 3, per = (ntiles + 7) >> 3;
-    t0 = x * per + w;
-    t1 = min(ntiles, (x + 1) * per);
+    k0 = x * per + w;
+    k1 = min(ntiles, (x + 1) * per);
+    step = G >> 3;
+  } else if (xcd >= 2 && (G & 7) == 0) {
+    k0 = blockIdx.x >> 3;
+    k1 = ntiles;  // the XCD's k-th tile lies at or past k
     step = G >> 3;
   } else {
-    t0 = blockIdx.x;
-    t1 = ntiles;
+    k0 = blockIdx.x;
+    k1 = ntiles;
     step = G;
   }
+}
+__device__ inline int tile_at(int k, int ntiles, int xcd) {
+  if (xcd >= 2 && (gridDim.x & 7) == 0) {
+    // the k-th tile of XCD x: chunk x + 8 (k / C), position k mod C in it
+    const int lc = 4 + 2 * (xcd - 2), C = 1 << lc, x = blockIdx.x & 7;
+    const int t = ((x + 8 * (k >> lc)) << lc) + (k & (C - 1));
+    return t < ntiles ? t : -1;
+  }
+  return k;
 }
 
 // elements per tile of the batched per-point phases with NT threads
@@ -66,9 +84,11 @@ template <class Ph, int NT>
 __global__ void __launch_bounds__(NT) kb_pre(const BatchArgs ba, const double* __restrict__ u) {
   constexpr int DIM = Ph::DIM;
   __shared__ LdsByDegree<PreLds, Ph, NT> L;
-  int t0, t1, step;
-  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
-  for (int t = t0; t < t1; t += step) {
+  int k0, k1, step;
+  tile_range(ba.ntiles, ba.xcd, k0, k1, step);
+  for (int k = k0; k < k1; k += step) {
+    const int t = tile_at(k, ba.ntiles, ba.xcd);
+    if (t < 0) break;
     const int inst = ba.tinst[t], blk = ba.tblk[t];
     const KParams& kp = ba.kps[inst];
     const double* un = u + ba.uoff[inst];
@@ -110,9 +130,11 @@ template <class Ph, int N, int NT>
 __global__ void __launch_bounds__(NT) kb_stages(const BatchArgs ba, const double* __restrict__ u_in,
                                                 double* __restrict__ u_out) {
   __shared__ StageLdsT<Ph, N, NT> L;
-  int t0, t1, step;
-  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
-  for (int t = t0; t < t1; t += step) {
+  int k0, k1, step;
+  tile_range(ba.ntiles, ba.xcd, k0, k1, step);
+  for (int k = k0; k < k1; k += step) {
+    const int t = tile_at(k, ba.ntiles, ba.xcd);
+    if (t < 0) break;
     const int inst = ba.tinst[t], blk = ba.tblk[t];
     const KParams& kp = ba.kps[inst];
     const double* un = u_in + ba.uoff[inst];
@@ -125,9 +147,11 @@ __global__ void __launch_bounds__(NT) kb_stages(const BatchArgs ba, const double
 // face phase: tiles of 128 face points in each direction
 template <class Ph>
 __global__ void __launch_bounds__(256) kb_faces(const BatchArgs ba, const double* __restrict__ u_in) {
-  int t0, t1, step;
-  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
-  for (int t = t0; t < t1; t += step) {
+  int k0, k1, step;
+  tile_range(ba.ntiles, ba.xcd, k0, k1, step);
+  for (int k = k0; k < k1; k += step) {
+    const int t = tile_at(k, ba.ntiles, ba.xcd);
+    if (t < 0) break;
     const int inst = ba.tinst[t];
     const KParams& kp = ba.kps[inst];
     const double* un = u_in + ba.uoff[inst];
@@ -151,9 +175,11 @@ __global__ void __launch_bounds__(NT) kb_update(const BatchArgs ba, const double
                                                 double* __restrict__ io) {
   constexpr int DIM = Ph::DIM;
   __shared__ LdsByDegree<UpdateLds, Ph, NT> L;
-  int t0, t1, step;
-  tile_range(ba.ntiles, ba.xcd, t0, t1, step);
-  for (int t = t0; t < t1; t += step) {
+  int k0, k1, step;
+  tile_range(ba.ntiles, ba.xcd, k0, k1, step);
+  for (int k = k0; k < k1; k += step) {
+    const int t = tile_at(k, ba.ntiles, ba.xcd);
+    if (t < 0) break;
     const int inst = ba.tinst[t], blk = ba.tblk[t];
     const KParams& kp = ba.kps[inst];
     const double* un = u_in + ba.uoff[inst];

@@ -1291,7 +1291,7 @@ lwfr_status lwfr_batch_set_launch(lwfr_batch* b, int32_t phase, int32_t tile_thr
   if (phase == LWFR_PHASE_FACES ? tile_threads != 256 : (tile_threads != 256 && tile_threads != 128))
     return fail(LWFR_E_INVALID_ARG, "tile_threads must be 256 or 128 (faces: 256)");
   if (grid < 0 || grid > (1 << 24)) return fail(LWFR_E_INVALID_ARG, "grid out of range");
-  if (xcd != 0 && xcd != 1) return fail(LWFR_E_INVALID_ARG, "xcd must be 0 or 1");
+  if (xcd < 0 || xcd > 4) return fail(LWFR_E_INVALID_ARG, "xcd must be 0..4");
   b->launch[phase] = BatchLaunch{tile_threads, grid, xcd};
   return LWFR_OK;
 }
@@ -1327,7 +1327,7 @@ lwfr_status lwfr_batch_autotune(lwfr_batch* b, const double* d_u_in, double* d_u
     for (int tt : {256, 128}) {
       if (ph == LWFR_PHASE_FACES && tt != 256) continue;
       for (int g : grids)
-        for (int x : {0, 1}) {
+        for (int x : {0, 1, 2, 3, 4}) {
           const BatchLaunch l{tt, g, x};
           float t = 0.0f;
           if (ph == LWFR_PHASE_UPDATE) st = time_phase(b, ph, l, d_u_in, d_u_out, reps, stages_first, e0, e1, t);

@@ -117,7 +117,7 @@ def test_batch_host_side():
     assert L.lwfr_batch_workspace_bytes(h, ctypes.byref(nb)) == lwfr.LWFR_OK
     single = sum(lwfr.lwfr_workspace_bytes(lwfr.lwfr_init(c)) for c in cfgs)
     assert nb.value > single
-    for phase, tt, grid, xcd in [(4, 256, 0, 1), (2, 128, 0, 1), (0, 64, 0, 1), (1, 256, -1, 1), (3, 256, 0, 2)]:
+    for phase, tt, grid, xcd in [(4, 256, 0, 1), (2, 128, 0, 1), (0, 64, 0, 1), (1, 256, -1, 1), (3, 256, 0, 5), (3, 256, 0, -1)]:
         assert L.lwfr_batch_set_launch(h, phase, tt, grid, xcd) == lwfr.LWFR_E_INVALID_ARG
     assert L.lwfr_batch_set_launch(h, 1, 128, 4096, 0) == lwfr.LWFR_OK
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -123,7 +123,7 @@ def test_launch_shapes_give_identical_results(stream):
     for phase in range(4):
         for tt in ((256,) if phase == lwfr.LWFR_PHASE_FACES else (256, 128)):
             for grid in (0, 1, 8, 24):
-                for xcd in (0, 1):
+                for xcd in (0, 1, 2, 4):
                     b.set_launch(phase, tt, grid, xcd)
                     out.fill_(0.0)
                     torch.cuda.synchronize()
