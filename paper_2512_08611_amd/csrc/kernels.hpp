@@ -1298,12 +1298,10 @@ __device__ __forceinline__ void stages2_body(const KParams& kp, Stages2Lds<Ph, N
     double f[M];
     Ph::flux_rd(u, d, f, pp);
     // the flux components whose derivative is c_h times that of a
-    // non-conservative column are not exchanged: f_d[8] = c_h B_d, and (N <= 3)
-    // of the pair (PA, PA+1) = (5, 6) the lane's f_d[5+d] = c_h psi; slot PA
-    // holds the other member of the pair (f[6] for direction 0, f[5] for
-    // direction 1).  At N = 4 the pair stays as two fields: the compiler then
-    // overlaps more of the line reads and needs two waves' registers
-    constexpr bool PAIR = N <= 3;
+    // non-conservative column are not exchanged: f_d[8] = c_h B_d, and of the
+    // pair (PA, PA+1) = (5, 6) the lane's f_d[5+d] = c_h psi; slot PA holds the
+    // other member of the pair (f[6] for direction 0, f[5] for direction 1)
+    constexpr bool PAIR = true;
     constexpr int PA = PAIR ? Ph::flux_pair_nc_alias : -2;
 #pragma unroll
     for (int v = 0; v < M; ++v)
@@ -1573,8 +1571,14 @@ constexpr int stage_threads() {
   return stage_lanes<Ph>() == 2 ? stages2_threads(EPB, ipow(N + 1, Ph::DIM)) : EPB * ipow(N + 1, Ph::DIM);
 }
 
+// at least three waves per SIMD for the two-lane stage kernels (at N = 4 the
+// compiler would otherwise keep more of a stage's line reads in flight and run
+// two); the one-lane kernels take no hint (under three they would spill)
+template <class Ph>
+constexpr int stage_waves_hint() { return stage_lanes<Ph>() == 2 ? 3 : STAGES_WAVES_PER_EU; }
+
 template <class Ph, int N, int EPB, class Tab = Tableau<N>>
-__global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((amdgpu_waves_per_eu(STAGES_WAVES_PER_EU)))
+__global__ void __launch_bounds__((stage_threads<Ph, N, EPB>())) __attribute__((amdgpu_waves_per_eu(stage_waves_hint<Ph>())))
     k_stages(const KParams kp, const double* __restrict__ un_g, double* __restrict__ rvol_g, double* d_alpha_out) {
   constexpr int NT = stage_threads<Ph, N, EPB>();
   __shared__ StageLdsT<Ph, N, NT> L;
