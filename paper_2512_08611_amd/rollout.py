@@ -2,7 +2,9 @@
 
 forward:  u_K = S_{K-1}( ... S_0(u_0)) with each step's dt from the CFL rule on
           the device; the state is kept every `every` steps (checkpoints) and
-          each step's (dt, c_h) is recorded.
+          each step's (dt, c_h) is recorded.  The steps of the last segment
+          write their tapes and keep their input states already (the backward
+          pass starts there, so they need no recomputation).
 backward: for each checkpoint segment, last first: recompute the segment's
           states from its checkpoint with the recorded dt, each step writing
           its tape (switches and face traces), then apply lwfr_adjoint_step
@@ -29,12 +31,21 @@ class LwfrRollout(torch.autograd.Function):
         ua = u0.detach().contiguous().clone()
         ub = torch.empty_like(ua)
         ckpts = []
+        last0 = (nsteps - 1) // every * every  # first step of the last segment
+        tapes = [stepper.new_tape() for _ in range(min(every, nsteps))]
+        last_states = []
         for n in range(nsteps):
             if n % every == 0:
                 ckpts.append(ua.clone())
-            stepper.step(ua, ub, 0.0, dtch[n])
+            if n >= last0:
+                # the same step (dt from the device), also writing its tape
+                last_states.append(ua.clone())
+                stepper.step_taped(ua, ub, 0.0, tapes[n - last0], dtch[n])
+            else:
+                stepper.step(ua, ub, 0.0, dtch[n])
             ua, ub = ub, ua
         ctx.stepper, ctx.nsteps, ctx.every = stepper, nsteps, every
+        ctx.tapes, ctx.last_states = tapes, last_states
         ctx.save_for_backward(dtch, *ckpts)
         return ua
 
@@ -45,17 +56,21 @@ class LwfrRollout(torch.autograd.Function):
         dts = dtch[:, 0].tolist()
         lam = grad.contiguous().clone()
         out = torch.empty_like(lam)
-        tapes = [st.new_tape() for _ in range(min(k, K))]
+        tapes = ctx.tapes
         for seg in reversed(range(len(ckpts))):
             n0, n1 = seg * k, min(seg * k + k, K)
-            states = [ckpts[seg]]
-            for n in range(n0, n1):
-                nxt = torch.empty_like(lam)
-                st.step_taped(states[-1], nxt, dts[n], tapes[n - n0])
-                states.append(nxt)
+            if seg == len(ckpts) - 1:
+                states = ctx.last_states  # taped in the forward pass
+            else:
+                states = [ckpts[seg]]
+                for n in range(n0, n1):
+                    nxt = torch.empty_like(lam)
+                    st.step_taped(states[-1], nxt, dts[n], tapes[n - n0])
+                    states.append(nxt)
             for n in reversed(range(n0, n1)):
                 st.adjoint_step(states[n - n0], dts[n], lam, out, tapes[n - n0])
                 lam, out = out, lam
+        ctx.tapes = ctx.last_states = None
         return lam, None, None, None
 
 

@@ -185,3 +185,28 @@ def test_rollout_gradient_per_value_vs_oracle_reverse_mode(kind):
     assert err.max() <= 1e-7
     if kind == "blocky":
         assert int((al > 0).sum()) > 0
+
+
+@pytest.mark.parametrize("kind", ["smooth", "blocky"])
+def test_rollout_gradient_independent_of_checkpoint_spacing(kind):
+    """The last segment's steps are taped in the forward pass, the others recomputed
+    from their checkpoints in the backward pass: the same states and tapes either way,
+    so the gradient of a 7-step rollout is the same, bit for bit, for checkpoints every
+    1, 2, 3, 5, 7 and 9 steps (segments of one step, uneven last segments, one segment
+    that the forward pass tapes whole)."""
+    n, steps = 16, 7
+    st, u0, target, wq = setup(n, steps=steps)
+    if kind == "blocky":
+        u0 = torch.tensor(W.mhd_blocky(np.array(st.xi), n, n, seed=2, nblocks=4), dtype=torch.float64, device=DEV)
+    grads, ends = [], []
+    for every in (1, 2, 3, 5, 7, 9):
+        x = u0.clone().requires_grad_(True)
+        y = rollout.rollout(x, st, steps, every)
+        loss_of(y, target, wq).backward()
+        torch.cuda.synchronize()
+        grads.append(x.grad.clone())
+        ends.append(y.detach().clone())
+    for g, e in zip(grads[1:], ends[1:]):
+        assert torch.equal(e, ends[0])
+        assert torch.equal(g, grads[0])
+    assert torch.isfinite(grads[0]).all() and grads[0].abs().max() > 0
