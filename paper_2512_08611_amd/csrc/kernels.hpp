@@ -231,8 +231,6 @@ __device__ __forceinline__ void pre_from_state(const KParams& kp, PreLds<Ph, N, 
   auto& s_lam = L.s_lam;
   const int tid = threadIdx.x;
   const int le = tid / P, p = tid - le * P;
-  const int e = blk * EPB + le;
-  const bool act = le < EPB && e < kp.E;
   const PhysParams pp = phys_params(kp, 0.0);
   const bool want_alpha = kp.blending >= 1 && kp.alpha_force < 0.0;
 #pragma unroll
@@ -275,49 +273,67 @@ __device__ __forceinline__ void pre_from_state(const KParams& kp, PreLds<Ph, N, 
     }
     s_q[le][p] = mode * mode;
   }
-  elem_sync<ipow(N + 1, Ph::DIM)>();
-  if (p < DIM) {
-    // the ideal speeds at the mean, lane p for direction p (one instruction
-    // stream for both directions)
+  // The wave speeds and the indicator energies are short serial tasks, one per
+  // (element, direction) and one per element.  They run on consecutive threads
+  // of the workgroup, each group from a wave boundary where it fits, so that
+  // one or two waves execute them instead of every wave with a few lanes on.
+  constexpr int NS = EPB * DIM;
+  constexpr int NS64 = (NS + 63) / 64 * 64;
+  constexpr int E0 = NS64 + EPB <= NT ? NS64 : NS;
+  __syncthreads();  // the tasks read the means and squared modes of every element
+  if (tid < NS) {
+    // the ideal speeds at the mean of element l in direction d
+    const int l = tid / DIM, d = tid - l * DIM;
+    const int el = blk * EPB + l;
     double lam = 0.0;
-    if (act) {
+    if (el < kp.E) {
       double ub[M];
 #pragma unroll
-      for (int v = 0; v < M; ++v) ub[v] = s_ub[le][v];
+      for (int v = 0; v < M; ++v) ub[v] = s_ub[l][v];
       double av, c;
-      if constexpr (DIM == 2) Ph::speeds_rd(ub, p, av, c, pp);
+      if constexpr (DIM == 2) Ph::speeds_rd(ub, d, av, c, pp);
       else Ph::template speeds<0>(ub, av, c, pp);
-      lam = (av + c) * (p ? kp.inv_dx[1] : kp.inv_dx[0]);
-      kp.speeds[(size_t)e * 2 * DIM + 2 * p] = av;
-      kp.speeds[(size_t)e * 2 * DIM + 2 * p + 1] = c;
+      lam = (av + c) * (d ? kp.inv_dx[1] : kp.inv_dx[0]);
+      kp.speeds[(size_t)el * 2 * DIM + 2 * d] = av;
+      kp.speeds[(size_t)el * 2 * DIM + 2 * d + 1] = c;
     }
-    s_lam[le][p] = lam;
-  } else if (p == DIM && want_alpha && act) {
-    // smoothness indicator, part 2: energy fractions of the highest modes,
-    // logistic map, clip and cap (mode (l, k) of degree max(k, l) at slot k + n1 l)
-    double tot = 0.0, c1 = 0.0, c2 = 0.0;
+    s_lam[l][d] = lam;
+  } else if (want_alpha && tid >= E0 && tid < E0 + EPB) {
+    // smoothness indicator, part 2, for element l: energy fractions of the
+    // highest modes, logistic map, clip and cap (mode (l, k) of degree
+    // max(k, l) at slot k + n1 l)
+    const int l = tid - E0;
+    const int el = blk * EPB + l;
+    if (el < kp.E) {
+      double tot = 0.0, c1 = 0.0, c2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-      const double m2 = s_q[le][r];
-      const int deg = DIM == 1 ? r : (r % n1 > r / n1 ? r % n1 : r / n1);
-      tot += m2;
-      if (deg <= N - 1) c1 += m2;
-      if (deg <= N - 2) c2 += m2;
+      for (int r = 0; r < P; ++r) {
+        const double m2 = s_q[l][r];
+        const int deg = DIM == 1 ? r : (r % n1 > r / n1 ? r % n1 : r / n1);
+        tot += m2;
+        if (deg <= N - 1) c1 += m2;
+        if (deg <= N - 2) c2 += m2;
+      }
+      double En = tot > 0.0 ? (tot - c1) / tot : 0.0;
+      if (N >= 2) {
+        const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
+        En = En >= e2 ? En : e2;
+      }
+      double a = 1.0 / (1.0 + exp(-(kp.ind_s / kp.ind_T) * (En - kp.ind_T)));
+      if (a < kp.alpha_min) a = 0.0;
+      if (a > 1.0 - kp.alpha_min) a = 1.0;
+      a = fmin(a, kp.alpha_max);
+      kp.alpha_raw[el] = a;
     }
-    double En = tot > 0.0 ? (tot - c1) / tot : 0.0;
-    if (N >= 2) {
-      const double e2 = c1 > 0.0 ? (c1 - c2) / c1 : 0.0;
-      En = En >= e2 ? En : e2;
-    }
-    double a = 1.0 / (1.0 + exp(-(kp.ind_s / kp.ind_T) * (En - kp.ind_T)));
-    if (a < kp.alpha_min) a = 0.0;
-    if (a > 1.0 - kp.alpha_min) a = 1.0;
-    a = fmin(a, kp.alpha_max);
-    kp.alpha_raw[e] = a;
   }
-  __syncthreads();  // the block-wide maximum reads every element slot
+  // Lambda_e = sum over the directions, then the largest of the block.  When
+  // the speed tasks are all in the first wave, that wave alone waits for them.
+  if constexpr (NS <= 64 && LWFR_WAVE_LOCAL_SYNC) {
+    if (tid < 64) elem_sync<64>();
+  } else {
+    __syncthreads();
+  }
   if (tid == 0) {
-    // Lambda_e = sum over the directions, then the largest of the block
     double m = 0.0;
     for (int l = 0; l < EPB; ++l) m = fmax(m, DIM == 2 ? s_lam[l][0] + s_lam[l][1] : s_lam[l][0]);
     part_out[0] = m;
