@@ -88,11 +88,17 @@ bool eq_info(int eq, EqInfo& info) {
 #ifndef LWFR_EPB_OVERRIDE
 #define LWFR_EPB_OVERRIDE 0
 #endif
-// Default: 256 threads per workgroup; 2-D degree 4 with 9 variables uses 5
-// elements (125 threads): measured fastest for the register-bound stage kernel.
+// Elements per workgroup of k_pre and the update.  Default: 256 threads per
+// workgroup.  2-D with 9 variables: degree 4 uses 5 elements (125 threads);
+// degree 3 uses 4 elements, one wave, whose barriers then hold no other wave
+// (measured fastest for the update that also forms the next step's element
+// data).
 template <int N>
 constexpr int epb_for(int DIM, int M) {
-  return LWFR_EPB_OVERRIDE > 0 ? LWFR_EPB_OVERRIDE : (DIM == 2 && N == 4 && M >= 9) ? 5 : 256 / ipow(N + 1, DIM);
+  return LWFR_EPB_OVERRIDE > 0                 ? LWFR_EPB_OVERRIDE
+         : (DIM == 2 && N == 4 && M >= 9) ? 5
+         : (DIM == 2 && N == 3 && M >= 9) ? 4
+                                          : 256 / ipow(N + 1, DIM);
 }
 // Elements per workgroup of the stage kernel (stage_lanes lanes per point):
 // about 256 threads.
@@ -725,7 +731,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->E = cfg->nelem[0] * ny;
   {
     const int epb = epb_runtime(c->N, c->DIM, c->M);
-    c->nblk_pre = (c->E + epb - 1) / epb;  // k_pre: 256/P elements per block
+    c->nblk_pre = (c->E + epb - 1) / epb;  // k_pre and the update: epb elements per block
     c->nblk_ch = (c->E + 255) / 256;       // k_ch: one thread per element
   }
   const bool gll = (cfg->flags & LWFR_CFG_GLL) != 0;
