@@ -111,6 +111,7 @@ __device__ __forceinline__ uint32_t elem_or(uint32_t x) {
 // everything a kernel needs besides the state pointers, passed by value
 struct KParams {
   int nx, ny, E, nblk_pre, nblk_ch;
+  int nblk_dt;                // blocks of k_dt's first level (GLM-MHD's c_h)
   int N;                      // degree (the batched kernels dispatch on it)
   double dx[2], inv_dx[2];
   double D[kMaxN1][kMaxN1], VL[kMaxN1], VR[kMaxN1], w[kMaxN1], gR[kMaxN1], gL[kMaxN1];
@@ -127,6 +128,7 @@ struct KParams {
   double* scal;               // [0] dt, [1] c_h, [2] Lambda
   double* part;               // per-block partial maxima / minima
   double* part2;
+  double* part3;              // [nblk_dt] k_dt's first-level maxima
   double* speeds;             // [E][2*DIM] (|v_d|, c_d)
   double* alpha_raw;          // [E]
   double* alpha;              // [E] smoothed alpha used by the step
@@ -390,10 +392,21 @@ __device__ inline double block_reduce(double x, double* s_w /* >= blockDim.x / 6
   return r;
 }
 
-// k_dt: one block of 1024 threads; Lambda and dt
+// k_dt: Lambda, the largest of the block maxima of k_pre (or of the update that
+// formed this step's element data), and dt.  Without GLM-MHD's c_h one block of
+// 1024 threads finishes both.  With it, k_dt is the first level of Lambda's
+// reduction: block g writes the largest of partials [1024 g, 1024 g + 1024)
+// to part3[g], and k_ch finishes Lambda and dt.  Max is exact, so both forms
+// give the same bits.
 __global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, int has_ch) {
   __shared__ double s_w[16];
   const int n = kp.nblk_pre, st = blockDim.x;
+  if (has_ch) {
+    const int i = blockIdx.x * st + threadIdx.x;
+    const double m = block_reduce<true>(i < n ? fmax(0.0, kp.part[i]) : 0.0, s_w);
+    if (threadIdx.x == 0) kp.part3[blockIdx.x] = m;
+    return;
+  }
   // 16 loads in flight per thread (up to 16384 partials in one round trip); an
   // index past the end reads the thread's first one again, which leaves the max
   double m = 0.0;
@@ -413,24 +426,31 @@ __global__ void __launch_bounds__(1024) k_dt(const KParams kp, double* d_dt_ch, 
     const double dt = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
     kp.scal[0] = dt;
     kp.scal[2] = lam;
-    if (!has_ch) {
-      const double ch = kp.ch_in >= 0.0 ? kp.ch_in : 0.0;
-      kp.scal[1] = ch;
-      if (d_dt_ch) { d_dt_ch[0] = dt; d_dt_ch[1] = ch; }
-    }
+    const double ch = kp.ch_in >= 0.0 ? kp.ch_in : 0.0;
+    kp.scal[1] = ch;
+    if (d_dt_ch) { d_dt_ch[0] = dt; d_dt_ch[1] = ch; }
   }
 }
 
 // k_ch: GLM speed candidate of each element: the largest c with
-// wx max(c_x, c) + wy max(c_y, c) <= Lambda - (wx |v_x| + wy |v_y|)
+// wx max(c_x, c) + wy max(c_y, c) <= Lambda - (wx |v_x| + wy |v_y|).
+// Every block first forms Lambda from k_dt's first-level maxima; block 0
+// stores Lambda and dt.
 __global__ void __launch_bounds__(256) k_ch(const KParams kp) {
-  __shared__ double s_w[4];
+  __shared__ double s_w[4], s_l[4];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < kp.nblk_dt; i += blockDim.x) m = fmax(m, kp.part3[i]);
+  const double lam = block_reduce<true>(m, s_l);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    kp.scal[0] = kp.dt_in > 0.0 ? kp.dt_in : kp.cs_cfl / lam;
+    kp.scal[2] = lam;
+  }
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   double ce = INFINITY;
   if (e < kp.E) {
     const double* sp = kp.speeds + (size_t)e * 4;
     const double wx = kp.inv_dx[0], wy = kp.inv_dx[1];
-    const double R = kp.scal[2] - (sp[0] * wx + sp[2] * wy);
+    const double R = lam - (sp[0] * wx + sp[2] * wy);
     double lo = sp[1], hi = sp[3], wlo = wx, whi = wy;
     if (lo > hi) { double t = lo; lo = hi; hi = t; t = wlo; wlo = whi; whi = t; }
     ce = (wlo + whi) * hi >= R ? (R - whi * hi) / wlo : R / (wlo + whi);

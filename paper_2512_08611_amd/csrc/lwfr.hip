@@ -39,12 +39,12 @@ struct Timing {
 struct lwfr_ctx {
   lwfr_config cfg;
   int M = 0, DIM = 0, K = 0, N = 0, n1 = 0, P = 0, NFP = 0, E = 0;
-  int nblk_pre = 0, nblk_ch = 0;
+  int nblk_pre = 0, nblk_ch = 0, nblk_dt = 0;
   RefData rd;
   double cfl = 0.0;
   KParams kp;
   // workspace carving (byte offsets)
-  size_t off_scal, off_part, off_part2, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr,
+  size_t off_scal, off_part, off_part2, off_part3, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr,
       off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, off_eflags, off_srows,
       ws_bytes;
   int nblk_stats = 0;
@@ -188,7 +188,7 @@ lwfr_status launch_step(lwfr_ctx* c, const KParams& kp, const double* u_in, doub
   const bool has_ch = std::is_same<Ph, MHD2D>::value && kp.ch_in < 0.0;
   if (!(chain & kChainFromPrev))
     LWFR_LAUNCH(KID_PRE, "k_pre", (k_pre<Ph, N, EPB>), dim3(c->nblk_pre), dim3(EPB * P), 0, s, kp, u_in);
-  LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(1), dim3(1024), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
+  LWFR_LAUNCH(KID_DT, "k_dt", k_dt, dim3(has_ch ? c->nblk_dt : 1), dim3(1024), 0, s, kp, d_dt_ch, has_ch ? 1 : 0);
   if (has_ch) {
     LWFR_LAUNCH(KID_CH, "k_ch", k_ch, dim3(c->nblk_ch), dim3(256), 0, s, kp);
     LWFR_LAUNCH(KID_CHFIN, "k_ch_fin", k_ch_fin, dim3(1), dim3(1024), 0, s, kp, d_dt_ch);
@@ -422,6 +422,7 @@ void carve_kp(const lwfr_ctx* c, char* b, KParams& kp) {
   kp.scal = reinterpret_cast<double*>(b + c->off_scal);
   kp.part = reinterpret_cast<double*>(b + c->off_part);
   kp.part2 = reinterpret_cast<double*>(b + c->off_part2);
+  kp.part3 = reinterpret_cast<double*>(b + c->off_part3);
   kp.speeds = reinterpret_cast<double*>(b + c->off_speeds);
   kp.alpha_raw = reinterpret_cast<double*>(b + c->off_araw);
   kp.alpha = reinterpret_cast<double*>(b + c->off_alpha);
@@ -733,6 +734,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     const int epb = epb_runtime(c->N, c->DIM, c->M);
     c->nblk_pre = (c->E + epb - 1) / epb;  // k_pre and the update: epb elements per block
     c->nblk_ch = (c->E + 255) / 256;       // k_ch: one thread per element
+    c->nblk_dt = (c->nblk_pre + 1023) / 1024;  // k_dt's first level: 1024 partials per block
   }
   const bool gll = (cfg->flags & LWFR_CFG_GLL) != 0;
   c->rd = make_refdata(c->N, gll);
@@ -744,6 +746,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   KParams& kp = c->kp;
   std::memset(&kp, 0, sizeof(kp));
   kp.nx = cfg->nelem[0]; kp.ny = ny; kp.E = c->E; kp.nblk_pre = c->nblk_pre; kp.nblk_ch = c->nblk_ch;
+  kp.nblk_dt = c->nblk_dt;
   kp.N = c->N;
   for (int d = 0; d < 2; ++d) {
     kp.dx[d] = d < info.DIM ? (cfg->hi[d] - cfg->lo[d]) / (d == 0 ? cfg->nelem[0] : ny) : 1.0;
@@ -779,6 +782,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   c->off_scal = take(8 * sizeof(double));
   c->off_part = take((size_t)c->nblk_pre * sizeof(double));
   c->off_part2 = take((size_t)c->nblk_ch * sizeof(double));
+  c->off_part3 = take((size_t)c->nblk_dt * sizeof(double));
   c->off_speeds = take((size_t)c->E * 2 * c->DIM * sizeof(double));
   c->off_araw = take((size_t)c->E * sizeof(double));
   c->off_alpha = take((size_t)c->E * sizeof(double));
