@@ -12,8 +12,9 @@ ctypes marshalling plus the Fourier (von Neumann) analysis in ``cfl.py``.
 
 Parity status of each part (what pins it) is listed in the design notes.  The
 smoothness indicator constants come from the cited work of Hennemann et al.,
-not from the paper: "parity unpinned" for the indicator beyond its special
-cases (constant state -> 0, pure highest mode -> alpha_max).
+not from the paper; the indicator is pinned by its special cases (constant
+state -> 0, pure highest mode -> alpha_max) and by closed-form energy
+fractions of nodal data built from chosen Legendre modes.
 """
 import ctypes
 import os

@@ -389,6 +389,55 @@ def test_indicator_special_cases():
     assert al[5] == 0.5 and al[4] == 0.25 and al[6] == 0.25 and al[1] == 0.25 and al[9] == 0.25
 
 
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_indicator_energy_fractions_closed_form(N):
+    """The raw indicator on nodal data built from chosen modal coefficients in the
+    orthonormal Legendre basis (§4, Hennemann et al.'s indicator): with q =
+    m00 + a B_hi + b B_lo, a mode of degree N and one of degree N-1, the energy
+    fractions are a^2/(m00^2+a^2+b^2) and b^2/(m00^2+b^2) exactly, and E is the
+    larger.  Targets around the threshold T(N) keep the logistic unclipped;
+    the degree of mode (j, k) is max(j, k), so every placement of the two
+    modes gives the same E."""
+    n1 = N + 1
+    re = oracle.refel(N)
+    L = re["Leg"]
+    T = 0.5 * 10.0 ** (-1.8 * (N + 1.0) ** 0.25)
+    s = np.log(9999.0)
+    m00 = 1.0 / L[0, 0]  # the constant mode that makes q's mean 1
+    # (E_hi, E_lo, mode of degree N, mode of degree N-1); E_* = 0 leaves the mode out
+    cases = [(T, 0.0, (N, 0), None), (0.8 * T, 0.0, (0, N), None), (1.3 * T, 0.0, (N, N), None),
+             (0.0, T, None, (N - 1, 0)), (0.0, 1.2 * T, None, (N - 1, N - 1)), (0.0, 0.7 * T, None, (0, N - 1)),
+             (0.9 * T, 1.1 * T, (N, 1), (1, N - 1)), (1.1 * T, 0.9 * T, (1, N), (N - 1, 0)),
+             (0.5, 0.0, (N, N - 1), None), (0.0, 0.0, None, None)]
+    n = 4
+    c = oracle.make_cfg(oracle.EQ_SW2D, N, n, n, blending=2, alpha_max=1.0, alpha_min=1e-3)
+    u = np.zeros((4, n * n, n1 * n1))
+    u[0] = 1.0
+    want = np.zeros(n * n)
+    for e, (Ehi, Elo, hi, lo) in enumerate(cases):
+        # b^2 = Elo m00^2/(1-Elo); then a^2 = Ehi (m00^2+b^2)/(1-Ehi)
+        b2 = Elo * m00 ** 2 / (1.0 - Elo)
+        a2 = Ehi * (m00 ** 2 + b2) / (1.0 - Ehi)
+        m = np.zeros((n1, n1))  # m[l, k]: L_k(x) L_l(y)
+        m[0, 0] = m00
+        if hi is not None:
+            m[hi[1], hi[0]] = np.sqrt(a2)
+        if lo is not None:
+            m[lo[1], lo[0]] = -np.sqrt(b2)
+        q = np.einsum("lk,li,kj->ij", m, L, L)  # q[i][j] at node (x_j, y_i)
+        u[0, e] = q.reshape(-1)
+        E = max(Ehi, Elo)
+        a = 1.0 / (1.0 + np.exp(-(s / T) * (E - T)))
+        want[e] = 0.0 if a < 1e-3 else (1.0 if a > 1.0 - 1e-3 else a)
+    araw, _, _ = oracle.alpha(c, u)
+    # the unclipped cases span the logistic's active band
+    assert 0.05 < want[1] < 0.5 < want[2] < 0.95 and want[0] == pytest.approx(0.5)
+    assert want[8] == 1.0 and want[9] == 0.0
+    np.testing.assert_allclose(araw[:len(cases)], want[:len(cases)], rtol=1e-9, atol=1e-12)
+    # elements with constant data: E = 0, below alpha_min after the logistic
+    assert np.all(araw[len(cases):] == 0.0)
+
 # ----------------------------------------------------------- jvp / FD ----
 @pytest.mark.parametrize("eq,N,blend", [(oracle.EQ_MHD2D, 3, 0), (oracle.EQ_MHD2D, 2, 2), (oracle.EQ_SW1D, 4, 2)])
 def test_jvp_matches_central_difference(eq, N, blend):
