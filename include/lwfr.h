@@ -239,8 +239,8 @@ lwfr_status lwfr_step(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, doub
  * All calls on one GPU share its array: calls that overlap in time on one GPU
  * (concurrent streams or threads) race and give wrong results; calls in one
  * stream order are safe.  Errors: LWFR_E_WORKSPACE when the step needs more
- * than LWFR_STATIC_SCRATCH_BYTES (GLM-MHD at N = 3: up to about 296,000
- * solution points, e.g. 136 x 136 elements), and those of lwfr_step. */
+ * than LWFR_STATIC_SCRATCH_BYTES (GLM-MHD at N = 3: up to about 300,000
+ * solution points, e.g. 137 x 137 elements), and those of lwfr_step. */
 #define LWFR_STATIC_SCRATCH_BYTES (64u << 20)
 lwfr_status lwfr_step_noalloc(lwfr_ctx* ctx, const double* d_u_in, double* d_u_out, double dt, double* d_dt_ch,
                               uint32_t* d_flags, void* hip_stream);

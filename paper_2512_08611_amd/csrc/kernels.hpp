@@ -60,6 +60,12 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+// Algorithm 1's outcome at a face point as the update's element flags need it:
+// bit 0 when the product of its thetas is below 1, bit 1 when the guard held.
+__device__ __forceinline__ uint8_t face_flag(double Theta, bool guard) {
+  return (uint8_t)((Theta < 1.0 ? 1u : 0u) | (guard ? 2u : 0u));
+}
+
 // Synchronisation of the lanes that share one element's LDS slot.  When no
 // element straddles two waves (LANES lanes per element dividing the 64 of a
 // wave), those lanes are one wave: a wave-level fence orders their LDS
@@ -138,8 +144,8 @@ struct KParams {
   double* Fp;                 // [d][M][E*nfp] F^+
   double* Dm;                 // [d][M][E*nfp] F^- - F_tr^- - B(u^{n,-}) U^- (systems that do not fold it)
   double* Dp;                 // [d][M][E*nfp] F^+ - F_tr^+ - B(u^{n,+}) U^+
-  double* theta_face;         // [d][E*nfp] product of Algorithm 1 thetas
-  uint32_t* guard_face;       // [d][E*nfp]
+  double* theta_face;         // [d][E*nfp] product of Algorithm 1 thetas (a tape's; null: not kept)
+  uint8_t* fflag_face;        // [d][E*nfp] bit 0: that product below 1, bit 1: the guard
   uint32_t* flag_or;          // [1] OR of every element flag since the last query
   double* theta_elem;         // [E] product of Algorithm 2 thetas
   uint32_t* eflags;           // [E] element flags of the last step with statistics
@@ -1856,8 +1862,8 @@ __device__ inline void face_point(const KParams& kp, const double* __restrict__ 
       kp.Dp[o] = Fp[v] - Cp[v];
     }
   }
-  kp.theta_face[fo] = Theta;
-  kp.guard_face[fo] = guard ? 1u : 0u;
+  if (kp.theta_face) kp.theta_face[fo] = Theta;
+  kp.fflag_face[fo] = face_flag(Theta, guard);
 }
 
 template <class Ph, int N>
@@ -2020,8 +2026,8 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
 #pragma unroll
   for (int v = 0; v < M; ++v) Fo[((size_t)d * M + v) * nf + fiL] = F[v];
   if (!side) {
-    kp.theta_face[(size_t)d * nf + fiL] = Theta;
-    kp.guard_face[(size_t)d * nf + fiL] = guard ? 1u : 0u;
+    if (kp.theta_face) kp.theta_face[(size_t)d * nf + fiL] = Theta;
+    kp.fflag_face[(size_t)d * nf + fiL] = face_flag(Theta, guard);
   }
 }
 
@@ -2249,8 +2255,8 @@ __device__ inline void bface_point(const KParams& kp, const double* __restrict__
       kp.Fm[o] = Fm[v];
       if constexpr (!fold_correction<Ph>()) kp.Dm[o] = Fm[v] - (in.F[v] + C[v]);
     }
-    kp.theta_face[(size_t)d * nf + slot] = Theta;
-    kp.guard_face[(size_t)d * nf + slot] = guard ? 1u : 0u;
+    if (kp.theta_face) kp.theta_face[(size_t)d * nf + slot] = Theta;
+    kp.fflag_face[(size_t)d * nf + slot] = face_flag(Theta, guard);
   } else {
 #pragma unroll
     for (int v = 0; v < M; ++v) {
@@ -2355,16 +2361,14 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
   // its left faces, whose slot is the left neighbour's, or a boundary half face
   // (a boundary half face's own values are read at the end, by its threads only)
   constexpr int NFW = 2 * DIM * NFP, NW = (NFW + P - 1) / P;
-  double thw[NW];
-  uint32_t guw[NW];
+  uint32_t ffw[NW];
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
     const int w = p + k * P < NFW ? p + k * P : 0;  // threads past the face points read point 0
     const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
     const int ef = side ? (d == 0 ? eL[0] : eL[DIM - 1]) : es;
     const size_t fo = (size_t)d * nf + (size_t)ef * NFP + q;
-    thw[k] = kp.blending == 2 ? kp.theta_face[fo] : 1.0;
-    guw[k] = kp.blending == 2 ? kp.guard_face[fo] : 0u;
+    ffw[k] = kp.blending == 2 ? kp.fflag_face[fo] : 0u;
   }
   // high order update
   double uH[M];
@@ -2571,10 +2575,9 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
     const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
     if (kp.blending == 2 && side && on_boundary(kp, es, d, 0)) {  // a boundary half face
       const size_t bl = (d == 0 ? 0 : (size_t)kp.ny * NFP) + (size_t)(d == 0 ? es / kp.nx : es % kp.nx) * NFP + q;
-      thw[k] = kp.theta_left[bl];
-      guw[k] = kp.guard_left[bl];
+      ffw[k] = face_flag(kp.theta_left[bl], kp.guard_left[bl] != 0u);
     }
-    fl |= (thw[k] < 1.0 ? 4u : 0u) | (guw[k] ? 16u : 0u);
+    fl |= (ffw[k] & 1u ? 4u : 0u) | (ffw[k] & 2u ? 16u : 0u);
   }
   uint32_t f = 0;
   if constexpr (elem_lane_exchange<P>()) {

@@ -45,7 +45,7 @@ struct lwfr_ctx {
   KParams kp;
   // workspace carving (byte offsets)
   size_t off_scal, off_part, off_part2, off_part3, off_speeds, off_araw, off_alpha, off_thel, off_Ftr, off_Utr,
-      off_Fm, off_Fp, off_Dm, off_Dp, off_thf, off_guard, off_thl, off_gul, off_flag, off_eflags, off_srows,
+      off_Fm, off_Fp, off_Dm, off_Dp, off_ffl, off_thf, off_thl, off_gul, off_flag, off_eflags, off_srows,
       ws_bytes;
   int nblk_stats = 0;
   size_t fwd_bytes = 0;
@@ -433,8 +433,8 @@ void carve_kp(const lwfr_ctx* c, char* b, KParams& kp) {
   kp.Fp = reinterpret_cast<double*>(b + c->off_Fp);
   kp.Dm = c->off_Dm ? reinterpret_cast<double*>(b + c->off_Dm) : nullptr;
   kp.Dp = c->off_Dp ? reinterpret_cast<double*>(b + c->off_Dp) : nullptr;
-  kp.theta_face = reinterpret_cast<double*>(b + c->off_thf);
-  kp.guard_face = reinterpret_cast<uint32_t*>(b + c->off_guard);
+  kp.theta_face = nullptr;  // kept only in a tape
+  kp.fflag_face = reinterpret_cast<uint8_t*>(b + c->off_ffl);
   kp.theta_left = reinterpret_cast<double*>(b + c->off_thl);
   kp.guard_left = reinterpret_cast<uint32_t*>(b + c->off_gul);
   kp.flag_or = reinterpret_cast<uint32_t*>(b + c->off_flag);
@@ -797,8 +797,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   const bool fold = c->DIM == 2 && c->M >= 8;
   c->off_Dm = fold ? 0 : take(nfpt * c->M * sizeof(double));
   c->off_Dp = fold ? 0 : take(nfpt * c->M * sizeof(double));
-  c->off_thf = take(nfpt * sizeof(double));
-  c->off_guard = take(nfpt * sizeof(uint32_t));
+  c->off_ffl = take(nfpt * sizeof(uint8_t));
   {
     const size_t nbl = ((size_t)ny + (info.DIM == 2 ? cfg->nelem[0] : 0)) * c->NFP;  // left boundary face points
     c->off_thl = take(nbl * sizeof(double));
@@ -812,6 +811,7 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
   if (c->adjoint) {
     const size_t nst = (size_t)c->M * c->E * c->P * sizeof(double);
     c->off_uscr = take(nst);
+    c->off_thf = take(nfpt * sizeof(double));  // Algorithm 1 thetas of the recomputed step (no tape)
     c->off_grvol = take(nst);
     c->off_gun = take(nst);
     c->off_gFm = take(nfpt * c->M * sizeof(double));
@@ -1039,6 +1039,7 @@ lwfr_status lwfr_adjoint_step(lwfr_ctx* c, const double* d_u_n, double dt, const
     kp = with_tape(c, kp, const_cast<void*>(d_tape));
   } else {
     double* uscr = reinterpret_cast<double*>(static_cast<char*>(c->ws) + c->off_uscr);
+    kp.theta_face = reinterpret_cast<double*>(static_cast<char*>(c->ws) + c->off_thf);
     lwfr_status st = dispatch_step(c, kp, d_u_n, uscr, nullptr, nullptr, nullptr);
     if (st != LWFR_OK) return st;
   }

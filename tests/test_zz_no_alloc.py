@@ -57,14 +57,14 @@ def _ws_bytes(n):
 
 
 def test_noalloc_largest_problem_fits_and_the_next_is_refused():
-    """GLM-MHD N=3: 136 x 136 elements are the largest square mesh whose step
-    workspace fits the scratch; it steps equal to lwfr_step, and 137 x 137 is refused."""
-    assert _ws_bytes(136) <= SCRATCH_BYTES < _ws_bytes(137)
-    st, u = _case(3, 136, 136, 2)
+    """GLM-MHD N=3: 137 x 137 elements are the largest square mesh whose step
+    workspace fits the scratch; it steps equal to lwfr_step, and 138 x 138 is refused."""
+    assert _ws_bytes(137) <= SCRATCH_BYTES < _ws_bytes(138)
+    st, u = _case(3, 137, 137, 2)
     _compare(st, u)
-    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (137, 137), blending=2)
+    cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (138, 138), blending=2)
     ctx = lwfr.lwfr_init(cfg)
-    u = torch.zeros((9, 137 * 137, 16), dtype=torch.float64, device=DEV)
+    u = torch.zeros((9, 138 * 138, 16), dtype=torch.float64, device=DEV)
     with pytest.raises(lwfr.LwfrError) as ei:
         lwfr.lwfr_step_noalloc(ctx, u, torch.empty_like(u))
     assert ei.value.status == lwfr.LWFR_E_WORKSPACE and "static scratch" in str(ei.value)
