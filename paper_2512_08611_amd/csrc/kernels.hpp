@@ -125,6 +125,10 @@ struct KParams {
   double inv_wdx[2][kMaxN1];  // 1/(w_p dx_d)
   double g, gamma;
   int blending;
+  // 1: F^+[0] is not stored and is read from F^-[0] of the same face (GLM-MHD
+  // with every side periodic: the non-conservative product has no mass
+  // component, so the two sides' mass fluxes are the same F^num[0])
+  int fp0_alias;
   double alpha_max, alpha_min, alpha_force;
   double ind_T, ind_s;        // indicator threshold T(N) and logistic sharpness s
   double cs_cfl;              // C_s * CFL(N)
@@ -2024,7 +2028,8 @@ __device__ inline void face_point2(const KParams& kp, const double* __restrict__
   const size_t fiL = (size_t)e * NFP + q;
   double* Fo = side ? kp.Fp : kp.Fm;
 #pragma unroll
-  for (int v = 0; v < M; ++v) Fo[((size_t)d * M + v) * nf + fiL] = F[v];
+  for (int v = 0; v < M; ++v)
+    if (v > 0 || !side || !kp.fp0_alias) Fo[((size_t)d * M + v) * nf + fiL] = F[v];
   if (!side) {
     if (kp.theta_face) kp.theta_face[(size_t)d * nf + fiL] = Theta;
     kp.fflag_face[(size_t)d * nf + fiL] = face_flag(Theta, guard);
@@ -2384,10 +2389,11 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
       const int w = p < NFW ? p : 0;
       const int q = w % NFP, d = (w / NFP) % DIM, side = w / (DIM * NFP);
       const double* src = side ? cp : cm;
+      const double* src0 = side && !kp.fp0_alias ? cp : cm;
       const size_t fo = (size_t)(side ? (d == 0 ? eL[0] : eL[DIM - 1]) : es) * NFP + q;
       double fw[M];
 #pragma unroll
-      for (int v = 0; v < M; ++v) fw[v] = src[((size_t)d * M + v) * nf + fo];
+      for (int v = 0; v < M; ++v) fw[v] = (v == 0 ? src0 : src)[((size_t)d * M + v) * nf + fo];
       if (p < NFW) {
 #pragma unroll
         for (int v = 0; v < M; ++v) s_f[le][v][p] = fw[v];
@@ -2409,7 +2415,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
 #pragma unroll
         for (int v = 0; v < M; ++v) {
           const double fm = cm[((size_t)d * M + v) * nf + fR];
-          const double fp = cp[((size_t)d * M + v) * nf + fL];
+          const double fp = (v == 0 && kp.fp0_alias ? cm : cp)[((size_t)d * M + v) * nf + fL];
           R[v] += (fm * kp.gR[ii] + fp * kp.gL[ii]) * kp.inv_dx[d];
         }
       }
@@ -2473,7 +2479,7 @@ __device__ __forceinline__ void update_body(const KParams& kp, UpdateLds<Ph, N, 
       } else {
         const size_t fL = (size_t)eL[d] * NFP + q;
 #pragma unroll
-        for (int v = 0; v < M; ++v) left[v] = kp.Fp[((size_t)d * M + v) * nf + fL];
+        for (int v = 0; v < M; ++v) left[v] = (v == 0 && kp.fp0_alias ? kp.Fm : kp.Fp)[((size_t)d * M + v) * nf + fL];
       }
 #pragma unroll
       for (int v = 0; v < M; ++v) RL[v] += (right[v] - left[v]) * kp.inv_wdx[d][ii];

@@ -763,6 +763,13 @@ lwfr_status lwfr_init(const lwfr_config* cfg, lwfr_ctx** out) {
     kp.ra = cfg->source[0]; kp.reps = cfg->source[1]; kp.rl = cfg->source[2]; kp.rq = cfg->source[3];
   }
   kp.blending = cfg->blending;
+  // F^+[0] from F^-[0]: only the two-lane GLM-MHD face kernel leaves it out, and
+  // only where every face slot holds one face (all sides periodic)
+  kp.fp0_alias = cfg->equation == LWFR_EQ_GLMMHD2D && cfg->bc[0] == LWFR_BC_PERIODIC &&
+                         cfg->bc[1] == LWFR_BC_PERIODIC && cfg->bc[2] == LWFR_BC_PERIODIC &&
+                         cfg->bc[3] == LWFR_BC_PERIODIC
+                     ? 1
+                     : 0;
   kp.alpha_max = cfg->alpha_max; kp.alpha_min = cfg->alpha_min; kp.alpha_force = cfg->alpha_force;
   kp.ind_T = 0.5 * std::pow(10.0, -1.8 * std::pow(c->N + 1.0, 0.25));
   kp.ind_s = std::log(9999.0);
