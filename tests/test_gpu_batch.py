@@ -192,13 +192,17 @@ def test_single_problem_graph_matches_eager(stream):
         assert torch.equal(hist, dtch), rep
 
 
-@pytest.mark.parametrize("case", ["mhd4", "sw1d", "jinxin", "sw2d_walls"])
+@pytest.mark.parametrize("case", ["mhd4", "mhd3_outflow", "sw1d", "jinxin", "sw2d_walls"])
 def test_single_problem_graph_matches_eager_more(stream, case):
     """Captured sequences form each step's element data in the previous step's update
     (no k_pre after the first step): bit-identical to eager steps, which run k_pre."""
     if case == "mhd4":
         cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 4, (9, 7), blending=2)
         gen = lambda xi: W.mhd_blocky(xi, 9, 7, 5, nblocks=4)
+    elif case == "mhd3_outflow":
+        # outflow sides: every face's F^+ is stored (a boundary slot holds two faces)
+        cfg = lwfr.make_config(lwfr.LWFR_EQ_GLMMHD2D, 3, (7, 6), blending=2, bc=(1, 1, 1, 1))
+        gen = lambda xi: W.mhd_blocky(xi, 7, 6, 6, nblocks=3)
     elif case == "sw1d":
         cfg = lwfr.make_config(lwfr.LWFR_EQ_SW1D, 3, 37, blending=2)
         gen = lambda xi: W.sw1d_wave(xi, 37, 2)
